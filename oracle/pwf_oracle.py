@@ -1,0 +1,327 @@
+"""Plain FP64 oracle of preconditioned Wirtinger flow (PWF).
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the HIP path.
+
+The oracle follows the paper "Speckle-based X-ray microtomography via
+preconditioned Wirtinger flow" (Lee, Hugonnet, Lim, Park; arXiv 2503.20146):
+Algorithm S1 (the PWF loop) and Algorithm S2 (PhysicalModel,
+WirtingerDerivative, Preconditioner, Regularizer, FreePropagation, Filter),
+with the windows of Eq. 5 (IOTF), Eq. 11 (inverse-Laplacian preconditioner),
+Eqs. 14-15 (STF and regularisation window) and the loss of Eq. 2.  Every
+operation is complex128/float64 and uses ``scipy.fft`` as the Fourier
+transform primitive; nothing is blocked, fused or reordered.
+
+Notation.  ``psi = log x = -mu + i phi`` is the complex phase (Results,
+"Preconditioned Wirtinger flow").  Algorithm S1 reuses the letters phi and mu
+for the Nesterov gradient-step iterate and the momentum scalar; here they are
+``z`` and ``tau`` so that phi and mu keep their physical meaning.
+
+Readings where the paper is silent or ambiguous (each one is listed in the
+design notes of the repository):
+
+* Propagator: angular spectrum with the constant carrier ``exp(i 2 pi L /
+  lambda)`` dropped (a global phase that cancels in ``|v|^2`` and in the
+  gradient), in the cancellation-free form
+  ``theta = -2 pi L lambda rho^2 / (1 + sqrt(1 - lambda^2 rho^2))``; bins with
+  ``lambda^2 rho^2 >= 1`` are evanescent and set to 0.
+* Preconditioner: Eqs. 9-11 derive the inverse Laplacian and then drop its
+  constants (the 4 pi^2 of the Laplacian's Fourier symbol, its sign and a
+  factor 2).  Here ``P^-1_k = s_P / (u^2 + v^2)`` with frequencies in cycles
+  per pixel and ``s_P = 1 / (4 pi^2)``, i.e. the magnitude of the inverse
+  Laplacian symbol on the pixel grid; its DC value is 0 (text after Eq. 11).
+* Step size: the paper fixes ``eta = 1`` for its beamline normalisation.  With
+  unit flat field, ``max|t|^2 ~ 1`` and the geometry of the synthetic
+  workloads, the unpreconditioned absorption channel of the Gauss-Newton
+  operator has ``eta * lambda_max ~ 1.7 > 4/3`` at ``eta = 1``, beyond the
+  stability limit of Nesterov momentum, so the default is ``eta = 1/2``: the
+  largest of {1, 1/2, 1/4, 1/8} for which the 128^2 workload's loss falls
+  monotonically over 50 iterations.
+* Filters of real images by real even windows keep the real part
+  (IOTF, preconditioner): the imaginary residue is rounding only.
+* The IPSF is Gaussian with standard deviation ``sigma`` px at the detector,
+  i.e. ``x_coh = 2 sqrt(pi) sigma p`` in Eqs. 4-5; the IOTF is applied as a
+  Fourier window (Results: "equivalently ... as a window function").
+* The loss is the plain sum of Eq. 2; the loss history holds the loss at the
+  iterate that enters each iteration.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import scipy.fft as _sfft
+
+PAPER_ALPHA = complex(0.1, 0.01)   # regularisation parameter (Results, PWF subsection)
+PAPER_GAMMA = 1.0                  # oversampling ratio (Results, PWF subsection)
+PAPER_ETA = 1.0                    # step size (Results, PWF subsection)
+PAPER_STOP_CORR = 10.0 ** (-0.00001)  # stopping correlation (Methods, Reconstruction procedure)
+DEFAULT_ETA = 0.5                     # step size used for the synthetic workloads (see header)
+DEFAULT_PRECOND_SCALE = 1.0 / (4.0 * math.pi ** 2)  # s_P of the preconditioner (see header)
+
+
+# --------------------------------------------------------------------------- grids & windows
+
+def spatial_frequencies(ny: int, nx: int, pixel_m: float):
+    """Spatial frequencies ``u`` (along x) and ``v`` (along y) in cycles/m.
+
+    DFT bin ``k`` of an ``n``-point axis has frequency ``k/(n p)`` for
+    ``k < n/2`` and ``(k - n)/(n p)`` otherwise (the usual FFT ordering).
+    """
+    def axis(n):
+        k = np.arange(n, dtype=np.float64)
+        k = np.where(k < (n + 1) // 2, k, k - n)
+        return k / (n * pixel_m)
+    return axis(nx)[None, :], axis(ny)[:, None]
+
+
+def coherence_lengths(sigma_x_px: float, sigma_y_px: float, pixel_m: float):
+    """``x_coh, y_coh`` of a Gaussian IPSF of std ``sigma`` px (Eq. 4 rewritten)."""
+    c = 2.0 * math.sqrt(math.pi) * pixel_m
+    return c * sigma_x_px, c * sigma_y_px
+
+
+def iotf_window(u, v, x_coh: float, y_coh: float):
+    """Eq. 5: ``IOTF_k = exp[-(pi/2)(u^2 x_coh^2 + v^2 y_coh^2)]``."""
+    return np.exp(-0.5 * math.pi * (u * u * x_coh * x_coh + v * v * y_coh * y_coh))
+
+
+def ipsf_kernel(ny: int, nx: int, pixel_m: float, x_coh: float, y_coh: float):
+    """Eq. 4 sampled at pixel centres of a periodic grid (origin at index 0), in 1/m^2."""
+    def axis(n):
+        k = np.arange(n, dtype=np.float64)
+        return np.where(k < (n + 1) // 2, k, k - n) * pixel_m
+    x = axis(nx)[None, :]
+    y = axis(ny)[:, None]
+    return 2.0 / (x_coh * y_coh) * np.exp(-2.0 * math.pi * (x * x / x_coh ** 2 + y * y / y_coh ** 2))
+
+
+def stf_window(u, v, x_coh: float, y_coh: float, gamma: float):
+    """Eq. 14: ``STF_k = exp[-pi gamma (u^2 x_coh^2 + v^2 y_coh^2)]``."""
+    return np.exp(-math.pi * gamma * (u * u * x_coh * x_coh + v * v * y_coh * y_coh))
+
+
+def regularization_window(u, v, x_coh: float, y_coh: float, gamma: float):
+    """Eq. 15: ``Gamma^2_k = 1 - STF_k``."""
+    return 1.0 - stf_window(u, v, x_coh, y_coh, gamma)
+
+
+def preconditioning_filter(u, v, pixel_m: float, scale: float = DEFAULT_PRECOND_SCALE):
+    """Eq. 11: ``P^-1_k = scale/(u^2 + v^2)`` with frequencies in cycles/pixel; 0 at DC."""
+    rho2 = (u * u + v * v) * pixel_m * pixel_m
+    out = np.zeros(np.broadcast(u, v).shape)
+    nz = rho2 > 0
+    out[nz] = scale / rho2[nz]
+    return out
+
+
+def transfer_function(u, v, wavelength_m: float, distance_m: float):
+    """FreePropagation window ``Q_k = exp(i 2 pi w L)``, ``w = sqrt(lambda^-2 - u^2 - v^2)``.
+
+    The constant ``exp(i 2 pi L / lambda)`` is dropped.  The remaining phase
+    ``2 pi L (w - 1/lambda)`` is evaluated without cancellation; evanescent
+    bins (``lambda^2 rho^2 >= 1``) are 0.
+    """
+    rho2 = u * u + v * v
+    s = wavelength_m * wavelength_m * rho2
+    prop = s < 1.0
+    root = np.sqrt(np.where(prop, 1.0 - s, 0.0))
+    theta = -2.0 * math.pi * distance_m * wavelength_m * rho2 / (1.0 + root)
+    return np.where(prop, np.exp(1j * theta), 0.0)
+
+
+# --------------------------------------------------------------------------- problem
+
+@dataclasses.dataclass
+class Problem:
+    """Everything Algorithm S1 takes besides ``y`` (windows precomputed in FP64)."""
+
+    t: np.ndarray            # diffuser transmission, complex128
+    wavelength_m: float
+    z1_m: float
+    z2_m: float
+    pixel_m: float
+    iotf: np.ndarray         # IOTF_k
+    p_inv: np.ndarray        # P^-1_k
+    gamma2: np.ndarray       # Gamma^2_k
+    alpha: complex
+    eta: float
+    u: np.ndarray
+    v: np.ndarray
+    precondition: bool = True
+
+    @property
+    def shape(self):
+        return self.t.shape
+
+
+def make_problem(t, geometry, *, alpha: complex = PAPER_ALPHA, gamma: float = PAPER_GAMMA,
+                 eta: float = DEFAULT_ETA, precond_scale: float = DEFAULT_PRECOND_SCALE,
+                 precondition: bool = True,
+                 iotf: np.ndarray | None = None) -> Problem:
+    """Build the FP64 windows of one projection from a ``synthetic.Geometry``-like object."""
+    g = geometry
+    u, v = spatial_frequencies(g.ny, g.nx, g.pixel_m)
+    x_coh, y_coh = coherence_lengths(g.sigma_x_px, g.sigma_y_px, g.pixel_m)
+    win = iotf_window(u, v, x_coh, y_coh) if iotf is None else np.asarray(iotf, np.float64)
+    return Problem(
+        t=np.asarray(t, dtype=np.complex128),
+        wavelength_m=g.wavelength_m, z1_m=g.z1_m, z2_m=g.z2_m, pixel_m=g.pixel_m,
+        iotf=win,
+        p_inv=preconditioning_filter(u, v, g.pixel_m, precond_scale),
+        gamma2=regularization_window(u, v, x_coh, y_coh, gamma),
+        alpha=complex(alpha), eta=float(eta), u=u, v=v, precondition=precondition,
+    )
+
+
+# --------------------------------------------------------------------------- Algorithm S2
+
+FFT_WORKERS = -1  # scipy.fft threads (-1: all cores); the transform itself is unchanged
+
+
+def fft2(a):
+    """2-D DFT ``A_k = sum_r a_r exp(-2 pi i k.r / n)`` (library primitive)."""
+    return _sfft.fft2(np.asarray(a, np.complex128), workers=FFT_WORKERS)
+
+
+def ifft2(a):
+    """Inverse 2-D DFT with the ``1/m`` normalisation (library primitive)."""
+    return _sfft.ifft2(np.asarray(a, np.complex128), workers=FFT_WORKERS)
+
+
+def filter_(x, w):
+    """Filter: ``F^-1{ F{x} W_k }`` (Algorithm S2)."""
+    return ifft2(fft2(x) * w)
+
+
+def free_propagation(x, prob: Problem, distance_m: float):
+    """FreePropagation over ``distance_m`` (negative distances propagate backwards)."""
+    return filter_(x, transfer_function(prob.u, prob.v, prob.wavelength_m, distance_m))
+
+
+def physical_model(psi, prob: Problem):
+    """PhysicalModel (Eq. 1): returns ``f, x, v``."""
+    x = np.exp(psi)
+    v = free_propagation(x, prob, prob.z1_m)             # sample -> diffuser
+    v = free_propagation(prob.t * v, prob, prob.z2_m)    # diffuser -> detector
+    f = np.real(filter_(np.abs(v) ** 2, prob.iotf))      # IPSF convolution
+    return f, x, v
+
+
+def wirtinger_derivative(e, x, v, prob: Problem):
+    """WirtingerDerivative: back-propagate the misfit ``e = y - f``."""
+    g = np.real(filter_(-e, prob.iotf))
+    g = free_propagation(v * g, prob, -prob.z2_m)
+    g = free_propagation(np.conj(prob.t) * g, prob, -prob.z1_m)
+    g = np.conj(x) * g
+    return g / np.max(np.abs(prob.t) ** 2)
+
+
+def preconditioner(g, prob: Problem):
+    """Preconditioner: inverse-Laplacian filter on the phase part ``Im g`` only."""
+    gi = np.imag(g)
+    if prob.precondition:
+        gi = np.real(filter_(gi, prob.p_inv))
+    return np.real(g) + 1j * gi
+
+
+def regularizer(psi, prob: Problem):
+    """Regularizer: ``Re(alpha) Re(rho) + i Im(alpha) Im(rho)``, ``rho = Filter(psi, Gamma^2)``."""
+    rho = filter_(psi, prob.gamma2)
+    return prob.alpha.real * np.real(rho) + 1j * prob.alpha.imag * np.imag(rho)
+
+
+def loss(y, f) -> float:
+    """Eq. 2: ``sum_r (y_r - f_r)^2``."""
+    return float(np.sum((np.asarray(y, np.float64) - f) ** 2))
+
+
+def gradient(psi, y, prob: Problem):
+    """Loss, Wirtinger gradient ``g`` and update direction ``d`` at ``psi``."""
+    f, x, v = physical_model(psi, prob)
+    e = np.asarray(y, np.float64) - f
+    g = wirtinger_derivative(e, x, v, prob)
+    d = preconditioner(g, prob) + regularizer(psi, prob)
+    return float(np.sum(e * e)), g, d
+
+
+def nesterov_tau(tau: float) -> float:
+    """Momentum scalar update of Algorithm S1: ``(1 + sqrt(1 + 4 tau^2)) / 2``."""
+    return 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * tau * tau))
+
+
+def field_correlation(psi_a, psi_b) -> float:
+    """Normalised correlation of the fields ``exp(psi_a)`` and ``exp(psi_b)``."""
+    xa, xb = np.exp(psi_a), np.exp(psi_b)
+    num = abs(np.vdot(xa, xb))
+    return float(num / math.sqrt(np.vdot(xa, xa).real * np.vdot(xb, xb).real))
+
+
+@dataclasses.dataclass
+class PWFState:
+    """Iterate of Algorithm S1: extrapolated ``psi``, gradient-step ``z``, momentum ``tau``."""
+
+    psi: np.ndarray
+    z: np.ndarray
+    tau: float = 1.0
+    k: int = 0
+
+
+def initial_state(shape, psi0=None) -> PWFState:
+    psi = np.zeros(shape, np.complex128) if psi0 is None else np.array(psi0, np.complex128)
+    return PWFState(psi=psi, z=np.zeros(shape, np.complex128), tau=1.0, k=0)
+
+
+def nesterov_update(psi, z_prev, tau_prev: float, d, eta: float):
+    """Gradient step and Nesterov extrapolation of Algorithm S1.
+
+    ``z = psi - eta d``; ``tau = (1 + sqrt(1 + 4 tau_prev^2)) / 2``;
+    ``psi_new = z + ((tau_prev - 1) / tau) (z - z_prev)``.
+    """
+    z = psi - eta * d
+    tau = nesterov_tau(tau_prev)
+    return z, tau, z + ((tau_prev - 1.0) / tau) * (z - z_prev)
+
+
+def pwf_step(state: PWFState, y, prob: Problem):
+    """One iteration of Algorithm S1.  Returns (new state, loss at the entering ``psi``)."""
+    f, x, v = physical_model(state.psi, prob)
+    e = np.asarray(y, np.float64) - f
+    l = float(np.sum(e * e))
+    if not math.isfinite(l):
+        raise FloatingPointError("PWF loss is not finite")
+    g = wirtinger_derivative(e, x, v, prob)
+    d = preconditioner(g, prob) + regularizer(state.psi, prob)
+    z, tau, psi = nesterov_update(state.psi, state.z, state.tau, d, prob.eta)
+    return PWFState(psi=psi, z=z, tau=tau, k=state.k + 1), l
+
+
+def pwf(y, prob: Problem, iters: int, corr_tol: float = 0.0, psi0=None, state: PWFState | None = None):
+    """Algorithm S1: ``iters`` iterations (or fewer when the correlation stop is met).
+
+    Returns ``(psi, loss_history, state)``.  With ``corr_tol > 0`` the loop stops
+    after the first iteration whose new ``exp(psi)`` correlates with the
+    previous one above ``corr_tol`` (the paper uses ``10^-0.00001``).
+    """
+    st = initial_state(prob.shape, psi0) if state is None else state
+    hist = []
+    for _ in range(iters):
+        prev = st.psi
+        st, l = pwf_step(st, y, prob)
+        hist.append(l)
+        if corr_tol > 0 and field_correlation(st.psi, prev) > corr_tol:
+            break
+    return st.psi, np.array(hist), st
+
+
+# --------------------------------------------------------------------------- linearisation (test aid)
+
+def physical_model_jvp(psi, dpsi, prob: Problem):
+    """Directional derivative of ``f`` at ``psi`` along the complex perturbation ``dpsi``."""
+    x = np.exp(psi)
+    v = free_propagation(prob.t * free_propagation(x, prob, prob.z1_m), prob, prob.z2_m)
+    dv = free_propagation(prob.t * free_propagation(x * dpsi, prob, prob.z1_m), prob, prob.z2_m)
+    return np.real(filter_(2.0 * np.real(np.conj(v) * dv), prob.iotf))
