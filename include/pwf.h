@@ -1,0 +1,187 @@
+/*
+ * pwf.h - C ABI of the preconditioned Wirtinger flow (PWF) hot path on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operations follow "Speckle-based X-ray microtomography via
+ * preconditioned Wirtinger flow" (Lee, Hugonnet, Lim, Park, arXiv 2503.20146):
+ * the forward model of Eq. 1 (PhysicalModel in Algorithm S2), the loss of
+ * Eq. 2, the Wirtinger derivative, preconditioner and regulariser of
+ * Algorithm S2, and the Nesterov-accelerated loop of Algorithm S1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Fields are row-major [ny][nx] with x fastest.  Complex fields are
+ *   interleaved single precision (re, im) pairs ("complex64"); intensities
+ *   are float32.  Every data pointer is a device pointer unless stated.
+ * - A call works on a batch of n independent instances (projections or
+ *   regions of interest).  Per-instance arguments are arrays of n pointers
+ *   that live in HOST memory and point to device buffers; problems are an
+ *   array of n descriptors in host memory.  Instances may share a diffuser.
+ * - Supported grids: nx, ny in {128, 256, 512, 1024, 2048} (independently).
+ * - The caller owns every device buffer, including the workspace whose size
+ *   pwf_workspace_size() returns.  The library allocates only its own
+ *   immutable twiddle tables (once per device) and never on the hot path.
+ * - Calls are asynchronous on `stream` (a hipStream_t; NULL is the default
+ *   stream).  Host pointer arrays may be reused as soon as a call returns.
+ * - Errors in arguments are reported synchronously through the return value
+ *   before any work is queued.  A non-finite loss found on the GPU sets a
+ *   device flag that pwf_sync_status() reports.  Nothing aborts or throws
+ *   across this boundary.
+ * - Calls that overlap on one workspace race; use one workspace per stream.
+ */
+#ifndef PWF_H_
+#define PWF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PWF_OK = 0,
+  PWF_ERR_ARG = -1,        /* NULL or non-finite argument, bad count */
+  PWF_ERR_SIZE = -2,       /* grid side outside the supported set */
+  PWF_ERR_EVANESCENT = -3, /* lambda / (2 p) >= 1/sqrt(2): evanescent bins */
+  PWF_ERR_WORKSPACE = -4,  /* workspace NULL, misaligned or too small */
+  PWF_ERR_HIP = -5,        /* a HIP runtime call failed */
+  PWF_ERR_NONFINITE = -6   /* the loss became NaN or Inf on the GPU */
+} pwf_status;
+
+/* Imaging geometry (Results, PWF subsection; Fig. 1a): grid, pixel pitch p at
+ * the detector, X-ray wavelength lambda, sample-to-diffuser distance L1 and
+ * diffuser-to-detector distance L2, all in SI units.  Distances may be 0
+ * (identity propagation) but not negative. */
+typedef struct {
+  int32_t nx, ny;
+  double pixel_m;
+  double wavelength_m;
+  double z1_m, z2_m;
+} pwf_geometry;
+
+/* Partial coherence (Methods, IOTF; Eqs. 4-5): Gaussian intensity point
+ * spread function with standard deviation sigma (pixels) at the detector,
+ * x_coh = 2 sqrt(pi) sigma p.  sigma = 0 means a fully coherent source. */
+typedef struct {
+  double sigma_x_px, sigma_y_px;
+} pwf_source;
+
+/* Solver parameters (Results, PWF subsection; Methods, Eqs. 11, 14-15).
+ *   eta            step size of the gradient step (Algorithm S1)
+ *   alpha_re/im    complex regularisation parameter alpha
+ *   gamma          oversampling ratio of the sample transfer function
+ *   precond_scale  s_P in P^-1_k = s_P / (u^2 + v^2), u, v in cycles/pixel
+ *   precondition   0 skips the preconditioner (Im g is used unfiltered) */
+typedef struct {
+  double eta;
+  double alpha_re, alpha_im;
+  double gamma;
+  double precond_scale;
+  int32_t precondition;
+} pwf_params;
+
+/* One instance: geometry, source, parameters and the diffuser transmission
+ * t (device, complex64 [ny][nx]; Methods, "Diffuser transmission function"). */
+typedef struct {
+  pwf_geometry geom;
+  pwf_source source;
+  pwf_params params;
+  const void* diffuser;
+} pwf_problem;
+
+/* Iterate of Algorithm S1 for pwf_step, in caller memory (all device,
+ * complex64 [ny][nx]):
+ *   psi      extrapolated iterate psi in real space (read/written)
+ *   psi_hat  spectrum of psi in the library's frequency layout
+ *   z_hat    spectrum of the gradient-step iterate z, same layout
+ *   y_hat    spectrum of the measured speckle y, same layout
+ *   k        iterations done so far (host value, advanced by pwf_step)
+ * The frequency layout is row-major [ky][s]: column kx of the 2-D DFT sits at
+ * s = 2 kx for 0 < kx < nx/2, at s = 2 (nx - kx) + 1 for nx/2 < kx < nx, at
+ * s = 0 for kx = 0 and at s = 1 for kx = nx/2, so that kx and -kx are
+ * neighbours. */
+typedef struct {
+  void* psi;
+  void* psi_hat;
+  void* z_hat;
+  void* y_hat;
+  int32_t k;
+} pwf_state;
+
+/* Human-readable text of a status code (static storage). */
+const char* pwf_status_string(int32_t status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t pwf_version(void);
+
+/* Bytes of workspace that any call below needs for this batch; 0 if the
+ * problems are invalid.  The workspace must be 256-byte aligned. */
+size_t pwf_workspace_size(const pwf_problem* problems, int32_t n);
+
+/* Forward model, Eq. 1 / PhysicalModel: f = |P2{t P1{exp(psi)}}|^2 * IPSF.
+ *   psi[i]   device complex64 [ny][nx], the complex phase -mu + i phi
+ *   f_out[i] device float32 [ny][nx] */
+pwf_status pwf_forward(const pwf_problem* problems, int32_t n, const void* const* psi, float* const* f_out,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Loss (Eq. 2), Wirtinger derivative g (WirtingerDerivative of Algorithm S2,
+ * normalised by max|t|^2) and update direction d = Preconditioner(g) +
+ * Regularizer(psi) at psi.  The real gradient of the loss is
+ * dL/dRe psi + i dL/dIm psi = 4 max|t|^2 g.
+ *   y[i]        device float32 [ny][nx], measured speckle
+ *   g_out[i]    device complex64 or NULL (array itself may be NULL)
+ *   d_out[i]    device complex64 or NULL (array itself may be NULL)
+ *   loss_out    device float64 [n] or NULL */
+pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
+                        void* const* g_out, void* const* d_out, double* loss_out, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/* Prepare states for pwf_step: psi = psi0 (or 0 when psi0 or psi0[i] is NULL),
+ * z = 0, momentum scalar 1, k = 0 (Algorithm S1 initialisation), and the
+ * spectrum of y.  states is a host array of n pwf_state. */
+pwf_status pwf_state_init(const pwf_problem* problems, int32_t n, pwf_state* states, const void* const* psi0,
+                          const float* const* y, void* workspace, size_t workspace_bytes, void* stream);
+
+/* One iteration of Algorithm S1 on every instance: loss at the entering psi,
+ * gradient, direction, z = psi - eta d, Nesterov extrapolation.  Advances
+ * states[i].k.  loss_out: device float64 [n] or NULL. */
+pwf_status pwf_step(const pwf_problem* problems, int32_t n, pwf_state* states, double* loss_out,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Algorithm S1 from psi = 0 for `iters` iterations per instance.
+ *   psi_out[i]  device complex64 [ny][nx]: psi after the last iteration
+ *   loss_hist   device float64 [n * iters] or NULL: loss at the psi entering
+ *               each iteration, instance-major
+ *   corr_tol    must be <= 0 (fixed iteration count); the correlation stop of
+ *               the Methods section is not available in this entry point
+ *   iters_done  host int32 [n] or NULL: receives iters for every instance
+ * With graph mode on (the default) the whole loop is one hipGraph launch. */
+pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const* y, void* const* psi_out,
+                     int32_t iters, double corr_tol, double* loss_hist, int32_t* iters_done, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
+/* Reference GPU path for speed comparisons: the literal Algorithm S1/S2 on
+ * ONE instance, one kernel per operation (16 two-dimensional FFTs plus
+ * element-wise kernels per iteration), no fusion, no batching, no graph.
+ * Same arguments and results as pwf_solve with n = 1. */
+pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi_out, int32_t iters,
+                           double* loss_hist, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Capture pwf_solve's loop in a hipGraph (1, default) or launch eagerly (0). */
+void pwf_set_graph_mode(int32_t on);
+
+/* Wait for `stream` and report PWF_ERR_NONFINITE if a loss computed by the
+ * last call that used `workspace` was NaN or Inf, PWF_ERR_HIP on a runtime
+ * error, else PWF_OK.  Every loss-computing call clears the flag when it
+ * starts. */
+pwf_status pwf_sync_status(void* workspace, void* stream);
+
+/* Release the library's twiddle tables and cached graphs. */
+void pwf_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWF_H_ */

@@ -1,0 +1,17 @@
+"""MI355X-native preconditioned Wirtinger flow (PWF) hot path.
+
+The computation lives in ``libpwf.so`` (hand-written HIP for gfx950, C ABI in
+``include/pwf.h``); this package marshals torch tensors into it.
+"""
+
+from .api import (  # noqa: F401
+    DEFAULT_ALPHA,
+    DEFAULT_ETA,
+    DEFAULT_GAMMA,
+    DEFAULT_PRECOND_SCALE,
+    PWF,
+    Problem,
+    problem_from_geometry,
+    set_graph_mode,
+)
+from ._lib import PwfError, load  # noqa: F401

@@ -1,0 +1,190 @@
+"""Torch-facing wrappers of the libpwf C ABI.
+
+Argument marshalling only: tensors are passed to the library as device
+pointers on the current HIP stream; every step of the method runs in the
+library's kernels.  Torch provides device memory and streams.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+from typing import Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+DEFAULT_ETA = 0.5
+DEFAULT_ALPHA = complex(0.1, 0.01)
+DEFAULT_GAMMA = 1.0
+DEFAULT_PRECOND_SCALE = 1.0 / (4.0 * math.pi ** 2)
+
+
+@dataclasses.dataclass
+class Problem:
+    """One PWF instance (projection or region of interest)."""
+
+    nx: int
+    ny: int
+    pixel_m: float
+    wavelength_m: float
+    z1_m: float
+    z2_m: float
+    sigma_x_px: float
+    sigma_y_px: float
+    diffuser: torch.Tensor            # complex64 [ny, nx] on the GPU
+    eta: float = DEFAULT_ETA
+    alpha: complex = DEFAULT_ALPHA
+    gamma: float = DEFAULT_GAMMA
+    precond_scale: float = DEFAULT_PRECOND_SCALE
+    precondition: bool = True
+
+    def to_c(self) -> _lib.pwf_problem:
+        d = self.diffuser
+        if d.dtype != torch.complex64 or not d.is_contiguous() or tuple(d.shape) != (self.ny, self.nx):
+            raise ValueError("diffuser must be a contiguous complex64 tensor of shape (ny, nx)")
+        p = _lib.pwf_problem()
+        p.geom = _lib.pwf_geometry(self.nx, self.ny, self.pixel_m, self.wavelength_m, self.z1_m, self.z2_m)
+        p.source = _lib.pwf_source(self.sigma_x_px, self.sigma_y_px)
+        p.params = _lib.pwf_params(self.eta, self.alpha.real, self.alpha.imag, self.gamma, self.precond_scale,
+                                   1 if self.precondition else 0)
+        p.diffuser = d.data_ptr()
+        return p
+
+
+def problem_from_geometry(geometry, diffuser: torch.Tensor, **kw) -> Problem:
+    """Build a Problem from any object with nx, ny, pixel_m, wavelength_m, z1_m, z2_m, sigma_*_px."""
+    g = geometry
+    return Problem(nx=g.nx, ny=g.ny, pixel_m=g.pixel_m, wavelength_m=g.wavelength_m, z1_m=g.z1_m, z2_m=g.z2_m,
+                   sigma_x_px=g.sigma_x_px, sigma_y_px=g.sigma_y_px, diffuser=diffuser, **kw)
+
+
+def _ptrs(tensors, dtype=None, shape=None) -> ctypes.Array:
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        if t is None:
+            arr[i] = None
+            continue
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("buffers must be contiguous GPU tensors")
+        if dtype is not None and t.dtype != dtype:
+            raise ValueError(f"expected {dtype}, got {t.dtype}")
+        if shape is not None and tuple(t.shape) != tuple(shape[i]):
+            raise ValueError(f"expected shape {shape[i]}, got {tuple(t.shape)}")
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class PWF:
+    """A batch of PWF instances with its workspace."""
+
+    def __init__(self, problems: Sequence[Problem]):
+        if not problems:
+            raise ValueError("need at least one problem")
+        self.lib = _lib.load()
+        self.problems = list(problems)
+        self.n = len(self.problems)
+        self.device = self.problems[0].diffuser.device
+        self._c = (_lib.pwf_problem * self.n)(*[p.to_c() for p in self.problems])
+        size = self.lib.pwf_workspace_size(self._c, self.n)
+        if size == 0:
+            raise ValueError("invalid problem description (see pwf_workspace_size)")
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace is not 256-byte aligned")
+        self.shapes = [(p.ny, p.nx) for p in self.problems]
+
+    # -- helpers
+    def _ws(self):
+        return ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_size_t(self.workspace.numel())
+
+    def _empty(self, dtype):
+        return [torch.empty(s, dtype=dtype, device=self.device) for s in self.shapes]
+
+    # -- entry points
+    def forward(self, psi: Sequence[torch.Tensor], out: Sequence[torch.Tensor] | None = None):
+        out = self._empty(torch.float32) if out is None else list(out)
+        ws, nb = self._ws()
+        check(self.lib.pwf_forward(self._c, self.n, _ptrs(psi, torch.complex64, self.shapes),
+                                   _ptrs(out, torch.float32, self.shapes), ws, nb, _stream(self.device)),
+              "pwf_forward")
+        return out
+
+    def gradient(self, psi, y, want_g: bool = True, want_d: bool = True):
+        g = self._empty(torch.complex64) if want_g else None
+        d = self._empty(torch.complex64) if want_d else None
+        loss = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        ws, nb = self._ws()
+        check(self.lib.pwf_gradient(self._c, self.n, _ptrs(psi, torch.complex64, self.shapes),
+                                    _ptrs(y, torch.float32, self.shapes),
+                                    _ptrs(g, torch.complex64, self.shapes) if g else None,
+                                    _ptrs(d, torch.complex64, self.shapes) if d else None,
+                                    ctypes.c_void_p(loss.data_ptr()), ws, nb, _stream(self.device)),
+              "pwf_gradient")
+        return loss, g, d
+
+    def init_states(self, y, psi0=None):
+        states = []
+        arr = (_lib.pwf_state * self.n)()
+        for i, s in enumerate(self.shapes):
+            st = {k: torch.empty(s, dtype=torch.complex64, device=self.device)
+                  for k in ("psi", "psi_hat", "z_hat", "y_hat")}
+            st["k"] = 0
+            states.append(st)
+            arr[i] = _lib.pwf_state(st["psi"].data_ptr(), st["psi_hat"].data_ptr(), st["z_hat"].data_ptr(),
+                                    st["y_hat"].data_ptr(), 0)
+        ws, nb = self._ws()
+        p0 = _ptrs(psi0, torch.complex64, self.shapes) if psi0 is not None else None
+        check(self.lib.pwf_state_init(self._c, self.n, arr, p0, _ptrs(y, torch.float32, self.shapes), ws, nb,
+                                      _stream(self.device)), "pwf_state_init")
+        return states
+
+    def step(self, states):
+        arr = (_lib.pwf_state * self.n)()
+        for i, st in enumerate(states):
+            arr[i] = _lib.pwf_state(st["psi"].data_ptr(), st["psi_hat"].data_ptr(), st["z_hat"].data_ptr(),
+                                    st["y_hat"].data_ptr(), st["k"])
+        loss = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        ws, nb = self._ws()
+        check(self.lib.pwf_step(self._c, self.n, arr, ctypes.c_void_p(loss.data_ptr()), ws, nb,
+                                _stream(self.device)), "pwf_step")
+        for i, st in enumerate(states):
+            st["k"] = arr[i].k
+        return loss
+
+    def solve(self, y, iters: int, psi_out=None, loss_hist: bool = True):
+        psi_out = self._empty(torch.complex64) if psi_out is None else list(psi_out)
+        hist = torch.empty((self.n, max(iters, 1)), dtype=torch.float64, device=self.device) if loss_hist else None
+        done = (ctypes.c_int32 * self.n)()
+        ws, nb = self._ws()
+        check(self.lib.pwf_solve(self._c, self.n, _ptrs(y, torch.float32, self.shapes),
+                                 _ptrs(psi_out, torch.complex64, self.shapes), iters, 0.0,
+                                 ctypes.c_void_p(hist.data_ptr()) if hist is not None else None, done, ws, nb,
+                                 _stream(self.device)), "pwf_solve")
+        return psi_out, hist
+
+    def solve_plain(self, y: torch.Tensor, iters: int, psi_out=None, loss_hist: bool = True):
+        if self.n != 1:
+            raise ValueError("the plain path runs one instance")
+        psi_out = self._empty(torch.complex64)[0] if psi_out is None else psi_out
+        hist = torch.empty(max(iters, 1), dtype=torch.float64, device=self.device) if loss_hist else None
+        ws, nb = self._ws()
+        check(self.lib.pwf_solve_plain(self._c, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(psi_out.data_ptr()),
+                                       iters, ctypes.c_void_p(hist.data_ptr()) if hist is not None else None,
+                                       ws, nb, _stream(self.device)), "pwf_solve_plain")
+        return psi_out, hist
+
+    def sync_status(self) -> int:
+        ws, _ = self._ws()
+        return self.lib.pwf_sync_status(ws, _stream(self.device))
+
+
+def set_graph_mode(on: bool) -> None:
+    _lib.load().pwf_set_graph_mode(1 if on else 0)

@@ -1,0 +1,813 @@
+// C ABI of libpwf: argument validation, workspace layout, launch sequences of
+// the fused path (Algorithm S1 as twelve sweeps per iteration), the plain
+// reference path, and hipGraph capture of the solve loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pwf.h"
+#include "pwf_device.h"
+#include "pwf_kernels.h"
+
+using pwf::Inst;
+using pwf::Sweep;
+
+namespace {
+
+constexpr int kVersion = 10000;        // 1.0.0
+constexpr int kBetaCap = 1 << 16;      // iterations covered by the momentum table
+constexpr size_t kAlign = 256;
+constexpr int kSizes[] = {128, 256, 512, 1024, 2048};
+constexpr int kMaxDevices = 64;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool supported_side(int n) {
+  for (int s : kSizes)
+    if (s == n) return true;
+  return false;
+}
+int size_index(int n) {
+  for (int i = 0; i < 5; ++i)
+    if (kSizes[i] == n) return i;
+  return -1;
+}
+
+// ------------------------------------------------------------------ device context
+
+struct GraphKey {
+  void* ws;
+  int n;
+  int iters;
+  std::vector<int> dims;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(ws, n, iters, dims) < std::tie(o.ws, o.n, o.iters, o.dims);
+  }
+};
+
+struct Context {
+  bool ready = false;
+  float2* tw[5] = {};          // twiddle tables per supported side
+  double* beta = nullptr;      // momentum table
+  hipStream_t side = nullptr;  // internal stream for graph launches
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  // pinned staging for descriptor uploads (ring of slots)
+  static constexpr int kSlots = 4;
+  void* stage[kSlots] = {};
+  size_t stage_bytes[kSlots] = {};
+  hipEvent_t stage_ev[kSlots] = {};
+  int next_slot = 0;
+};
+
+std::mutex g_mu;
+Context g_ctx[kMaxDevices];
+bool g_graph_mode = true;
+
+pwf_status hip_fail(hipError_t e) { return e == hipSuccess ? PWF_OK : PWF_ERR_HIP; }
+#define PWF_HIP(call)                              \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return PWF_ERR_HIP;      \
+  } while (0)
+
+pwf_status context_for_current(Context** out) {
+  int dev = 0;
+  PWF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return PWF_ERR_HIP;
+  Context& c = g_ctx[dev];
+  if (!c.ready) {
+    for (int i = 0; i < 5; ++i) {
+      const int cnt = pwf::plan_twiddles(kSizes[i], nullptr);
+      std::vector<float2> host(cnt);
+      pwf::plan_twiddles(kSizes[i], host.data());
+      PWF_HIP(hipMalloc(&c.tw[i], sizeof(float2) * std::max(cnt, 1)));
+      PWF_HIP(hipMemcpy(c.tw[i], host.data(), sizeof(float2) * cnt, hipMemcpyHostToDevice));
+    }
+    // beta_k = (tau_k - 1) / tau_{k+1}, tau_0 = 1, tau_{k+1} = (1 + sqrt(1 + 4 tau_k^2)) / 2
+    std::vector<double> b(kBetaCap);
+    double tau = 1.0;
+    for (int k = 0; k < kBetaCap; ++k) {
+      const double nt = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
+      b[k] = (tau - 1.0) / nt;
+      tau = nt;
+    }
+    PWF_HIP(hipMalloc(&c.beta, sizeof(double) * kBetaCap));
+    PWF_HIP(hipMemcpy(c.beta, b.data(), sizeof(double) * kBetaCap, hipMemcpyHostToDevice));
+    PWF_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+    PWF_HIP(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
+    PWF_HIP(hipEventCreateWithFlags(&c.ev_out, hipEventDisableTiming));
+    for (int i = 0; i < Context::kSlots; ++i) PWF_HIP(hipEventCreateWithFlags(&c.stage_ev[i], hipEventDisableTiming));
+    c.ready = true;
+  }
+  *out = &c;
+  return PWF_OK;
+}
+
+// Copy descriptors to the workspace through a pinned staging slot.
+pwf_status upload(Context& c, const void* src, size_t bytes, void* dst, hipStream_t st) {
+  const int slot = c.next_slot;
+  c.next_slot = (c.next_slot + 1) % Context::kSlots;
+  PWF_HIP(hipEventSynchronize(c.stage_ev[slot]));
+  if (c.stage_bytes[slot] < bytes) {
+    if (c.stage[slot]) PWF_HIP(hipHostFree(c.stage[slot]));
+    c.stage[slot] = nullptr;
+    c.stage_bytes[slot] = 0;
+    PWF_HIP(hipHostMalloc(&c.stage[slot], bytes));
+    c.stage_bytes[slot] = bytes;
+  }
+  std::memcpy(c.stage[slot], src, bytes);
+  PWF_HIP(hipMemcpyAsync(dst, c.stage[slot], bytes, hipMemcpyHostToDevice, st));
+  PWF_HIP(hipEventRecord(c.stage_ev[slot], st));
+  return PWF_OK;
+}
+
+// ------------------------------------------------------------------ validation
+
+bool finite(double x) { return std::isfinite(x); }
+
+pwf_status validate_problem(const pwf_problem& p) {
+  const pwf_geometry& g = p.geom;
+  if (!supported_side(g.nx) || !supported_side(g.ny)) return PWF_ERR_SIZE;
+  if (!finite(g.pixel_m) || g.pixel_m <= 0 || !finite(g.wavelength_m) || g.wavelength_m <= 0) return PWF_ERR_ARG;
+  if (!finite(g.z1_m) || !finite(g.z2_m) || g.z1_m < 0 || g.z2_m < 0) return PWF_ERR_ARG;
+  // largest lambda^2 rho^2 on the grid is (lambda/p)^2 / 2 (corner bin)
+  const double lp = g.wavelength_m / g.pixel_m;
+  if (0.5 * lp * lp >= 1.0) return PWF_ERR_EVANESCENT;
+  const pwf_source& s = p.source;
+  if (!finite(s.sigma_x_px) || !finite(s.sigma_y_px) || s.sigma_x_px < 0 || s.sigma_y_px < 0) return PWF_ERR_ARG;
+  const pwf_params& q = p.params;
+  if (!finite(q.eta) || !finite(q.alpha_re) || !finite(q.alpha_im) || !finite(q.gamma) || q.gamma < 0)
+    return PWF_ERR_ARG;
+  if (q.precondition && (!finite(q.precond_scale) || q.precond_scale <= 0)) return PWF_ERR_ARG;
+  if (!p.diffuser) return PWF_ERR_ARG;
+  return PWF_OK;
+}
+
+pwf_status validate_batch(const pwf_problem* probs, int32_t n) {
+  if (!probs || n <= 0) return PWF_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    const pwf_status st = validate_problem(probs[i]);
+    if (st != PWF_OK) return st;
+  }
+  return PWF_OK;
+}
+
+// ------------------------------------------------------------------ workspace layout
+
+size_t field_bytes(const pwf_problem& p) { return align_up((size_t)p.geom.nx * p.geom.ny * sizeof(float2)); }
+int n_partials(const pwf_problem& p) { return p.geom.nx / pwf::col_cols_per_block(p.geom.ny); }
+
+struct Layout {
+  size_t status = 0, maxt2 = 0, maxt2_part = 0, desc = 0, partials = 0;
+  std::vector<size_t> W, psi_hat, z_hat, v, psi, y_hat, extra0, extra1, part;
+  size_t total = 0;
+};
+
+// Region order keeps W, psi_hat and z_hat of all instances contiguous so that
+// one fill kernel clears them.
+Layout make_layout(const pwf_problem* probs, int n) {
+  Layout L;
+  size_t off = 0;
+  L.status = off;
+  off += kAlign;
+  L.maxt2 = off;
+  off += align_up(sizeof(float) * n);
+  L.maxt2_part = off;
+  off += align_up(sizeof(float) * (size_t)pwf::maxabs2_blocks() * n);
+  L.desc = off;
+  off += align_up(sizeof(Inst) * n);
+  L.part.resize(n);
+  L.partials = off;
+  for (int i = 0; i < n; ++i) {
+    L.part[i] = off;
+    off += align_up(sizeof(double) * std::max(n_partials(probs[i]), pwf::plain_elementwise_blocks()));
+  }
+  auto region = [&](std::vector<size_t>& r) {
+    r.resize(n);
+    for (int i = 0; i < n; ++i) {
+      r[i] = off;
+      off += field_bytes(probs[i]);
+    }
+  };
+  region(L.W);
+  region(L.psi_hat);
+  region(L.z_hat);
+  region(L.v);
+  region(L.psi);
+  region(L.y_hat);
+  // two more fields for the first instance (the plain path's buffers)
+  L.extra0.assign(1, off);
+  off += field_bytes(probs[0]);
+  L.extra1.assign(1, off);
+  off += field_bytes(probs[0]);
+  L.total = off;
+  return L;
+}
+
+// ------------------------------------------------------------------ descriptors
+
+Inst base_inst(const pwf_problem& p) {
+  Inst I;
+  std::memset(&I, 0, sizeof(I));
+  const pwf_geometry& g = p.geom;
+  I.nx = g.nx;
+  I.ny = g.ny;
+  I.n_partials = n_partials(p);
+  I.t = (const float2*)p.diffuser;
+  const double p2 = g.pixel_m * g.pixel_m;
+  I.chirp1_rev = g.z1_m * g.wavelength_m / (2.0 * p2);
+  I.chirp2_rev = g.z2_m * g.wavelength_m / (2.0 * p2);
+  I.s_coef = (g.wavelength_m / g.pixel_m) * (g.wavelength_m / g.pixel_m);
+  I.series = (0.5 * I.s_coef < 1e-4) ? 1 : 0;
+  const double pi2 = M_PI * M_PI;
+  I.iotf_cx = (float)(2.0 * pi2 * p.source.sigma_x_px * p.source.sigma_x_px);
+  I.iotf_cy = (float)(2.0 * pi2 * p.source.sigma_y_px * p.source.sigma_y_px);
+  I.stf_cx = (float)(4.0 * pi2 * p.params.gamma * p.source.sigma_x_px * p.source.sigma_x_px);
+  I.stf_cy = (float)(4.0 * pi2 * p.params.gamma * p.source.sigma_y_px * p.source.sigma_y_px);
+  I.pinv_scale = p.params.precondition ? (float)p.params.precond_scale : -1.0f;
+  I.alpha_c1 = (float)(0.5 * (p.params.alpha_re + p.params.alpha_im));
+  I.alpha_c2 = (float)(0.5 * (p.params.alpha_re - p.params.alpha_im));
+  I.eta = (float)p.params.eta;
+  I.inv_m_d = 1.0 / ((double)g.nx * g.ny);
+  I.inv_m = (float)I.inv_m_d;
+  return I;
+}
+
+// Instances grouped by grid shape; each class is a contiguous run of the
+// (reordered) descriptor table.
+struct Class {
+  int nx, ny, first, count;
+};
+
+struct Batch {
+  std::vector<int> order;  // descriptor slot -> caller index
+  std::vector<Class> classes;
+};
+
+Batch group(const pwf_problem* probs, int n) {
+  Batch b;
+  b.order.resize(n);
+  for (int i = 0; i < n; ++i) b.order[i] = i;
+  std::stable_sort(b.order.begin(), b.order.end(), [&](int a, int c) {
+    return std::make_pair(probs[a].geom.ny, probs[a].geom.nx) < std::make_pair(probs[c].geom.ny, probs[c].geom.nx);
+  });
+  for (int s = 0; s < n;) {
+    const pwf_problem& p = probs[b.order[s]];
+    int e = s;
+    while (e < n && probs[b.order[e]].geom.nx == p.geom.nx && probs[b.order[e]].geom.ny == p.geom.ny) ++e;
+    b.classes.push_back({p.geom.nx, p.geom.ny, s, e - s});
+    s = e;
+  }
+  return b;
+}
+
+struct Launcher {
+  Context& ctx;
+  char* ws;
+  const Layout& L;
+  const Batch& B;
+  hipStream_t st;
+  Inst* dev_desc() const { return (Inst*)(ws + L.desc); }
+  int32_t* status() const { return (int32_t*)(ws + L.status); }
+
+  Sweep sweep(const Class& c, int iter) const {
+    Sweep S;
+    S.inst = dev_desc() + c.first;
+    S.iter = iter;
+    S.beta = ctx.beta;
+    S.tw_row = ctx.tw[size_index(c.nx)];
+    S.tw_col = ctx.tw[size_index(c.ny)];
+    S.status = status();
+    S.blocks_per_inst = 0;
+    return S;
+  }
+  pwf_status row(int op, int iter = 0) const {
+    for (const Class& c : B.classes) {
+      Sweep S = sweep(c, iter);
+      S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx);
+      PWF_HIP(pwf::launch_row(c.nx, op, S.blocks_per_inst * c.count, S, st));
+    }
+    return PWF_OK;
+  }
+  pwf_status col(int op, int iter = 0) const {
+    for (const Class& c : B.classes) {
+      Sweep S = sweep(c, iter);
+      S.blocks_per_inst = c.nx / pwf::col_cols_per_block(c.ny);
+      PWF_HIP(pwf::launch_col(c.ny, op, S.blocks_per_inst * c.count, S, st));
+    }
+    return PWF_OK;
+  }
+};
+
+#define PWF_TRY(x)                      \
+  do {                                  \
+    const pwf_status s_ = (x);          \
+    if (s_ != PWF_OK) return s_;        \
+  } while (0)
+
+pwf_status check_ws(const pwf_problem* probs, int n, void* ws, size_t ws_bytes, Layout* out) {
+  if (!ws || ((uintptr_t)ws % kAlign) != 0) return PWF_ERR_WORKSPACE;
+  *out = make_layout(probs, n);
+  if (ws_bytes < out->total) return PWF_ERR_WORKSPACE;
+  return PWF_OK;
+}
+
+// max|t|^2 for every distinct diffuser; sets inst.maxt2.
+pwf_status launch_maxt2(const pwf_problem* probs, int n, const Batch& B, std::vector<Inst>& desc, char* ws,
+                        const Layout& L, hipStream_t st) {
+  std::vector<const void*> seen;
+  for (int s = 0; s < n; ++s) {
+    const pwf_problem& p = probs[B.order[s]];
+    int slot = -1;
+    for (size_t j = 0; j < seen.size(); ++j)
+      if (seen[j] == p.diffuser) slot = (int)j;
+    if (slot < 0) {
+      slot = (int)seen.size();
+      seen.push_back(p.diffuser);
+      float* part = (float*)(ws + L.maxt2_part) + (size_t)slot * pwf::maxabs2_blocks();
+      PWF_HIP(pwf::launch_maxabs2((const float2*)p.diffuser, (size_t)p.geom.nx * p.geom.ny, part,
+                                  (float*)(ws + L.maxt2) + slot, st));
+    }
+    desc[s].maxt2 = (const float*)(ws + L.maxt2) + slot;
+  }
+  return PWF_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char* pwf_status_string(int32_t s) {
+  switch (s) {
+    case PWF_OK: return "ok";
+    case PWF_ERR_ARG: return "invalid argument";
+    case PWF_ERR_SIZE: return "unsupported grid size (nx, ny must be 128, 256, 512, 1024 or 2048)";
+    case PWF_ERR_EVANESCENT: return "geometry has evanescent frequency bins (lambda/p >= sqrt(2))";
+    case PWF_ERR_WORKSPACE: return "workspace missing, misaligned (256 B) or too small";
+    case PWF_ERR_HIP: return "HIP runtime error";
+    case PWF_ERR_NONFINITE: return "non-finite loss (NaN or Inf) on the GPU";
+    default: return "unknown status";
+  }
+}
+
+int32_t pwf_version(void) { return kVersion; }
+
+size_t pwf_workspace_size(const pwf_problem* problems, int32_t n) {
+  if (validate_batch(problems, n) != PWF_OK) return 0;
+  return make_layout(problems, n).total;
+}
+
+void pwf_set_graph_mode(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_graph_mode = on != 0;
+}
+
+pwf_status pwf_forward(const pwf_problem* problems, int32_t n, const void* const* psi, float* const* f_out,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!psi || !f_out) return PWF_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!psi[i] || !f_out[i]) return PWF_ERR_ARG;
+  Layout L;
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Batch B = group(problems, n);
+  std::vector<Inst> desc(n);
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    I.W = (float2*)(ws + L.W[i]);
+    I.psi_src = (const float2*)psi[i];
+    I.f_out = f_out[i];
+    I.loss_partial = (double*)(ws + L.part[i]);
+  }
+  PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  const Launcher K{*ctx, ws, L, B, st};
+  PWF_TRY(K.row(pwf::ROW_START));
+  PWF_TRY(K.col(pwf::COL_CHIRP1));
+  PWF_TRY(K.row(pwf::ROW_MUL_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP2));
+  PWF_TRY(K.row(pwf::ROW_INTENSITY));
+  PWF_TRY(K.col(pwf::COL_BLUR));
+  PWF_TRY(K.row(pwf::ROW_FORWARD_OUT));
+  return PWF_OK;
+}
+
+pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
+                        void* const* g_out, void* const* d_out, double* loss_out, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!psi || !y) return PWF_ERR_ARG;
+  bool want_d = false;
+  for (int i = 0; i < n; ++i) {
+    if (!psi[i] || !y[i]) return PWF_ERR_ARG;
+    if (d_out && d_out[i]) want_d = true;
+  }
+  Layout L;
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Batch B = group(problems, n);
+  std::vector<Inst> desc(n);
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    I.W = (float2*)(ws + L.W[i]);
+    I.v = (float2*)(ws + L.v[i]);
+    I.psi = (float2*)psi[i];
+    I.psi_src = (const float2*)psi[i];
+    I.psi_hat = (float2*)(ws + L.psi_hat[i]);
+    I.y_hat = (float2*)(ws + L.y_hat[i]);
+    I.y = y[i];
+    I.g_out = g_out ? (float2*)g_out[i] : nullptr;
+    I.out = d_out ? (float2*)d_out[i] : nullptr;
+    I.loss_partial = (double*)(ws + L.part[i]);
+    I.loss_dst = loss_out ? loss_out + i : nullptr;
+  }
+  PWF_HIP(pwf::launch_fill_zero(ws + L.status, 16, st));
+  PWF_TRY(launch_maxt2(problems, n, B, desc, ws, L, st));
+  PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  const Launcher K{*ctx, ws, L, B, st};
+  if (want_d) {
+    // spectrum of psi for the regulariser (psi is not copied: I.psi == psi_src)
+    PWF_TRY(K.row(pwf::ROW_CPLX_FFT));
+    PWF_TRY(K.col(pwf::COL_SPEC_PSIHAT));
+  }
+  PWF_TRY(K.row(pwf::ROW_REAL_FFT));
+  PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
+  PWF_TRY(K.row(pwf::ROW_START));
+  PWF_TRY(K.col(pwf::COL_CHIRP1));
+  PWF_TRY(K.row(pwf::ROW_MUL_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP2));
+  PWF_TRY(K.row(pwf::ROW_INTENSITY));
+  PWF_TRY(K.col(pwf::COL_BLUR_LOSS));
+  PWF_TRY(K.row(pwf::ROW_BACKBLUR));
+  PWF_TRY(K.col(pwf::COL_CHIRP2_CONJ));
+  PWF_TRY(K.row(pwf::ROW_MUL_CONJ_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP1_CONJ));
+  PWF_TRY(K.row(pwf::ROW_GRAD));
+  if (want_d) {
+    PWF_TRY(K.col(pwf::COL_DIRECTION));
+    PWF_TRY(K.row(pwf::ROW_IFFT_OUT));
+  }
+  return PWF_OK;
+}
+
+pwf_status pwf_state_init(const pwf_problem* problems, int32_t n, pwf_state* states, const void* const* psi0,
+                          const float* const* y, void* workspace, size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!states || !y) return PWF_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!y[i] || !states[i].psi || !states[i].psi_hat || !states[i].z_hat || !states[i].y_hat) return PWF_ERR_ARG;
+  Layout L;
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Batch B = group(problems, n);
+  std::vector<Inst> desc(n);
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    I.W = (float2*)(ws + L.W[i]);
+    I.y = y[i];
+    I.y_hat = (float2*)states[i].y_hat;
+    I.psi_src = psi0 ? (const float2*)psi0[i] : nullptr;
+    I.psi = (float2*)states[i].psi;
+    I.psi_hat = (float2*)states[i].psi_hat;
+    I.z_hat = (float2*)states[i].z_hat;
+    I.loss_partial = (double*)(ws + L.part[i]);
+  }
+  PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  const Launcher K{*ctx, ws, L, B, st};
+  PWF_TRY(K.row(pwf::ROW_REAL_FFT));
+  PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
+  PWF_TRY(K.row(pwf::ROW_CPLX_FFT));
+  PWF_TRY(K.col(pwf::COL_SPEC_PSIHAT));
+  for (int i = 0; i < n; ++i) states[i].k = 0;
+  return PWF_OK;
+}
+
+pwf_status pwf_step(const pwf_problem* problems, int32_t n, pwf_state* states, double* loss_out, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!states) return PWF_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!states[i].psi || !states[i].psi_hat || !states[i].z_hat || !states[i].y_hat) return PWF_ERR_ARG;
+    if (states[i].k < 0 || states[i].k >= kBetaCap) return PWF_ERR_ARG;
+  }
+  Layout L;
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Batch B = group(problems, n);
+  std::vector<Inst> desc(n);
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    I.k0 = states[i].k;
+    I.W = (float2*)(ws + L.W[i]);
+    I.v = (float2*)(ws + L.v[i]);
+    I.psi = (float2*)states[i].psi;
+    I.psi_src = (const float2*)states[i].psi;
+    I.psi_hat = (float2*)states[i].psi_hat;
+    I.z_hat = (float2*)states[i].z_hat;
+    I.y_hat = (float2*)states[i].y_hat;
+    I.out = (float2*)states[i].psi;
+    I.loss_partial = (double*)(ws + L.part[i]);
+    I.loss_dst = loss_out ? loss_out + i : nullptr;
+  }
+  PWF_HIP(pwf::launch_fill_zero(ws + L.status, 16, st));
+  PWF_TRY(launch_maxt2(problems, n, B, desc, ws, L, st));
+  PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  const Launcher K{*ctx, ws, L, B, st};
+  PWF_TRY(K.row(pwf::ROW_START));
+  PWF_TRY(K.col(pwf::COL_CHIRP1));
+  PWF_TRY(K.row(pwf::ROW_MUL_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP2));
+  PWF_TRY(K.row(pwf::ROW_INTENSITY));
+  PWF_TRY(K.col(pwf::COL_BLUR_LOSS));
+  PWF_TRY(K.row(pwf::ROW_BACKBLUR));
+  PWF_TRY(K.col(pwf::COL_CHIRP2_CONJ));
+  PWF_TRY(K.row(pwf::ROW_MUL_CONJ_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP1_CONJ));
+  PWF_TRY(K.row(pwf::ROW_GRAD));
+  PWF_TRY(K.col(pwf::COL_NESTEROV));
+  PWF_TRY(K.row(pwf::ROW_IFFT_OUT));
+  for (int i = 0; i < n; ++i) states[i].k += 1;
+  return PWF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The solve sequence after the descriptor upload: setup, iters x 12 sweeps,
+// final inverse pass into psi_out.
+pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, std::vector<Inst>& desc, int iters) {
+  (void)probs;
+  (void)n;
+  (void)desc;
+  // clear the status word, and W, psi_hat and z_hat of every instance (contiguous regions)
+  PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.status, 16, K.st));
+  PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.W[0], K.L.v[0] - K.L.W[0], K.st));
+  PWF_TRY(K.row(pwf::ROW_REAL_FFT));
+  PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
+  for (int k = 0; k < iters; ++k) {
+    PWF_TRY(K.row(pwf::ROW_PSI_UPDATE, k));
+    PWF_TRY(K.col(pwf::COL_CHIRP1, k));
+    PWF_TRY(K.row(pwf::ROW_MUL_T, k));
+    PWF_TRY(K.col(pwf::COL_CHIRP2, k));
+    PWF_TRY(K.row(pwf::ROW_INTENSITY, k));
+    PWF_TRY(K.col(pwf::COL_BLUR_LOSS, k));
+    PWF_TRY(K.row(pwf::ROW_BACKBLUR, k));
+    PWF_TRY(K.col(pwf::COL_CHIRP2_CONJ, k));
+    PWF_TRY(K.row(pwf::ROW_MUL_CONJ_T, k));
+    PWF_TRY(K.col(pwf::COL_CHIRP1_CONJ, k));
+    PWF_TRY(K.row(pwf::ROW_GRAD, k));
+    PWF_TRY(K.col(pwf::COL_NESTEROV, k));
+  }
+  PWF_TRY(K.row(pwf::ROW_IFFT_OUT, iters));
+  return PWF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const* y, void* const* psi_out,
+                     int32_t iters, double corr_tol, double* loss_hist, int32_t* iters_done, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!y || !psi_out || iters < 0 || iters > kBetaCap || corr_tol > 0 || std::isnan(corr_tol)) return PWF_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!y[i] || !psi_out[i]) return PWF_ERR_ARG;
+  Layout L;
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Batch B = group(problems, n);
+  std::vector<Inst> desc(n);
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    I.W = (float2*)(ws + L.W[i]);
+    I.v = (float2*)(ws + L.v[i]);
+    I.psi = (float2*)(ws + L.psi[i]);
+    I.psi_hat = (float2*)(ws + L.psi_hat[i]);
+    I.z_hat = (float2*)(ws + L.z_hat[i]);
+    I.y_hat = (float2*)(ws + L.y_hat[i]);
+    I.y = y[i];
+    I.out = (float2*)psi_out[i];
+    I.loss_partial = (double*)(ws + L.part[i]);
+    I.loss_dst = loss_hist ? loss_hist + (size_t)i * iters : nullptr;
+  }
+  // maxt2 slots depend only on the diffuser pointers; fill desc before upload
+  {
+    std::vector<const void*> seen;
+    for (int s = 0; s < n; ++s) {
+      const pwf_problem& p = problems[B.order[s]];
+      int slot = -1;
+      for (size_t j = 0; j < seen.size(); ++j)
+        if (seen[j] == p.diffuser) slot = (int)j;
+      if (slot < 0) {
+        slot = (int)seen.size();
+        seen.push_back(p.diffuser);
+      }
+      desc[s].maxt2 = (const float*)(ws + L.maxt2) + slot;
+    }
+  }
+  PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  if (iters_done)
+    for (int i = 0; i < n; ++i) iters_done[i] = iters;
+
+  auto enqueue = [&](hipStream_t s) -> pwf_status {
+    const Launcher K{*ctx, ws, L, B, s};
+    std::vector<Inst> tmp = desc;
+    PWF_TRY(launch_maxt2(problems, n, B, tmp, ws, L, s));
+    return solve_sequence(K, problems, n, desc, iters);
+  };
+
+  if (!g_graph_mode) return enqueue(st);
+
+  GraphKey key{workspace, n, iters, {}};
+  for (int s = 0; s < n; ++s) {
+    const pwf_problem& p = problems[B.order[s]];
+    key.dims.push_back(p.geom.nx);
+    key.dims.push_back(p.geom.ny);
+    key.dims.push_back((int)(((uintptr_t)p.diffuser) & 0x7fffffff));
+    key.dims.push_back((int)(((uintptr_t)p.diffuser) >> 31));
+  }
+  hipGraphExec_t exec = nullptr;
+  auto it = ctx->graphs.find(key);
+  if (it != ctx->graphs.end()) {
+    exec = it->second;
+  } else {
+    hipGraph_t graph = nullptr;
+    PWF_HIP(hipStreamBeginCapture(ctx->side, hipStreamCaptureModeThreadLocal));
+    const pwf_status cs = enqueue(ctx->side);
+    const hipError_t ee = hipStreamEndCapture(ctx->side, &graph);
+    if (cs != PWF_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return cs;
+    }
+    PWF_HIP(ee);
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    PWF_HIP(ie);
+    if (ctx->graphs.size() >= 8) {
+      hipGraphExecDestroy(ctx->graphs.begin()->second);
+      ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs[key] = exec;
+  }
+  PWF_HIP(hipEventRecord(ctx->ev_in, st));
+  PWF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_in, 0));
+  PWF_HIP(hipGraphLaunch(exec, ctx->side));
+  PWF_HIP(hipEventRecord(ctx->ev_out, ctx->side));
+  PWF_HIP(hipStreamWaitEvent(st, ctx->ev_out, 0));
+  return PWF_OK;
+}
+
+pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi_out, int32_t iters,
+                           double* loss_hist, void* workspace, size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problem, 1));
+  if (!y || !psi_out || iters < 0 || iters > kBetaCap) return PWF_ERR_ARG;
+  Layout L;
+  PWF_TRY(check_ws(problem, 1, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const pwf_problem& p = *problem;
+  const int nx = p.geom.nx, ny = p.geom.ny;
+  const size_t m = (size_t)nx * ny;
+  Inst I = base_inst(p);
+  I.y = y;
+  I.maxt2 = (const float*)(ws + L.maxt2);
+  Inst* dI = (Inst*)(ws + L.desc);
+  PWF_TRY(upload(*ctx, &I, sizeof(Inst), dI, st));
+  float2* psi = (float2*)psi_out;
+  float2* Z = (float2*)(ws + L.W[0]);
+  float2* X = (float2*)(ws + L.psi_hat[0]);
+  float2* V = (float2*)(ws + L.z_hat[0]);
+  float2* A = (float2*)(ws + L.v[0]);
+  float2* Bf = (float2*)(ws + L.psi[0]);
+  float2* Cc = (float2*)(ws + L.y_hat[0]);
+  float2* G = (float2*)(ws + L.extra0[0]);
+  double* part = (double*)(ws + L.part[0]);
+  int32_t* status = (int32_t*)(ws + L.status);
+  const float2* twx = ctx->tw[size_index(nx)];
+  const float2* twy = ctx->tw[size_index(ny)];
+
+  PWF_HIP(pwf::launch_fill_zero(status, 16, st));
+  PWF_HIP(pwf::launch_maxabs2((const float2*)p.diffuser, m, (float*)(ws + L.maxt2_part), (float*)(ws + L.maxt2), st));
+  PWF_HIP(pwf::launch_fill_zero(psi, m * sizeof(float2), st));
+  PWF_HIP(pwf::launch_fill_zero(Z, m * sizeof(float2), st));
+
+  // Filter (Algorithm S2): F^-1{ F{src} W_k } -> dst, one kernel per step
+  auto filter = [&](const float2* src, float2* dst, int window) -> pwf_status {
+    PWF_HIP(pwf::launch_plain_rows(nx, -1, src, dst, ny, twx, st));
+    PWF_HIP(pwf::launch_plain_cols(ny, -1, dst, nx, twy, st));
+    PWF_HIP(pwf::launch_plain_window(dst, dI, window, m, st));
+    PWF_HIP(pwf::launch_plain_cols(ny, 1, dst, nx, twy, st));
+    PWF_HIP(pwf::launch_plain_rows(nx, 1, dst, dst, ny, twx, st));
+    return PWF_OK;
+  };
+  auto ew = [&](int op, const float2* a, const float2* b, float2* c, float2* out, int iter) -> pwf_status {
+    PWF_HIP(pwf::launch_plain_elementwise(op, m, a, b, c, out, dI, ctx->beta, iter, part, st));
+    return PWF_OK;
+  };
+  for (int k = 0; k < iters; ++k) {
+    PWF_TRY(ew(pwf::PLAIN_EXP, psi, nullptr, nullptr, X, k));         // x = exp(psi)
+    PWF_TRY(filter(X, V, pwf::PLAIN_W_Q1));                           // sample -> diffuser
+    PWF_TRY(ew(pwf::PLAIN_MUL_T, V, nullptr, nullptr, V, k));         // t v
+    PWF_TRY(filter(V, V, pwf::PLAIN_W_Q2));                           // diffuser -> detector
+    PWF_TRY(ew(pwf::PLAIN_ABS2, V, nullptr, nullptr, A, k));          // |v|^2
+    PWF_TRY(filter(A, A, pwf::PLAIN_W_IOTF));                         // f
+    PWF_TRY(ew(pwf::PLAIN_NEG_ERR, A, nullptr, nullptr, A, k));       // -e and the loss
+    PWF_HIP(pwf::launch_plain_loss_final(part, pwf::plain_elementwise_blocks(),
+                                         loss_hist, k, status, st));
+    PWF_TRY(filter(A, A, pwf::PLAIN_W_IOTF));                         // Filter(-e, IOTF)
+    PWF_TRY(ew(pwf::PLAIN_MUL, V, A, nullptr, A, k));                 // v h
+    PWF_TRY(filter(A, A, pwf::PLAIN_W_Q2C));                          // propagate -L2
+    PWF_TRY(ew(pwf::PLAIN_MUL_CONJ_T, A, nullptr, nullptr, A, k));    // t* (.)
+    PWF_TRY(filter(A, A, pwf::PLAIN_W_Q1C));                          // propagate -L1
+    PWF_TRY(ew(pwf::PLAIN_GRAD, A, X, nullptr, G, k));                // g = x* (.) / max|t|^2
+    PWF_TRY(ew(pwf::PLAIN_IMAG, G, nullptr, nullptr, Bf, k));         // Im g
+    PWF_TRY(filter(Bf, Bf, pwf::PLAIN_W_PINV));                       // preconditioner
+    PWF_TRY(filter(psi, Cc, pwf::PLAIN_W_GAMMA2));                    // Filter(psi, Gamma^2)
+    PWF_TRY(ew(pwf::PLAIN_DIRECTION, G, Bf, Cc, A, k));               // d
+    PWF_TRY(ew(pwf::PLAIN_NESTEROV, psi, A, Z, psi, k));              // z, tau, psi
+  }
+  return PWF_OK;
+}
+
+pwf_status pwf_sync_status(void* workspace, void* stream) {
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return PWF_ERR_WORKSPACE;
+  PWF_HIP(hipStreamSynchronize((hipStream_t)stream));
+  int32_t flag = 0;
+  PWF_HIP(hipMemcpy(&flag, workspace, sizeof(flag), hipMemcpyDeviceToHost));
+  return (flag & 1) ? PWF_ERR_NONFINITE : PWF_OK;
+}
+
+void pwf_finalize(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (Context& c : g_ctx) {
+    if (!c.ready) continue;
+    for (auto& kv : c.graphs) hipGraphExecDestroy(kv.second);
+    c.graphs.clear();
+    for (float2*& t : c.tw) {
+      if (t) hipFree(t);
+      t = nullptr;
+    }
+    if (c.beta) hipFree(c.beta);
+    c.beta = nullptr;
+    for (int i = 0; i < Context::kSlots; ++i) {
+      if (c.stage_ev[i]) hipEventSynchronize(c.stage_ev[i]);
+      if (c.stage[i]) hipHostFree(c.stage[i]);
+      c.stage[i] = nullptr;
+      c.stage_bytes[i] = 0;
+      if (c.stage_ev[i]) hipEventDestroy(c.stage_ev[i]);
+      c.stage_ev[i] = nullptr;
+    }
+    if (c.ev_in) hipEventDestroy(c.ev_in);
+    if (c.ev_out) hipEventDestroy(c.ev_out);
+    if (c.side) hipStreamDestroy(c.side);
+    c = Context();
+  }
+}
+
+}  // extern "C"

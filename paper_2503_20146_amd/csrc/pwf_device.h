@@ -1,0 +1,136 @@
+// Per-instance descriptors, FFT configurations and the Fourier-domain windows
+// of the PWF hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pwf_fft.h"
+
+namespace pwf {
+
+// Per-instance descriptor, uploaded to device memory once per call.  Field
+// buffers are complex64 [ny][nx] unless noted.  Spectra (psi_hat, z_hat,
+// y_hat and the x-transformed work field W) store column kx at the paired
+// position s(kx) (see col_of_kx) so that kx and -kx are neighbours.
+struct Inst {
+  int32_t nx, ny;
+  int32_t k0;           // iterations already done (momentum table offset)
+  int32_t n_partials;   // number of loss partials (column tiles)
+  float2* W;            // work field between sweeps
+  float2* v;            // detector field v, saved by the forward for the gradient
+  float2* psi;          // real-space psi read by the gradient (x* = exp(psi)*)
+  const float2* psi_src;// real-space psi that a forward pass starts from
+  float2* psi_hat;      // spectrum of the extrapolated iterate psi
+  float2* z_hat;        // spectrum of the gradient-step iterate z
+  float2* y_hat;        // spectrum of the measured speckle
+  const float* y;       // measured speckle (real space, float32)
+  const float2* t;      // diffuser transmission
+  const float* maxt2;   // device scalar max_r |t_r|^2
+  float* f_out;         // forward-model output (float32), may be null
+  float2* g_out;        // Wirtinger derivative output, may be null
+  float2* out;          // real-space complex output of a final inverse pass
+  double* loss_partial; // one FP64 partial per column tile
+  double* loss_dst;     // loss destination (indexed by iteration), may be null
+  // Fourier-domain constants (frequencies f in cycles/pixel)
+  double chirp1_rev;    // L1 lambda / (2 p^2): revolutions per f^2 (paraxial part)
+  double chirp2_rev;    // L2 lambda / (2 p^2)
+  double s_coef;        // (lambda / p)^2: lambda^2 rho^2 = s_coef f^2
+  int32_t series;       // 1: evaluate 2/(1+sqrt(1-s)) by its power series
+  float iotf_cx, iotf_cy;  // IOTF = exp(-(cx fx^2 + cy fy^2)), c = 2 pi^2 sigma^2
+  float stf_cx, stf_cy;    // STF  = exp(-(cx fx^2 + cy fy^2)), c = 4 pi^2 gamma sigma^2
+  float pinv_scale;        // s_P; negative: preconditioner off
+  float alpha_c1, alpha_c2;// (Re a + Im a)/2, (Re a - Im a)/2
+  float eta;
+  float inv_m;             // 1/(nx ny)
+  double inv_m_d;
+};
+
+// Paired column order of x-spectra: kx = 0 -> 0, kx = n/2 -> 1,
+// 0 < kx < n/2 -> 2 kx, n/2 < kx < n -> 2 (n - kx) + 1.
+__device__ __forceinline__ int col_of_kx(int kx, int n) {
+  const int h = n >> 1;
+  if (kx == 0) return 0;
+  if (kx == h) return 1;
+  return kx < h ? 2 * kx : 2 * (n - kx) + 1;
+}
+__device__ __forceinline__ int kx_of_col(int s, int n) {
+  if (s == 0) return 0;
+  if (s == 1) return n >> 1;
+  return (s & 1) ? n - (s >> 1) : (s >> 1);
+}
+__device__ __forceinline__ int mirror_col(int s) { return s <= 1 ? s : (s ^ 1); }
+
+// Signed frequency in cycles/pixel of DFT bin k of an n-point axis (exact).
+__device__ __forceinline__ float freq_of(int k, int n) {
+  return (float)(k < (n >> 1) ? k : k - n) / (float)n;
+}
+
+// Transfer function Q = exp(i theta) of FreePropagation over L, carrier dropped:
+// theta / 2 pi = -(L lambda / 2 p^2) f^2 * 2 / (1 + sqrt(1 - s)), s = (lambda/p)^2 f^2.
+// The argument is formed and reduced modulo one revolution in FP64; the
+// reduced angle goes to an FP32 sincos.  conj selects the backward direction.
+__device__ __forceinline__ float2 transfer(double chirp_rev, double s_coef, int series, float fx, float fy,
+                                           bool conj) {
+  const double r2 = (double)fx * (double)fx + (double)fy * (double)fy;
+  const double s = s_coef * r2;
+  double c;
+  if (series) {
+    // 2/(1+sqrt(1-s)) = sum_n Catalan(n) (s/4)^n; exact to FP64 for s < 1e-4
+    c = 1.0 + s * (0.25 + s * (0.125 + s * (0.078125 + s * 0.0546875)));
+  } else {
+    if (s >= 1.0) return make_float2(0.f, 0.f);
+    c = 2.0 / (1.0 + sqrt(1.0 - s));
+  }
+  double rev = -chirp_rev * r2 * c;
+  rev -= rint(rev);
+  const float th = (float)(rev * 6.283185307179586476925);
+  float sn, cs;
+  sincosf(th, &sn, &cs);
+  return make_float2(cs, conj ? -sn : sn);
+}
+
+__device__ __forceinline__ float iotf_of(const Inst& I, float fx, float fy) {
+  return expf(-(I.iotf_cx * fx * fx + I.iotf_cy * fy * fy));
+}
+__device__ __forceinline__ float gamma2_of(const Inst& I, float fx, float fy) {
+  return -expm1f(-(I.stf_cx * fx * fx + I.stf_cy * fy * fy));
+}
+__device__ __forceinline__ float pinv_of(const Inst& I, float fx, float fy) {
+  const float r2 = fx * fx + fy * fy;
+  if (I.pinv_scale < 0.f) return 1.f;
+  return r2 > 0.f ? I.pinv_scale / r2 : 0.f;
+}
+
+// ------------------------------------------------------------------ FFT configurations
+
+// Row sweeps: T lanes per row, RW rows per workgroup.
+template <int N> struct RowCfg;
+template <> struct RowCfg<128>  { using Plan = FftPlan<128, 16, 8>;     static constexpr int T = 8,  RW = 32; };
+template <> struct RowCfg<256>  { using Plan = FftPlan<256, 16, 16>;    static constexpr int T = 16, RW = 16; };
+template <> struct RowCfg<512>  { using Plan = FftPlan<512, 32, 16>;    static constexpr int T = 16, RW = 16; };
+template <> struct RowCfg<1024> { using Plan = FftPlan<1024, 32, 32>;   static constexpr int T = 32, RW = 8; };
+template <> struct RowCfg<2048> { using Plan = FftPlan<2048, 32, 8, 8>; static constexpr int T = 64, RW = 4; };
+
+// Column sweeps: T lanes per column, W adjacent columns per workgroup (lane
+// index = t * W + w, so the W columns of one row are one coalesced segment).
+template <int N> struct ColCfg;
+template <> struct ColCfg<128>  { using Plan = FftPlan<128, 16, 8>;     static constexpr int T = 8,  W = 32; };
+template <> struct ColCfg<256>  { using Plan = FftPlan<256, 16, 16>;    static constexpr int T = 16, W = 16; };
+template <> struct ColCfg<512>  { using Plan = FftPlan<512, 32, 16>;    static constexpr int T = 16, W = 16; };
+template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 32, 32>;   static constexpr int T = 32, W = 16; };
+template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 32, 8, 8>; static constexpr int T = 64, W = 8; };
+
+// Arguments common to every sweep launch.
+struct Sweep {
+  const Inst* inst;       // device array of descriptors
+  int32_t blocks_per_inst;
+  int32_t iter;           // iteration index within this call
+  const double* beta;     // momentum table (Algorithm S1), indexed by k0 + iter
+  const float2* tw_row;   // twiddles of the row plan (forward, then reversed plan)
+  const float2* tw_col;   // twiddles of the column plan
+  int32_t* status;        // bit 0: non-finite loss seen
+};
+
+}  // namespace pwf

@@ -1,0 +1,309 @@
+// Device-side FFT engine for gfx950: register-resident radix-R butterflies
+// with compile-time twiddles, joined by Stockham auto-sort passes through LDS.
+//
+// A transform of length N is shared by T lanes; each lane holds E = N / T
+// complex values in registers.  Pass p (radix R, stride L = product of the
+// earlier radices, m = N / R) computes, for butterfly j in [0, m):
+//     k = j mod L,  a_q = x[j + q m] * w_{L R}^{q k},  b_r = sum_q a_q w_R^{q r},
+//     y[(j / L) L R + k + r L] = b_r,
+// with w_n = exp(-2 pi i / n) forward and its conjugate inverse.  Lane t owns
+// butterflies j = t + T c.  The first pass reads a_q from registers that the
+// caller loaded at positions t + T c + q m (coalesced along t); the last pass
+// (L = m) leaves b_r in registers at frequency t + T c + r m, which is also
+// the input layout of an inverse transform whose first radix is the same.
+// Between passes the data goes through LDS.  Inverse transforms are
+// unnormalised.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace pwf {
+
+// ------------------------------------------------------------------ helpers
+
+template <int I, int END, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < END) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, END>(static_cast<F&&>(f));
+  }
+}
+
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
+
+__host__ __device__ constexpr int bitrev(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// cos and sin of 2 pi num / den evaluated at compile time (Taylor series after
+// an exact reduction to the first octant).
+__host__ __device__ constexpr double cx_taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int i = 1; i < 14; ++i) {
+    term *= -x * x / ((2 * i) * (2 * i + 1));
+    sum += term;
+  }
+  return sum;
+}
+__host__ __device__ constexpr double cx_taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int i = 1; i < 14; ++i) {
+    term *= -x * x / ((2 * i - 1) * (2 * i));
+    sum += term;
+  }
+  return sum;
+}
+// angle = 2 pi num / den, returns cos (which=0) or sin (which=1)
+__host__ __device__ constexpr double cx_trig(long num, long den, int which) {
+  num %= den;
+  if (num < 0) num += den;
+  // reduce to [0, den/8] using exact symmetries: work with octant index
+  long n8 = num * 8;
+  int oct = (int)(n8 / den);        // 0..7
+  long rem = n8 - (long)oct * den;  // angle within octant = 2 pi rem / (8 den)
+  const double quarter_pi = 0.78539816339744830961566084581987572;
+  double a = quarter_pi * (double)rem / (double)den;  // [0, pi/4)
+  double b = quarter_pi - a;                           // (0, pi/4]
+  double c = 0, s = 0;
+  switch (oct) {
+    case 0: c = cx_taylor_cos(a); s = cx_taylor_sin(a); break;
+    case 1: c = cx_taylor_sin(b); s = cx_taylor_cos(b); break;
+    case 2: c = -cx_taylor_sin(a); s = cx_taylor_cos(a); break;
+    case 3: c = -cx_taylor_cos(b); s = cx_taylor_sin(b); break;
+    case 4: c = -cx_taylor_cos(a); s = -cx_taylor_sin(a); break;
+    case 5: c = -cx_taylor_sin(b); s = -cx_taylor_cos(b); break;
+    case 6: c = cx_taylor_sin(a); s = -cx_taylor_cos(a); break;
+    default: c = cx_taylor_cos(b); s = -cx_taylor_sin(b); break;
+  }
+  return which == 0 ? c : s;
+}
+
+// ------------------------------------------------------------------ complex helpers
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// Multiply by w_n^k (DIR = -1 forward, +1 inverse) with n, k compile-time.
+template <int DIR, int K, int NN>
+__device__ __forceinline__ float2 twiddle_const(float2 a) {
+  constexpr int k = ((K % NN) + NN) % NN;
+  if constexpr (k == 0) {
+    return a;
+  } else if constexpr (4 * k == NN) {  // w = -i (fwd) / +i (inv)
+    return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+  } else if constexpr (2 * k == NN) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (4 * k == 3 * NN) {  // w = +i (fwd) / -i (inv)
+    return DIR < 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+  } else {
+    constexpr float c = (float)cx_trig(k, NN, 0);
+    constexpr float s = (float)(DIR * cx_trig(k, NN, 1));  // exp(DIR i 2 pi k / n)
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// In-register radix-R DFT (decimation in frequency).  On entry a[OFF + q] holds
+// input q; on exit a[OFF + bitrev(r)] holds output r.
+template <int R, int DIR, int OFF, int E>
+__device__ __forceinline__ void dft_reg(float2 (&a)[E]) {
+  constexpr int LOGR = ilog2(R);
+  static_for<0, LOGR>([&](auto st) {
+    constexpr int half = R >> (decltype(st)::value + 1);
+    static_for<0, R / (2 * half)>([&](auto bb) {
+      constexpr int blk = decltype(bb)::value * 2 * half;
+      static_for<0, half>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        float2 x = a[OFF + blk + i];
+        float2 y = a[OFF + blk + i + half];
+        a[OFF + blk + i] = cadd(x, y);
+        a[OFF + blk + i + half] = twiddle_const<DIR, i, 2 * half>(csub(x, y));
+      });
+    });
+  });
+}
+
+// ------------------------------------------------------------------ Stockham passes
+
+// LDS index with one pad element every 32 (breaks power-of-two bank strides).
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lds_len(int n) { return n + (n >> 5); }
+
+// Where a transform's elements live in LDS: element i -> base[(pad(i)) * stride].
+struct LdsView {
+  float2* base;
+  int stride;
+  __device__ __forceinline__ float2& at(int i) const { return base[lds_pad(i) * stride]; }
+};
+
+// Twiddles of pass p of an N-point transform: table[q * L + k] = w_{L R}^{q k}
+// (forward sign; the inverse uses the conjugate).  Tables for all passes of a
+// plan are concatenated; offsets are compile-time.
+template <int N, int... RS>
+struct FftPlan {
+  static constexpr int NPASS = sizeof...(RS);
+  static constexpr int radix[NPASS] = {RS...};
+  static constexpr int stride_before(int p) {
+    int l = 1;
+    for (int i = 0; i < p; ++i) l *= radix[i];
+    return l;
+  }
+  static constexpr int tw_offset(int p) {
+    int off = 0;
+    for (int i = 1; i < p; ++i) off += stride_before(i) * radix[i];
+    return off;
+  }
+  static constexpr int tw_total() { return tw_offset(NPASS); }
+  static constexpr bool valid() {
+    int prod = 1;
+    for (int i = 0; i < NPASS; ++i) prod *= radix[i];
+    return prod == N;
+  }
+};
+
+// One pass over registers.  v holds B = E/R butterflies' inputs at v[c*R + q].
+// Applies the inter-pass twiddle and the radix-R DFT; leaves outputs at
+// v[c*R + bitrev(r)].
+template <class Plan, int P, int T, int DIR, int E>
+__device__ __forceinline__ void pass_compute(float2 (&v)[E], int t, const float2* __restrict__ tw) {
+  constexpr int N = E * T;
+  constexpr int R = Plan::radix[P];
+  constexpr int L = Plan::stride_before(P);
+  constexpr int B = E / R;
+  static_assert(B * R == E, "radix must divide elements per lane");
+  static_assert((N / R) % T == 0, "lanes must divide butterflies");
+  static_for<0, B>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    if constexpr (L > 1) {
+      const int j = t + T * c;
+      const int k = j & (L - 1);
+      const float2* twp = tw + Plan::tw_offset(P) + k;
+      static_for<1, R>([&](auto qq) {
+        constexpr int q = decltype(qq)::value;
+        float2 w = twp[q * L];
+        if constexpr (DIR > 0) w.y = -w.y;
+        v[c * R + q] = cmul(v[c * R + q], w);
+      });
+    }
+    dft_reg<R, DIR, c * R>(v);
+  });
+}
+
+// Write pass-P outputs (bit-reversed in registers) to LDS at Stockham positions.
+template <class Plan, int P, int T, int E>
+__device__ __forceinline__ void pass_store_lds(const float2 (&v)[E], int t, LdsView lds) {
+  constexpr int R = Plan::radix[P];
+  constexpr int L = Plan::stride_before(P);
+  constexpr int B = E / R;
+  constexpr int LOGR = ilog2(R);
+  static_for<0, B>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    const int j = t + T * c;
+    const int k = j & (L - 1);
+    const int base = (j / L) * L * R + k;
+    static_for<0, R>([&](auto rr) {
+      constexpr int r = decltype(rr)::value;
+      lds.at(base + r * L) = v[c * R + bitrev(r, LOGR)];
+    });
+  });
+}
+
+// Read pass-P inputs from LDS: v[c*R + q] = x[j + q m].
+template <class Plan, int P, int T, int E>
+__device__ __forceinline__ void pass_load_lds(float2 (&v)[E], int t, LdsView lds) {
+  constexpr int N = E * T;
+  constexpr int R = Plan::radix[P];
+  constexpr int M = N / R;
+  constexpr int B = E / R;
+  static_for<0, B>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    const int j = t + T * c;
+    static_for<0, R>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
+      v[c * R + q] = lds.at(j + q * M);
+    });
+  });
+}
+
+// Put the last pass's bit-reversed outputs back in natural register order so
+// that v[c*R + r] holds frequency t + T c + r m.
+template <int R, int E>
+__device__ __forceinline__ void unscramble(float2 (&v)[E]) {
+  constexpr int LOGR = ilog2(R);
+  constexpr int B = E / R;
+  float2 tmp[R];
+  static_for<0, B>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    static_for<0, R>([&](auto rr) { tmp[decltype(rr)::value] = v[c * R + decltype(rr)::value]; });
+    static_for<0, R>([&](auto rr) {
+      constexpr int r = decltype(rr)::value;
+      v[c * R + r] = tmp[bitrev(r, LOGR)];
+    });
+  });
+}
+
+// Forward transform: registers in "first-radix layout" (v[c*R0 + q] = x[t + T c
+// + q N/R0]) -> registers in "last-radix layout" (v[c*RL + r] = X[t + T c + r
+// N/RL]).  The LDS region must be free on entry; it is free again on exit
+// (a trailing barrier is issued only between passes).
+template <class Plan, int T, int E>
+__device__ __forceinline__ void fft_forward(float2 (&v)[E], int t, const float2* __restrict__ tw, LdsView lds) {
+  static_for<0, Plan::NPASS>([&](auto pp) {
+    constexpr int P = decltype(pp)::value;
+    if constexpr (P > 0) {
+      pass_load_lds<Plan, P, T>(v, t, lds);
+      __syncthreads();
+    }
+    pass_compute<Plan, P, T, -1>(v, t, tw);
+    if constexpr (P + 1 < Plan::NPASS) {
+      pass_store_lds<Plan, P, T>(v, t, lds);
+      __syncthreads();
+    }
+  });
+  unscramble<Plan::radix[Plan::NPASS - 1]>(v);
+}
+
+// Inverse plan: the same radices in reverse order.
+template <class Plan>
+struct Reverse;
+template <int N, int... RS>
+struct Reverse<FftPlan<N, RS...>> {
+  template <int... IS>
+  static auto make(std::integer_sequence<int, IS...>)
+      -> FftPlan<N, FftPlan<N, RS...>::radix[sizeof...(RS) - 1 - IS]...>;
+  using type = decltype(make(std::make_integer_sequence<int, sizeof...(RS)>{}));
+};
+
+// Inverse transform: registers in last-radix layout of Plan -> registers in
+// first-radix layout of Plan.  `twr` is the twiddle table of the reversed plan.
+template <class Plan, int T, int E>
+__device__ __forceinline__ void fft_inverse(float2 (&v)[E], int t, const float2* __restrict__ twr, LdsView lds) {
+  using RP = typename Reverse<Plan>::type;
+  static_for<0, RP::NPASS>([&](auto pp) {
+    constexpr int P = decltype(pp)::value;
+    if constexpr (P > 0) {
+      pass_load_lds<RP, P, T>(v, t, lds);
+      __syncthreads();
+    }
+    pass_compute<RP, P, T, +1>(v, t, twr);
+    if constexpr (P + 1 < RP::NPASS) {
+      pass_store_lds<RP, P, T>(v, t, lds);
+      __syncthreads();
+    }
+  });
+  unscramble<RP::radix[RP::NPASS - 1]>(v);
+}
+
+}  // namespace pwf

@@ -1,0 +1,71 @@
+// Host-side entry points of the PWF kernels (C++ linkage, internal to libpwf).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "pwf_device.h"
+
+namespace pwf {
+
+enum RowOp {
+  ROW_PSI_UPDATE = 0,  // S0: psi = IFFT_x(W); store psi; x = exp(psi); FFT_x
+  ROW_START,           // start of a forward pass from real-space psi_src
+  ROW_MUL_T,           // S2
+  ROW_MUL_CONJ_T,      // S8
+  ROW_INTENSITY,       // S4
+  ROW_BACKBLUR,        // S6 (+ final loss sum)
+  ROW_GRAD,            // S10
+  ROW_FORWARD_OUT,     // f = Re IFFT_x(W)
+  ROW_REAL_FFT,        // W = FFT_x(y)
+  ROW_CPLX_FFT,        // W = FFT_x(psi_src) (psi_src null: zeros)
+  ROW_IFFT_OUT,        // out = IFFT_x(W)
+};
+
+enum ColOp {
+  COL_CHIRP1 = 0,      // S1
+  COL_CHIRP2,          // S3
+  COL_CHIRP2_CONJ,     // S7
+  COL_CHIRP1_CONJ,     // S9
+  COL_BLUR_LOSS,       // S5
+  COL_BLUR,            // forward-only source blur
+  COL_NESTEROV,        // S11
+  COL_DIRECTION,       // spectrum of the update direction d
+  COL_SPEC_YHAT,       // y_hat = FFT_y(W)
+  COL_SPEC_PSIHAT,     // psi_hat = FFT_y(W); z_hat = 0
+};
+
+enum PlainWindow { PLAIN_W_Q1 = 0, PLAIN_W_Q2, PLAIN_W_Q2C, PLAIN_W_Q1C, PLAIN_W_IOTF, PLAIN_W_PINV, PLAIN_W_GAMMA2 };
+
+enum PlainOp {
+  PLAIN_EXP = 0, PLAIN_MUL_T, PLAIN_MUL_CONJ_T, PLAIN_ABS2, PLAIN_REAL, PLAIN_NEG_ERR, PLAIN_MUL,
+  PLAIN_GRAD, PLAIN_IMAG, PLAIN_DIRECTION, PLAIN_NESTEROV
+};
+
+int row_rows_per_block(int n);
+int col_cols_per_block(int n);
+hipError_t launch_row(int nx, int op, int nblocks, const Sweep& S, hipStream_t st);
+hipError_t launch_col(int ny, int op, int nblocks, const Sweep& S, hipStream_t st);
+
+hipError_t launch_plain_rows(int nx, int dir, const float2* src, float2* dst, int ny, const float2* tw,
+                             hipStream_t st);
+hipError_t launch_plain_cols(int ny, int dir, float2* a, int nx, const float2* tw, hipStream_t st);
+hipError_t launch_plain_window(float2* a, const Inst* inst, int which, size_t m, hipStream_t st);
+int plain_elementwise_blocks();
+hipError_t launch_plain_elementwise(int op, size_t m, const float2* a, const float2* b, float2* c, float2* out,
+                                    const Inst* inst, const double* beta, int iter, double* partial,
+                                    hipStream_t st);
+hipError_t launch_plain_loss_final(const double* partial, int np, double* dst, int iter, int32_t* status,
+                                   hipStream_t st);
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+int maxabs2_blocks();
+hipError_t launch_maxabs2(const float2* t, size_t m, float* partial, float* out, hipStream_t st);
+
+// Number of float2 twiddles of the N-point plan (forward and reversed); fills
+// `out` when it is not null.  Returns -1 for unsupported N.
+int plan_twiddles(int n, float2* out);
+
+}  // namespace pwf

@@ -1,0 +1,274 @@
+// Element-wise, reduction and utility kernels of libpwf, and the host-side
+// dispatch of the per-side sweep instantiations.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "pwf_device.h"
+#include "pwf_kernels.h"
+
+namespace pwf {
+
+__device__ __forceinline__ float2 cexp_c(float2 p) {
+  float s, c;
+  sincosf(p.y, &s, &c);
+  const float a = expf(p.x);
+  return make_float2(a * c, a * s);
+}
+
+// Multiply a natural-order spectrum by one of the Algorithm S2 windows and 1/m.
+__global__ void plain_window(float2* __restrict__ a, const Inst* __restrict__ ip, int which) {
+  const Inst& I = *ip;
+  const int nx = I.nx, ny = I.ny;
+  const size_t m = (size_t)nx * ny;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    const int ky = (int)(i / nx), kx = (int)(i - (size_t)ky * nx);
+    const float fx = freq_of(kx, nx), fy = freq_of(ky, ny);
+    float2 val = a[i];
+    switch (which) {
+      case PLAIN_W_Q1: val = cmul(val, transfer(I.chirp1_rev, I.s_coef, I.series, fx, fy, false)); break;
+      case PLAIN_W_Q2: val = cmul(val, transfer(I.chirp2_rev, I.s_coef, I.series, fx, fy, false)); break;
+      case PLAIN_W_Q2C: val = cmul(val, transfer(I.chirp2_rev, I.s_coef, I.series, fx, fy, true)); break;
+      case PLAIN_W_Q1C: val = cmul(val, transfer(I.chirp1_rev, I.s_coef, I.series, fx, fy, true)); break;
+      case PLAIN_W_IOTF: val = cscale(val, iotf_of(I, fx, fy)); break;
+      case PLAIN_W_PINV: val = cscale(val, pinv_of(I, fx, fy)); break;
+      case PLAIN_W_GAMMA2: val = cscale(val, gamma2_of(I, fx, fy)); break;
+      default: break;
+    }
+    a[i] = cscale(val, I.inv_m);
+  }
+}
+
+// Element-wise steps of Algorithm S2 in natural layout.
+__global__ void plain_elementwise(int op, size_t m, const float2* __restrict__ a, const float2* __restrict__ b,
+                                  float2* __restrict__ c, float2* __restrict__ out,
+                                  const Inst* __restrict__ ip, const double* beta, int iter,
+                                  double* __restrict__ partial) {
+  const Inst& I = *ip;
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    switch (op) {
+      case PLAIN_EXP: out[i] = cexp_c(a[i]); break;
+      case PLAIN_MUL_T: out[i] = cmul(a[i], I.t[i]); break;
+      case PLAIN_MUL_CONJ_T: out[i] = cmulc(a[i], I.t[i]); break;
+      case PLAIN_ABS2: out[i] = make_float2(a[i].x * a[i].x + a[i].y * a[i].y, 0.f); break;
+      case PLAIN_REAL: out[i] = make_float2(a[i].x, 0.f); break;
+      case PLAIN_NEG_ERR: {  // -e = f - y, and the loss sum of e^2
+        const float e = I.y[i] - a[i].x;
+        acc += (double)e * (double)e;
+        out[i] = make_float2(-e, 0.f);
+        break;
+      }
+      case PLAIN_MUL: out[i] = cmul(a[i], make_float2(b[i].x, 0.f)); break;  // v * Re(h)
+      case PLAIN_GRAD: out[i] = cscale(cmulc(a[i], b[i]), 1.0f / *I.maxt2); break;  // b * conj(x) / max|t|^2
+      case PLAIN_IMAG: out[i] = make_float2(a[i].y, 0.f); break;
+      case PLAIN_DIRECTION: {  // d = Re g + i Re(Filter(Im g, P)) + Re a Re(rho) + i Im a Im(rho)
+        out[i] = make_float2(a[i].x + (I.alpha_c1 + I.alpha_c2) * c[i].x,
+                             b[i].x + (I.alpha_c1 - I.alpha_c2) * c[i].y);
+        break;
+      }
+      case PLAIN_NESTEROV: {  // a = psi (in/out via out), b = d, c = z (updated in place)
+        const float bf = (float)beta[iter];
+        const float2 zp = c[i];
+        const float2 z = make_float2(a[i].x - I.eta * b[i].x, a[i].y - I.eta * b[i].y);
+        c[i] = z;
+        out[i] = make_float2(z.x + bf * (z.x - zp.x), z.y + bf * (z.y - zp.y));
+        break;
+      }
+      default: break;
+    }
+  }
+  if (op == PLAIN_NEG_ERR) {
+    __shared__ double red[16];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) sum += red[i];
+      partial[blockIdx.x] = sum;
+    }
+  }
+}
+
+__global__ void plain_loss_final(const double* partial, int np, double* dst, int iter, int32_t* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < np; ++i) s += partial[i];
+    if (dst) dst[iter] = s;
+    if (!isfinite(s)) atomicOr(status, 1);
+  }
+}
+
+// ------------------------------------------------------------------ utilities
+
+__global__ void fill_zero_kernel(float4* __restrict__ p, size_t n16) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// max_r |t_r|^2 of one diffuser: per-block maxima, then the last pass reduces them.
+__global__ void maxabs2_partial(const float2* __restrict__ t, size_t m, float* __restrict__ partial) {
+  float mx = 0.f;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 a = t[i];
+    mx = fmaxf(mx, a.x * a.x + a.y * a.y);
+  }
+  __shared__ float red[16];
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) mx = fmaxf(mx, red[i]);
+    partial[blockIdx.x] = fmaxf(mx, red[0]);
+  }
+}
+
+__global__ void maxabs2_final(const float* __restrict__ partial, int np, float* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float mx = 0.f;
+    for (int i = 0; i < np; ++i) mx = fmaxf(mx, partial[i]);
+    *out = mx;
+  }
+}
+
+// ------------------------------------------------------------------ host dispatch
+
+#define PWF_DECLARE_SIDE(N)                                                                              \
+  template <int M> hipError_t launch_row_n(int op, int nblocks, const Sweep& S, hipStream_t st);        \
+  template <int M> hipError_t launch_col_n(int op, int nblocks, const Sweep& S, hipStream_t st);        \
+  template <int M> hipError_t plain_rows_n(int dir, const float2* src, float2* dst, int ny,             \
+                                           const float2* tw, hipStream_t st);                          \
+  template <int M> hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, hipStream_t st); \
+  template <int M> int plan_twiddles_n(float2* out);                                                  \
+  extern template hipError_t launch_row_n<N>(int, int, const Sweep&, hipStream_t);                     \
+  extern template hipError_t launch_col_n<N>(int, int, const Sweep&, hipStream_t);                     \
+  extern template hipError_t plain_rows_n<N>(int, const float2*, float2*, int, const float2*, hipStream_t); \
+  extern template hipError_t plain_cols_n<N>(int, float2*, int, const float2*, hipStream_t);           \
+  extern template int plan_twiddles_n<N>(float2*);
+PWF_DECLARE_SIDE(128)
+PWF_DECLARE_SIDE(256)
+PWF_DECLARE_SIDE(512)
+PWF_DECLARE_SIDE(1024)
+PWF_DECLARE_SIDE(2048)
+#undef PWF_DECLARE_SIDE
+
+int row_rows_per_block(int n) {
+  switch (n) {
+    case 128: return RowCfg<128>::RW;
+    case 256: return RowCfg<256>::RW;
+    case 512: return RowCfg<512>::RW;
+    case 1024: return RowCfg<1024>::RW;
+    case 2048: return RowCfg<2048>::RW;
+    default: return 0;
+  }
+}
+
+int col_cols_per_block(int n) {
+  switch (n) {
+    case 128: return ColCfg<128>::W;
+    case 256: return ColCfg<256>::W;
+    case 512: return ColCfg<512>::W;
+    case 1024: return ColCfg<1024>::W;
+    case 2048: return ColCfg<2048>::W;
+    default: return 0;
+  }
+}
+
+hipError_t launch_row(int nx, int op, int nblocks, const Sweep& S, hipStream_t st) {
+  switch (nx) {
+    case 128: return launch_row_n<128>(op, nblocks, S, st);
+    case 256: return launch_row_n<256>(op, nblocks, S, st);
+    case 512: return launch_row_n<512>(op, nblocks, S, st);
+    case 1024: return launch_row_n<1024>(op, nblocks, S, st);
+    case 2048: return launch_row_n<2048>(op, nblocks, S, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_col(int ny, int op, int nblocks, const Sweep& S, hipStream_t st) {
+  switch (ny) {
+    case 128: return launch_col_n<128>(op, nblocks, S, st);
+    case 256: return launch_col_n<256>(op, nblocks, S, st);
+    case 512: return launch_col_n<512>(op, nblocks, S, st);
+    case 1024: return launch_col_n<1024>(op, nblocks, S, st);
+    case 2048: return launch_col_n<2048>(op, nblocks, S, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_plain_rows(int nx, int dir, const float2* src, float2* dst, int ny, const float2* tw,
+                             hipStream_t st) {
+  switch (nx) {
+    case 128: return plain_rows_n<128>(dir, src, dst, ny, tw, st);
+    case 256: return plain_rows_n<256>(dir, src, dst, ny, tw, st);
+    case 512: return plain_rows_n<512>(dir, src, dst, ny, tw, st);
+    case 1024: return plain_rows_n<1024>(dir, src, dst, ny, tw, st);
+    case 2048: return plain_rows_n<2048>(dir, src, dst, ny, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_plain_cols(int ny, int dir, float2* a, int nx, const float2* tw, hipStream_t st) {
+  switch (ny) {
+    case 128: return plain_cols_n<128>(dir, a, nx, tw, st);
+    case 256: return plain_cols_n<256>(dir, a, nx, tw, st);
+    case 512: return plain_cols_n<512>(dir, a, nx, tw, st);
+    case 1024: return plain_cols_n<1024>(dir, a, nx, tw, st);
+    case 2048: return plain_cols_n<2048>(dir, a, nx, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_plain_window(float2* a, const Inst* inst, int which, size_t m, hipStream_t st) {
+  const int blocks = (int)((m + 255) / 256 < 4096 ? (m + 255) / 256 : 4096);
+  hipLaunchKernelGGL(plain_window, dim3(blocks), dim3(256), 0, st, a, inst, which);
+  return hipGetLastError();
+}
+
+int plain_elementwise_blocks() { return 1024; }
+
+hipError_t launch_plain_elementwise(int op, size_t m, const float2* a, const float2* b, float2* c, float2* out,
+                                    const Inst* inst, const double* beta, int iter, double* partial,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(plain_elementwise, dim3(plain_elementwise_blocks()), dim3(256), 0, st, op, m, a, b, c, out,
+                     inst, beta, iter, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_loss_final(const double* partial, int np, double* dst, int iter, int32_t* status,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(plain_loss_final, dim3(1), dim3(64), 0, st, partial, np, dst, iter, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  const size_t want = (n16 + 255) / 256;
+  const int blocks = (int)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, st, (float4*)p, n16);
+  return hipGetLastError();
+}
+
+int maxabs2_blocks() { return 256; }
+
+hipError_t launch_maxabs2(const float2* t, size_t m, float* partial, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(maxabs2_partial, dim3(maxabs2_blocks()), dim3(256), 0, st, t, m, partial);
+  hipLaunchKernelGGL(maxabs2_final, dim3(1), dim3(64), 0, st, partial, maxabs2_blocks(), out);
+  return hipGetLastError();
+}
+
+int plan_twiddles(int n, float2* out) {
+  switch (n) {
+    case 128: return plan_twiddles_n<128>(out);
+    case 256: return plan_twiddles_n<256>(out);
+    case 512: return plan_twiddles_n<512>(out);
+    case 1024: return plan_twiddles_n<1024>(out);
+    case 2048: return plan_twiddles_n<2048>(out);
+    default: return -1;
+  }
+}
+
+}  // namespace pwf

@@ -1,0 +1,47 @@
+"""Shared helpers of the GPU parity tests (inputs from ``synthetic``, expected values from ``oracle``)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+
+
+def device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_20146_amd import _lib
+    _lib.load()  # fails loudly when the HIP library is missing
+    return torch.device("cuda:0")
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def instance(workload=0, n=None, instance=None, sigma=None, geometry=None):
+    """(inputs, oracle problem, noisy y float32) for a single-projection instance."""
+    inp = S.instance_inputs(workload, n, instance, sigma)
+    geo = inp["geometry"] if geometry is None else geometry
+    prob = O.make_problem(inp["t"], geo)
+    f, _, _ = O.physical_model(inp["psi_true"], prob)
+    y = S.poisson_intensity(f, inp["seed_key"])
+    return inp, geo, prob, y
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def gpu_problem(geo, t, dev, **kw):
+    from paper_2503_20146_amd import problem_from_geometry
+    return problem_from_geometry(geo, to_dev(np.asarray(t, np.complex64), dev), **kw)

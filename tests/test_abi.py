@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI (no GPU work: every call here fails validation
+before anything is queued, or only queries sizes and strings)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pwf.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2503_20146_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libpwf.so not built")
+    return _lib.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pwf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = header_functions()
+    for required in ("pwf_forward", "pwf_gradient", "pwf_step", "pwf_solve", "pwf_workspace_size",
+                     "pwf_status_string", "pwf_solve_plain", "pwf_state_init"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header():
+    from paper_2503_20146_amd import _lib
+    assert set(_lib.SIGNATURES) == set(header_functions())
+
+
+def test_status_strings(lib):
+    from paper_2503_20146_amd import _lib
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = lib.pwf_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert lib.pwf_status_string(42).decode() == "unknown status"
+    assert lib.pwf_version() >= 10000
+    assert _lib.status_string(-3).startswith("geometry has evanescent")
+
+
+def _problem(nx=128, ny=128, **kw):
+    from paper_2503_20146_amd import _lib
+    p = _lib.pwf_problem()
+    p.geom = _lib.pwf_geometry(nx, ny, kw.get("pixel", 1e-6), kw.get("lam", 0.05e-9), kw.get("z1", 5e-3),
+                               kw.get("z2", 0.2))
+    p.source = _lib.pwf_source(kw.get("sx", 1.0), kw.get("sy", 1.0))
+    p.params = _lib.pwf_params(kw.get("eta", 0.5), 0.1, 0.01, kw.get("gamma", 1.0), kw.get("sp", 0.025), 1)
+    p.diffuser = kw.get("diffuser", 0x1000)
+    return p
+
+
+def test_workspace_size(lib):
+    from paper_2503_20146_amd import _lib
+    arr = (_lib.pwf_problem * 2)(_problem(), _problem(256, 512))
+    size = lib.pwf_workspace_size(arr, 2)
+    fields = 6 * (128 * 128 + 256 * 512) * 8 + 2 * 128 * 128 * 8
+    assert fields < size < fields + (1 << 20)
+    assert lib.pwf_workspace_size(arr, 0) == 0
+    bad = (_lib.pwf_problem * 1)(_problem(100, 128))
+    assert lib.pwf_workspace_size(bad, 1) == 0
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(nx=100), -2), (dict(ny=4096), -2), (dict(pixel=0.0), -1), (dict(lam=float("nan")), -1),
+    (dict(z1=-1e-3), -1), (dict(sx=-1.0), -1), (dict(eta=float("inf")), -1), (dict(sp=0.0), -1),
+    (dict(diffuser=0), -1), (dict(lam=2e-6, pixel=1e-6), -3),
+])
+def test_invalid_problems_rejected_before_any_gpu_work(lib, kw, expect):
+    from paper_2503_20146_amd import _lib
+    arr = (_lib.pwf_problem * 1)(_problem(**kw))
+    ptrs = (ctypes.c_void_p * 1)(0x2000)
+    ws = ctypes.c_void_p(0x100000)
+    assert lib.pwf_forward(arr, 1, ptrs, ptrs, ws, 1 << 40, None) == expect
+    assert lib.pwf_solve(arr, 1, ptrs, ptrs, 10, 0.0, None, None, ws, 1 << 40, None) == expect
+
+
+def test_bad_workspace_and_pointers(lib):
+    from paper_2503_20146_amd import _lib
+    arr = (_lib.pwf_problem * 1)(_problem())
+    ptrs = (ctypes.c_void_p * 1)(0x2000)
+    null = (ctypes.c_void_p * 1)(None)
+    size = lib.pwf_workspace_size(arr, 1)
+    assert lib.pwf_forward(arr, 1, ptrs, ptrs, ctypes.c_void_p(0x100001), size, None) == -4
+    assert lib.pwf_forward(arr, 1, ptrs, ptrs, ctypes.c_void_p(0x100000), size - 1, None) == -4
+    assert lib.pwf_forward(arr, 1, ptrs, ptrs, None, size, None) == -4
+    assert lib.pwf_forward(arr, 1, null, ptrs, ctypes.c_void_p(0x100000), size, None) == -1
+    assert lib.pwf_forward(None, 1, ptrs, ptrs, ctypes.c_void_p(0x100000), size, None) == -1
+    assert lib.pwf_solve(arr, 1, ptrs, ptrs, -1, 0.0, None, None, ctypes.c_void_p(0x100000), size, None) == -1
+    assert lib.pwf_solve(arr, 1, ptrs, ptrs, 5, 0.5, None, None, ctypes.c_void_p(0x100000), size, None) == -1
+    assert lib.pwf_sync_status(ctypes.c_void_p(0x100001), None) == -4
+
+
+def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2503_20146_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()
+
+
+def test_product_code_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2503_20146_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "synthetic" not in text, f

@@ -1,0 +1,302 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (FP32 fields, FP64 reductions): forward intensity relative L2 <=
+1e-5; Wirtinger gradient g and update direction d relative L2 <= 1e-4;
+retrieved phase after 100 iterations RMS <= 1e-3 rad.  Batched, graph and
+repeated runs must match their unbatched / eager / first counterparts bit for
+bit.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from gpu_helpers import device, gpu_problem, instance, rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-5
+GRAD_TOL = 1e-4
+PHASE_TOL = 1e-3
+
+
+def _pwf(problems):
+    from paper_2503_20146_amd import PWF
+    return PWF(problems)
+
+
+# --------------------------------------------------------------------------- forward
+
+@pytest.mark.parametrize("ny,nx", [(128, 128), (256, 512), (512, 256), (1024, 1024), (128, 2048), (2048, 128)])
+def test_forward_parity_sizes(ny, nx):
+    dev = device()
+    say(f"forward {ny}x{nx}")
+    rng = np.random.default_rng(ny * 7 + nx)
+    geo = S.Geometry(ny=ny, nx=nx, sigma_x_px=1.5, sigma_y_px=1.0)
+    t = S.diffuser(rng, ny, nx)
+    psi = S.phase_object(rng, ny, nx, 6.0, 3.0).astype(np.complex64)
+    prob = O.make_problem(t, geo)
+    f_ref, _, _ = O.physical_model(psi.astype(np.complex128), prob)
+    batch = _pwf([gpu_problem(geo, t, dev)])
+    f = batch.forward([to_dev(psi, dev)])[0].cpu().numpy()
+    assert rel(f, f_ref) <= FWD_TOL
+
+
+def test_forward_parity_workload1_zero_and_truth():
+    dev = device()
+    inp, geo, prob, y = instance(1)
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    for name, psi in (("zero", np.zeros((1024, 1024), np.complex64)),
+                      ("truth", inp["psi_true"].astype(np.complex64))):
+        say(f"forward 1024 {name}")
+        f_ref, _, _ = O.physical_model(psi.astype(np.complex128), prob)
+        f = batch.forward([to_dev(psi, dev)])[0].cpu().numpy()
+        assert rel(f, f_ref) <= FWD_TOL, name
+
+
+def test_forward_special_geometries():
+    """z = 0 (identity propagation) and sigma = 0 (no blur) run through the same kernels."""
+    dev = device()
+    rng = np.random.default_rng(5)
+    for kw in (dict(z1_m=0.0, z2_m=0.0), dict(sigma_x_px=0.0, sigma_y_px=0.0), dict(z1_m=0.0)):
+        say(f"forward special {kw}")
+        geo = S.Geometry(ny=256, nx=256, **kw)
+        t = S.diffuser(rng, 256, 256)
+        psi = S.phase_object(rng, 256, 256, 4.0, 2.0).astype(np.complex64)
+        prob = O.make_problem(t, geo)
+        f_ref, _, _ = O.physical_model(psi.astype(np.complex128), prob)
+        f = _pwf([gpu_problem(geo, t, dev)]).forward([to_dev(psi, dev)])[0].cpu().numpy()
+        assert rel(f, f_ref) <= FWD_TOL, kw
+
+
+# --------------------------------------------------------------------------- gradient
+
+@pytest.mark.parametrize("workload", [0, 1])
+def test_gradient_and_direction_parity(workload):
+    dev = device()
+    inp, geo, prob, y = instance(workload)
+    say(f"gradient workload {workload}")
+    psi = (0.5 * inp["psi_true"]).astype(np.complex64)
+    l_ref, g_ref, d_ref = O.gradient(psi.astype(np.complex128), y, prob)
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    loss, g, d = batch.gradient([to_dev(psi, dev)], [to_dev(y, dev)])
+    assert rel(g[0].cpu().numpy(), g_ref) <= GRAD_TOL
+    assert rel(d[0].cpu().numpy(), d_ref) <= GRAD_TOL
+    assert abs(float(loss[0].cpu()) - l_ref) <= 1e-5 * l_ref
+
+
+def test_gradient_without_preconditioner_and_other_alpha():
+    dev = device()
+    inp, geo, _, y = instance(0)
+    say("gradient precondition off, alpha 0.3+0.2i")
+    prob = O.make_problem(inp["t"], geo, precondition=False, alpha=complex(0.3, 0.2))
+    psi = (0.5 * inp["psi_true"]).astype(np.complex64)
+    _, g_ref, d_ref = O.gradient(psi.astype(np.complex128), y, prob)
+    batch = _pwf([gpu_problem(geo, inp["t"], dev, precondition=False, alpha=complex(0.3, 0.2))])
+    _, g, d = batch.gradient([to_dev(psi, dev)], [to_dev(y, dev)])
+    assert rel(g[0].cpu().numpy(), g_ref) <= GRAD_TOL
+    assert rel(d[0].cpu().numpy(), d_ref) <= GRAD_TOL
+
+
+def test_gradient_at_truth_is_small():
+    """Noise-free data at psi_true: g vanishes up to FP32 rounding of the residual."""
+    dev = device()
+    inp = S.instance_inputs(0)
+    geo = inp["geometry"]
+    prob = O.make_problem(inp["t"], geo)
+    psi = inp["psi_true"].astype(np.complex64)
+    f, _, _ = O.physical_model(psi.astype(np.complex128), prob)
+    say("gradient truth point")
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    loss, g, _ = batch.gradient([to_dev(psi, dev)], [to_dev(f.astype(np.float32), dev)])
+    _, g_ref, _ = O.gradient(psi.astype(np.complex128), f.astype(np.float32), prob)
+    # the FP32 forward model reproduces f to ~1e-6, so the residual is at that level
+    assert float(loss[0].cpu()) <= 1e-6
+    assert np.max(np.abs(g[0].cpu().numpy())) <= 1e-4
+
+
+# --------------------------------------------------------------------------- solve
+
+def test_solve_parity_workload0_50_iterations():
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say("solve workload 0, 50 iterations")
+    psi_ref, hist_ref, _ = O.pwf(y, prob, 50)
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    out, hist = batch.solve([to_dev(y, dev)], 50)
+    psi = out[0].cpu().numpy()
+    assert np.sqrt(np.mean((psi.imag - psi_ref.imag) ** 2)) <= PHASE_TOL
+    assert np.sqrt(np.mean((psi.real - psi_ref.real) ** 2)) <= PHASE_TOL
+    assert np.max(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref) <= 1e-4
+
+
+def test_solve_parity_workload1_100_iterations():
+    dev = device()
+    inp, geo, prob, y = instance(1)
+    say("solve workload 1 (1024^2), 100 iterations")
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    out, hist = batch.solve([to_dev(y, dev)], 100)
+    psi = out[0].cpu().numpy()
+    psi_ref, hist_ref, _ = O.pwf(y, prob, 100)
+    assert np.sqrt(np.mean((psi.imag - psi_ref.imag) ** 2)) <= PHASE_TOL
+    assert np.sqrt(np.mean((psi.real - psi_ref.real) ** 2)) <= PHASE_TOL
+    assert np.max(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref) <= 1e-4
+
+
+def test_plain_path_parity():
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say("plain solve workload 0, 30 iterations")
+    psi_ref, hist_ref, _ = O.pwf(y, prob, 30)
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    psi, hist = batch.solve_plain(to_dev(y, dev), 30)
+    psi = psi.cpu().numpy()
+    assert np.sqrt(np.mean(np.abs(psi - psi_ref) ** 2)) <= PHASE_TOL
+    assert np.max(np.abs(hist.cpu().numpy() - hist_ref) / hist_ref) <= 1e-4
+
+
+def test_step_matches_solve_and_oracle_state():
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say("step x 7 vs solve 7")
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    yd = to_dev(y, dev)
+    states = batch.init_states([yd])
+    losses = [float(batch.step(states)[0].cpu()) for _ in range(7)]
+    out, hist = batch.solve([yd], 7)
+    assert states[0]["k"] == 7
+    a, b = states[0]["psi"].cpu().numpy(), out[0].cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-5 * max(1.0, np.max(np.abs(b)))
+    assert np.allclose(losses, hist[0].cpu().numpy(), rtol=1e-6)
+    psi_ref, _, st_ref = O.pwf(y, prob, 7)
+    assert np.sqrt(np.mean(np.abs(a - psi_ref) ** 2)) <= PHASE_TOL
+
+
+def test_step_resume_equals_uninterrupted():
+    """Checkpoint/resume: 4 steps + copy of the state + 3 steps == 7 steps."""
+    import torch
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say("step resume")
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    yd = to_dev(y, dev)
+    s1 = batch.init_states([yd])
+    for _ in range(4):
+        batch.step(s1)
+    saved = [{k: (v.clone() if torch.is_tensor(v) else v) for k, v in s1[0].items()}]
+    for _ in range(3):
+        batch.step(s1)
+    for _ in range(3):
+        batch.step(saved)
+    assert torch.equal(s1[0]["psi"], saved[0]["psi"])
+
+
+def test_step_from_initial_psi_matches_oracle():
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say("step from psi0")
+    psi0 = (0.8 * inp["psi_true"]).astype(np.complex64)
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    states = batch.init_states([to_dev(y, dev)], [to_dev(psi0, dev)])
+    for _ in range(5):
+        batch.step(states)
+    st = O.initial_state(psi0.shape, psi0.astype(np.complex128))
+    for _ in range(5):
+        st, _ = O.pwf_step(st, y, prob)
+    assert np.sqrt(np.mean(np.abs(states[0]["psi"].cpu().numpy() - st.psi) ** 2)) <= PHASE_TOL
+
+
+# --------------------------------------------------------------------------- batching, graphs, determinism
+
+def test_batched_equals_unbatched_bitwise():
+    import torch
+    dev = device()
+    say("batched vs unbatched (shared and own diffusers)")
+    inps = [instance(0, instance=i) for i in range(3)]
+    shared_t = to_dev(inps[0][0]["t"], dev)
+    from paper_2503_20146_amd import problem_from_geometry
+    probs = [problem_from_geometry(inps[0][1], shared_t), gpu_problem(inps[1][1], inps[1][0]["t"], dev),
+             problem_from_geometry(inps[2][1], shared_t)]
+    ys = [to_dev(x[3], dev) for x in inps]
+    out_b, hist_b = _pwf(probs).solve(ys, 12)
+    for i in range(3):
+        out_1, hist_1 = _pwf([probs[i]]).solve([ys[i]], 12)
+        assert torch.equal(out_b[i], out_1[0]), i
+        assert torch.equal(hist_b[i], hist_1[0]), i
+
+
+def test_mixed_sizes_in_one_batch():
+    import torch
+    dev = device()
+    say("mixed sizes 512 / 128 / 256x128")
+    specs = [(512, 512, 0.7), (128, 128, 1.9), (256, 128, 1.2)]
+    probs, ys, refs = [], [], []
+    for k, (ny, nx, sig) in enumerate(specs):
+        rng = np.random.default_rng(100 + k)
+        geo = S.Geometry(ny=ny, nx=nx, sigma_x_px=sig, sigma_y_px=sig)
+        t = S.diffuser(rng, ny, nx)
+        psi_true = S.phase_object(rng, ny, nx, 4.0, 2.0)
+        prob = O.make_problem(t, geo)
+        f, _, _ = O.physical_model(psi_true, prob)
+        y = S.poisson_intensity(f, (7, k))
+        probs.append(gpu_problem(geo, t, dev))
+        ys.append(to_dev(y, dev))
+        refs.append((prob, y))
+    out, hist = _pwf(probs).solve(ys, 10)
+    for i in range(3):
+        one, _ = _pwf([probs[i]]).solve([ys[i]], 10)
+        assert torch.equal(out[i], one[0])
+        psi_ref, _, _ = O.pwf(refs[i][1], refs[i][0], 10)
+        assert np.sqrt(np.mean(np.abs(out[i].cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL
+
+
+def test_graph_replay_equals_eager():
+    import torch
+    from paper_2503_20146_amd import set_graph_mode
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say("graph vs eager")
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    yd = to_dev(y, dev)
+    set_graph_mode(False)
+    try:
+        eager, he = batch.solve([yd], 9)
+    finally:
+        set_graph_mode(True)
+    results = []
+    for _ in range(3):  # replays of the cached graph, with eager work and syncs between them
+        g, hg = batch.solve([yd], 9)
+        torch.cuda.synchronize()
+        _ = batch.forward([g[0]])
+        torch.cuda.synchronize()
+        results.append((g[0].clone(), hg.clone()))
+    for g, hg in results:
+        assert torch.equal(g, eager[0])
+        assert torch.equal(hg, he)
+
+
+def test_repeatable_bitwise():
+    import torch
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say("repeatability")
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    yd = to_dev(y, dev)
+    a, ha = batch.solve([yd], 6)
+    a0 = a[0].clone()
+    b, hb = batch.solve([yd], 6)
+    assert torch.equal(a0, b[0]) and torch.equal(ha, hb)
+
+
+def test_nonfinite_loss_is_reported():
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say("non-finite flag")
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    ybad = y.copy()
+    ybad[3, 5] = np.nan
+    batch.solve([to_dev(ybad, dev)], 2)
+    assert batch.sync_status() == -6
+    batch.solve([to_dev(y, dev)], 2)
+    assert batch.sync_status() == 0
