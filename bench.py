@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of batched PWF on one MI355X.
+
+Workload: 180 projections of 1024^2 (the 40-ellipsoid phantom over 0-180 deg,
+one shared diffuser, source sigma 1.5 px, Poisson noise at 1e4 photons/px).
+One step is one pwf_solve call: 100 iterations of Algorithm S1 on every
+projection (forward model, loss, Wirtinger gradient, preconditioner,
+regulariser, Nesterov step), captured as one hipGraph.  The value is
+projection-iterations per second with all inputs resident in HBM.
+
+Prints ONE JSON line.  Extra objects:
+  roofline      the dominant sweep kernel, timed live with HIP events
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload
+  plain_baseline the unfused one-kernel-per-operation GPU path on one projection
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PWF projection-iterations/s (fwd+grad) at 1024^2; % HBM roofline vs plain"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per pixel of each fused sweep (reads + writes of
+# complex64 fields; windows and chirps are generated from indices).
+SWEEP_BYTES_PER_PX = [24, 16, 24, 16, 24, 24, 24, 16, 24, 16, 24, 48]
+SWEEP_NAMES = ["S0 row psi-update", "S1 col Q_L1", "S2 row x t", "S3 col Q_L2", "S4 row |v|^2",
+               "S5 col blur+loss", "S6 row back-blur", "S7 col conj Q_L2", "S8 row x conj t",
+               "S9 col conj Q_L1", "S10 row gradient", "S11 col direction+Nesterov"]
+ITER_BYTES_PER_PX = sum(SWEEP_BYTES_PER_PX)   # 280
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2503_20146_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(sweep: int, pixels: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None if stale."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("sweeps", {}).get(str(sweep))
+    if not ent:
+        return None
+    return ent["hbm_bytes_per_px"] * pixels
+
+
+def build_workload(n_proj: int, dev):
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    from paper_2503_20146_amd import PWF, problem_from_geometry
+
+    d = S.tomo_projection_inputs(2, range(n_proj))
+    geo = d["geometry"]
+    t = torch.from_numpy(d["t"]).to(dev)
+    probs = [problem_from_geometry(geo, t) for _ in range(n_proj)]
+    batch = PWF(probs)
+    psi_true = [torch.from_numpy(p.astype(np.complex64)).to(dev) for p in d["psi_true"]]
+    f = batch.forward(psi_true)          # noise-free speckle from the GPU forward model
+    torch.cuda.synchronize()
+    ys = []
+    for j in range(n_proj):
+        y = S.poisson_intensity(f[j].cpu().numpy(), d["seed_keys"][j])
+        ys.append(torch.from_numpy(y).to(dev))
+    del f, psi_true
+    return batch, ys, geo, probs, d
+
+
+def time_events(fn, reps_note=None):
+    import torch
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    fn()
+    b.record(s)
+    b.synchronize()
+    return a.elapsed_time(b) / 1e3
+
+
+def cpu_baseline(iters: int):
+    import numpy as np
+
+    import oracle as O
+    import synthetic as S
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    threads = max(1, min(threads, 16))
+    O.FFT_WORKERS = threads
+    d = S.tomo_projection_inputs(2, [0])
+    prob = O.make_problem(d["t"], d["geometry"])
+    f, _, _ = O.physical_model(d["psi_true"][0], prob)
+    y = S.poisson_intensity(f, d["seed_keys"][0])
+    st = O.initial_state(prob.shape)
+    st, _ = O.pwf_step(st, y, prob)       # warm-up iteration (not timed)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        st, _ = O.pwf_step(st, y, prob)
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "proj-iter/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 projection of 1024^2 (projection 0 of the workload), {iters} iterations of the "
+                      f"FP64 scipy.fft oracle after 1 warm-up iteration, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--projections", type=int, default=180)
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--sweep-reps", type=int, default=10)
+    ap.add_argument("--plain-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--sweep-only", type=int, default=-1,
+                    help="after setup, only launch this sweep (for counter collection)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "projections are independent, see the sharding notes in DESIGN.md", file=sys.stderr)
+        return 2
+
+    import torch
+    dev = torch.device("cuda:0")
+    print(f"[bench] building workload: {args.projections} x 1024^2", file=sys.stderr, flush=True)
+    batch, ys, geo, probs, _ = build_workload(args.projections, dev)
+    pixels = args.projections * geo.nx * geo.ny
+
+    if args.sweep_only >= 0:
+        batch.solve(ys, 2)
+        torch.cuda.synchronize()
+        batch.bench_sweep(args.sweep_only, args.sweep_reps)
+        torch.cuda.synchronize()
+        print(f"[bench] sweep {args.sweep_only} x {args.sweep_reps} done", file=sys.stderr, flush=True)
+        return 0
+
+    out = [torch.empty((geo.ny, geo.nx), dtype=torch.complex64, device=dev) for _ in range(args.projections)]
+    for w in range(args.warmup):
+        batch.solve(ys, args.iters, psi_out=out, loss_hist=False)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        batch.solve(ys, args.iters, psi_out=out, loss_hist=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if batch.sync_status() != 0:
+        print("[bench] non-finite loss during the timed run", file=sys.stderr)
+        return 1
+    value = args.projections * args.iters * args.steps / dt
+    print(f"[bench] timed {args.steps} steps in {dt:.3f} s -> {value:.1f} proj-iter/s", file=sys.stderr, flush=True)
+
+    # per-sweep kernel durations, live, with HIP events on the launch stream
+    sweep_s = []
+    for s in range(12):
+        sec = time_events(lambda: batch.bench_sweep(s, args.sweep_reps)) / args.sweep_reps
+        sweep_s.append(sec)
+    # restore a meaningful state is not needed: timing only
+    dom = max(range(12), key=lambda s: sweep_s[s])
+    alg_bytes = SWEEP_BYTES_PER_PX[dom] * pixels
+    achieved = alg_bytes / sweep_s[dom] / 1e9
+    traffic = measured_traffic(dom, pixels)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": SWEEP_NAMES[dom], "launch_ms": round(sweep_s[dom] * 1e3, 4),
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "per_sweep_ms": [round(x * 1e3, 4) for x in sweep_s],
+                "iteration_frac_of_hbm_roofline": round(value * ITER_BYTES_PER_PX * geo.nx * geo.ny / 1e9
+                                                        / HBM_PEAK_GBS, 4)}
+    print(f"[bench] sweeps ms: {[round(x * 1e3, 3) for x in sweep_s]}", file=sys.stderr, flush=True)
+
+    plain = None
+    if not args.no_plain:
+        from paper_2503_20146_amd import PWF
+        one = PWF([probs[0]])
+        one.solve_plain(ys[0], 2)
+        torch.cuda.synchronize()
+        sec = time_events(lambda: one.solve_plain(ys[0], args.plain_iters, loss_hist=False))
+        pv = args.plain_iters / sec
+        plain = {"value": round(pv, 2), "unit": "proj-iter/s",
+                 "path": "pwf_solve_plain: one projection, one kernel per operation (16 2-D FFTs per iteration), "
+                         "no batching, no graph", "speedup_of_batched": round(value / pv, 2)}
+        print(f"[bench] plain {pv:.1f} proj-iter/s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_iters)
+        print(f"[bench] cpu oracle {cpu['value']:.3f} proj-iter/s on {cpu['cores']} threads", file=sys.stderr,
+              flush=True)
+
+    rec = {
+        "metric": METRIC, "value": round(value, 2), "unit": "proj-iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.projections} projections x 1024^2 of a 40-ellipsoid phantom over 0-180 deg, "
+                               f"shared diffuser, {args.iters} PWF iterations per step in one hipGraph",
+                   "projections": args.projections, "grid": [geo.ny, geo.nx], "iterations_per_step": args.iters,
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "plain_baseline": plain,
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -168,6 +168,16 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
 pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi_out, int32_t iters,
                            double* loss_hist, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Timing aid: launch sweep `sweep` (0..11, the steps of one fused iteration
+ * in order: S0 psi update, S1 x Q_L1, S2 x t, S3 x Q_L2, S4 |v|^2, S5 blur and
+ * loss, S6 back-blur, S7 x conj Q_L2, S8 x conj t, S9 x conj Q_L1, S10
+ * gradient, S11 direction and Nesterov step) `reps` times over the batch.  It
+ * reuses the fields that a previous pwf_solve with the same problems left in
+ * `workspace`; the fields it rewrites are meaningless afterwards.  Returns
+ * PWF_ERR_ARG for a sweep outside 0..11 or reps < 1. */
+pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep, int32_t reps, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
 /* Capture pwf_solve's loop in a hipGraph (1, default) or launch eagerly (0). */
 void pwf_set_graph_mode(int32_t on);
 

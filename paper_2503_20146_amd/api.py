@@ -181,6 +181,12 @@ class PWF:
                                        ws, nb, _stream(self.device)), "pwf_solve_plain")
         return psi_out, hist
 
+    def bench_sweep(self, sweep: int, reps: int) -> None:
+        """Launch fused sweep ``sweep`` (0..11) ``reps`` times on the state of the last solve."""
+        ws, nb = self._ws()
+        check(self.lib.pwf_bench_sweep(self._c, self.n, sweep, reps, ws, nb, _stream(self.device)),
+              "pwf_bench_sweep")
+
     def sync_status(self) -> int:
         ws, _ = self._ws()
         return self.lib.pwf_sync_status(ws, _stream(self.device))

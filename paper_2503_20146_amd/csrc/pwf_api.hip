@@ -575,11 +575,12 @@ pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, st
   (void)probs;
   (void)n;
   (void)desc;
-  // clear the status word, and W, psi_hat and z_hat of every instance (contiguous regions)
-  PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.status, 16, K.st));
-  PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.W[0], K.L.v[0] - K.L.W[0], K.st));
+  // spectrum of y (uses W as scratch), then clear the status word and W,
+  // psi_hat, z_hat of every instance (contiguous regions): psi = z = 0
   PWF_TRY(K.row(pwf::ROW_REAL_FFT));
   PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
+  PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.status, 16, K.st));
+  PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.W[0], K.L.v[0] - K.L.W[0], K.st));
   for (int k = 0; k < iters; ++k) {
     PWF_TRY(K.row(pwf::ROW_PSI_UPDATE, k));
     PWF_TRY(K.col(pwf::COL_CHIRP1, k));
@@ -697,6 +698,56 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
   PWF_HIP(hipGraphLaunch(exec, ctx->side));
   PWF_HIP(hipEventRecord(ctx->ev_out, ctx->side));
   PWF_HIP(hipStreamWaitEvent(st, ctx->ev_out, 0));
+  return PWF_OK;
+}
+
+pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep, int32_t reps, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (sweep < 0 || sweep > 11 || reps < 1) return PWF_ERR_ARG;
+  Layout L;
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Batch B = group(problems, n);
+  std::vector<Inst> desc(n);
+  std::vector<const void*> seen;
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    I.W = (float2*)(ws + L.W[i]);
+    I.v = (float2*)(ws + L.v[i]);
+    I.psi = (float2*)(ws + L.psi[i]);
+    I.psi_hat = (float2*)(ws + L.psi_hat[i]);
+    I.z_hat = (float2*)(ws + L.z_hat[i]);
+    I.y_hat = (float2*)(ws + L.y_hat[i]);
+    I.loss_partial = (double*)(ws + L.part[i]);
+    int slot = -1;
+    for (size_t j = 0; j < seen.size(); ++j)
+      if (seen[j] == problems[i].diffuser) slot = (int)j;
+    if (slot < 0) {
+      slot = (int)seen.size();
+      seen.push_back(problems[i].diffuser);
+    }
+    I.maxt2 = (const float*)(ws + L.maxt2) + slot;
+  }
+  PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  const Launcher K{*ctx, ws, L, B, st};
+  static const int kOps[12][2] = {
+      {0, pwf::ROW_PSI_UPDATE}, {1, pwf::COL_CHIRP1},      {0, pwf::ROW_MUL_T},      {1, pwf::COL_CHIRP2},
+      {0, pwf::ROW_INTENSITY},  {1, pwf::COL_BLUR_LOSS},   {0, pwf::ROW_BACKBLUR},   {1, pwf::COL_CHIRP2_CONJ},
+      {0, pwf::ROW_MUL_CONJ_T}, {1, pwf::COL_CHIRP1_CONJ}, {0, pwf::ROW_GRAD},       {1, pwf::COL_NESTEROV}};
+  for (int r = 0; r < reps; ++r) {
+    if (kOps[sweep][0] == 0) {
+      PWF_TRY(K.row(kOps[sweep][1], 0));
+    } else {
+      PWF_TRY(K.col(kOps[sweep][1], 0));
+    }
+  }
   return PWF_OK;
 }
 

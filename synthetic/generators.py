@@ -198,16 +198,17 @@ def project_ellipsoids(ellipsoids: list[dict], angle_rad: float, ny: int, nx: in
         j1 = min(int(math.ceil(v_c + amax + ny / 2.0 + 1)), ny)
         if i1 <= i0 or j1 <= j0:
             continue
-        u = np.arange(i0, i1) + 0.5 - nx / 2.0
-        v = np.arange(j0, j1) + 0.5 - ny / 2.0
-        uu, vv = np.meshgrid(u, v)
-        w = uu[..., None] * ex + vv[..., None] * ey - c   # ray origin minus centre
-        ad = a_mat @ d
+        u = (np.arange(i0, i1) + 0.5 - nx / 2.0)[None, :]
+        v = (np.arange(j0, j1) + 0.5 - ny / 2.0)[:, None]
+        # ray r(s) = u ex + v ey + s d; with w = r(0) - c the chord solves
+        # qa s^2 + 2 qb s + qc = 0, expanded as polynomials in (u, v)
+        ad, ac = a_mat @ d, a_mat @ c
         qa = d @ ad
-        qb = w @ ad
-        qc = np.einsum("...i,ij,...j->...", w, a_mat, w) - 1.0
+        qb = u * (ex @ ad) + v * (ey @ ad) - c @ ad
+        qc = (u * u * (ex @ a_mat @ ex) + 2.0 * u * v * (ex @ a_mat @ ey) + v * v * (ey @ a_mat @ ey)
+              - 2.0 * u * (ex @ ac) - 2.0 * v * (ey @ ac) + c @ ac - 1.0)
         disc = qb * qb - qa * qc
-        chord = np.where(disc > 0.0, 2.0 * np.sqrt(np.clip(disc, 0.0, None)) / qa, 0.0)
+        chord = 2.0 * np.sqrt(np.maximum(disc, 0.0)) / qa
         chord_m = chord * pixel_m
         phi[j0:j1, i0:i1] += k0 * e["delta"] * chord_m
         mu[j0:j1, i0:i1] += k0 * e["beta"] * chord_m

@@ -72,6 +72,19 @@ def test_forward_special_geometries():
 
 # --------------------------------------------------------------------------- gradient
 
+def direction_tolerance(n: int) -> float:
+    """End-to-end tolerance of d on an n x n grid.
+
+    d's phase part is P^-1 applied to Im g, and P^-1 = s_P / rho^2 (rho in
+    cycles/pixel) reaches s_P n^2 at the lowest frequency.  White FP32 rounding
+    noise of g is amplified in RMS by sqrt(mean_k P_k^2) ~ sqrt(6) s_P n, which
+    grows linearly in n, so the 1e-4 budget that holds at 128^2 scales as n/128.
+    The preconditioner/regulariser arithmetic itself is held to 1e-4 by
+    comparing against the FP64 functions applied to the GPU's own g.
+    """
+    return GRAD_TOL * max(1.0, n / 128.0)
+
+
 @pytest.mark.parametrize("workload", [0, 1])
 def test_gradient_and_direction_parity(workload):
     dev = device()
@@ -81,8 +94,12 @@ def test_gradient_and_direction_parity(workload):
     l_ref, g_ref, d_ref = O.gradient(psi.astype(np.complex128), y, prob)
     batch = _pwf([gpu_problem(geo, inp["t"], dev)])
     loss, g, d = batch.gradient([to_dev(psi, dev)], [to_dev(y, dev)])
-    assert rel(g[0].cpu().numpy(), g_ref) <= GRAD_TOL
-    assert rel(d[0].cpu().numpy(), d_ref) <= GRAD_TOL
+    g_gpu, d_gpu = g[0].cpu().numpy(), d[0].cpu().numpy()
+    assert rel(g_gpu, g_ref) <= GRAD_TOL
+    # S11 arithmetic: oracle Preconditioner + Regularizer applied to the GPU's g
+    d_stage = O.preconditioner(g_gpu.astype(np.complex128), prob) + O.regularizer(psi.astype(np.complex128), prob)
+    assert rel(d_gpu, d_stage) <= GRAD_TOL
+    assert rel(d_gpu, d_ref) <= direction_tolerance(geo.nx)
     assert abs(float(loss[0].cpu()) - l_ref) <= 1e-5 * l_ref
 
 
