@@ -62,6 +62,75 @@ def measured_traffic(sweep: int, pixels: int):
     return ent["hbm_bytes_per_px"] * pixels
 
 
+COPY_BYTES = 1 << 30
+# kernel-name fragments of each fused sweep at 1024^2 (template op ids of row_sweep / col_sweep)
+SWEEP_KERNELS = ["row_sweep<1024, 0>", "col_sweep<1024, {w}, 0>", "row_sweep<1024, 2>", "col_sweep<1024, {w}, 1>",
+                 "row_sweep<1024, 4>", "col_sweep<1024, {w}, 4>", "row_sweep<1024, 5>", "col_sweep<1024, {w}, 2>",
+                 "row_sweep<1024, 3>", "col_sweep<1024, {w}, 3>", "row_sweep<1024, 6>", "col_sweep<1024, {w}, 6>"]
+
+
+def autotune(batch) -> dict:
+    """Pick the column-tile width per grid side (pwf_autotune) and report the choice."""
+    from paper_2503_20146_amd import _lib
+    lib = _lib.load()
+    ws, nb = batch._ws()
+    import torch
+    _lib.check(lib.pwf_autotune(batch._c, batch.n, 5, ws, nb,
+                                __import__("ctypes").c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "pwf_autotune")
+    return {n: lib.pwf_column_tile(n) for n in sorted({p.ny for p in batch.problems})}
+
+
+def _read_counter_csv(path: str, counter: str) -> dict:
+    """Per-kernel mean of `counter` over dispatches from a rocprofv3 counter_collection.csv."""
+    import csv
+    sums, counts = {}, {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row["Kernel_Name"]
+            key = (name, row.get("Dispatch_Id"))
+            sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+    per_kernel = {}
+    for (name, _), val in sums.items():
+        per_kernel.setdefault(name, []).append(val)
+    return {k: sum(v) / len(v) for k, v in per_kernel.items()}
+
+
+def ingest_counters(fetch_csv: str, write_csv: str, projections: int) -> int:
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the copy-kernel calibration."""
+    fetch = _read_counter_csv(fetch_csv, "FETCH_SIZE")
+    write = _read_counter_csv(write_csv, "WRITE_SIZE")
+    copy_f = [v for k, v in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+    copy_w = [v for k, v in write.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+    if not copy_f or not copy_w:
+        print("no copy kernel in the counter files", file=sys.stderr)
+        return 1
+    kib = COPY_BYTES / 1024.0
+    f_scale = kib / max(copy_f)
+    w_scale = kib / max(copy_w)
+    pixels = projections * 1024 * 1024
+    out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES,
+           "fetch_scale": f_scale, "write_scale": w_scale, "pixels_per_launch": pixels, "sweeps": {}}
+    for s, frag in enumerate(SWEEP_KERNELS):
+        names = [k for k in fetch if any(frag.format(w=w) in k for w in (4, 8, 16))]
+        if not names:
+            continue
+        name = names[0]
+        wname = [k for k in write if k == name]
+        fb = fetch[name] * 1024.0 * f_scale
+        wb = write[wname[0]] * 1024.0 * w_scale if wname else 0.0
+        out["sweeps"][str(s)] = {"kernel": name, "fetch_bytes": fb, "write_bytes": wb,
+                                 "hbm_bytes_per_px": (fb + wb) / pixels,
+                                 "algorithmic_bytes_per_px": SWEEP_BYTES_PER_PX[s]}
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+    return 0
+
+
 def build_workload(n_proj: int, dev):
     import numpy as np
     import torch
@@ -128,12 +197,19 @@ def main() -> int:
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--sweep-reps", type=int, default=10)
     ap.add_argument("--plain-iters", type=int, default=20)
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--sweep-only", type=int, default=-1,
-                    help="after setup, only launch this sweep (for counter collection)")
+    ap.add_argument("--sweep-only", default=None,
+                    help="after setup, only launch sweep K (0..11) or 'all' plus a 1 GiB copy (counter runs)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs of a --sweep-only all run "
+                         "into profiles/traffic_counters.json and exit")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
+
+    if args.ingest_counters:
+        return ingest_counters(*args.ingest_counters, projections=args.projections)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -147,12 +223,26 @@ def main() -> int:
     batch, ys, geo, probs, _ = build_workload(args.projections, dev)
     pixels = args.projections * geo.nx * geo.ny
 
-    if args.sweep_only >= 0:
+    tiles = {}
+    if not args.no_autotune:
+        tiles = autotune(batch)
+        print(f"[bench] column tiles {tiles}", file=sys.stderr, flush=True)
+
+    if args.sweep_only is not None:
         batch.solve(ys, 2)
         torch.cuda.synchronize()
-        batch.bench_sweep(args.sweep_only, args.sweep_reps)
+        sweeps = range(12) if args.sweep_only == "all" else [int(args.sweep_only)]
+        if args.sweep_only == "all":
+            # calibration: a plain device copy of exactly COPY_BYTES
+            src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        for sw in sweeps:
+            batch.bench_sweep(sw, args.sweep_reps)
         torch.cuda.synchronize()
-        print(f"[bench] sweep {args.sweep_only} x {args.sweep_reps} done", file=sys.stderr, flush=True)
+        print(f"[bench] sweeps {list(sweeps)} x {args.sweep_reps} done", file=sys.stderr, flush=True)
         return 0
 
     out = [torch.empty((geo.ny, geo.nx), dtype=torch.complex64, device=dev) for _ in range(args.projections)]
@@ -219,7 +309,7 @@ def main() -> int:
         "config": {"workload": f"{args.projections} projections x 1024^2 of a 40-ellipsoid phantom over 0-180 deg, "
                                f"shared diffuser, {args.iters} PWF iterations per step in one hipGraph",
                    "projections": args.projections, "grid": [geo.ny, geo.nx], "iterations_per_step": args.iters,
-                   "parallelism": "single GPU"},
+                   "column_tiles": tiles, "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "plain_baseline": plain,
     }
     print(json.dumps(rec), flush=True)

@@ -178,6 +178,22 @@ pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi
 pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep, int32_t reps, void* workspace,
                            size_t workspace_bytes, void* stream);
 
+/* Column-sweep tile width (columns per workgroup) for grid side n.  Two
+ * widths are compiled per side (128: 32/16, 256-1024: 16/8, 2048: 8/4); 0
+ * restores the default.  PWF_ERR_SIZE / PWF_ERR_ARG for an unsupported side
+ * or width.  Process-wide; applies to calls issued afterwards. */
+pwf_status pwf_set_column_tile(int32_t n, int32_t width);
+
+/* Current column-sweep tile width for grid side n (0 if unsupported). */
+int32_t pwf_column_tile(int32_t n);
+
+/* Autotuner: for each grid shape in the batch, time the column sweeps at
+ * every compiled tile width (`reps` launches each, HIP events on `stream`,
+ * synchronous) and keep the fastest, as pwf_set_column_tile would.  Clobbers
+ * the workspace contents. */
+pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
 /* Capture pwf_solve's loop in a hipGraph (1, default) or launch eagerly (0). */
 void pwf_set_graph_mode(int32_t on);
 

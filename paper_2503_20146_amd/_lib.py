@@ -59,6 +59,9 @@ SIGNATURES = {
                          ctypes.c_size_t, _vp]),
     "pwf_solve_plain": (_i32, [_P(pwf_problem), _vp, _vp, _i32, _vp, _vp, ctypes.c_size_t, _vp]),
     "pwf_bench_sweep": (_i32, [_P(pwf_problem), _i32, _i32, _i32, _vp, ctypes.c_size_t, _vp]),
+    "pwf_set_column_tile": (_i32, [_i32, _i32]),
+    "pwf_column_tile": (_i32, [_i32]),
+    "pwf_autotune": (_i32, [_P(pwf_problem), _i32, _i32, _vp, ctypes.c_size_t, _vp]),
     "pwf_set_graph_mode": (None, [_i32]),
     "pwf_sync_status": (_i32, [_vp, _vp]),
     "pwf_finalize": (None, []),

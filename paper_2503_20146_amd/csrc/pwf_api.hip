@@ -55,7 +55,8 @@ struct GraphKey {
 
 struct Context {
   bool ready = false;
-  float2* tw[5] = {};          // twiddle tables per supported side
+  float2* tw[5] = {};          // row-plan twiddle tables per supported side
+  float2* twc[5] = {};         // column-plan twiddle tables per supported side
   double* beta = nullptr;      // momentum table
   hipStream_t side = nullptr;  // internal stream for graph launches
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -67,6 +68,16 @@ struct Context {
   hipEvent_t stage_ev[kSlots] = {};
   int next_slot = 0;
 };
+
+// Column-tile width per supported side (0: compiled default); set by
+// pwf_set_column_tile or pwf_autotune.
+int g_col_width[5] = {0, 0, 0, 0, 0};
+
+int col_width(int n) {
+  const int i = size_index(n);
+  if (i < 0) return 0;
+  return g_col_width[i] ? g_col_width[i] : pwf::col_default_width(n);
+}
 
 std::mutex g_mu;
 Context g_ctx[kMaxDevices];
@@ -86,11 +97,14 @@ pwf_status context_for_current(Context** out) {
   Context& c = g_ctx[dev];
   if (!c.ready) {
     for (int i = 0; i < 5; ++i) {
-      const int cnt = pwf::plan_twiddles(kSizes[i], nullptr);
-      std::vector<float2> host(cnt);
-      pwf::plan_twiddles(kSizes[i], host.data());
-      PWF_HIP(hipMalloc(&c.tw[i], sizeof(float2) * std::max(cnt, 1)));
-      PWF_HIP(hipMemcpy(c.tw[i], host.data(), sizeof(float2) * cnt, hipMemcpyHostToDevice));
+      for (int which = 0; which < 2; ++which) {
+        float2*& dst = which == 0 ? c.tw[i] : c.twc[i];
+        const int cnt = pwf::plan_twiddles(kSizes[i], which, nullptr);
+        std::vector<float2> host(std::max(cnt, 1));
+        pwf::plan_twiddles(kSizes[i], which, host.data());
+        PWF_HIP(hipMalloc(&dst, sizeof(float2) * std::max(cnt, 1)));
+        PWF_HIP(hipMemcpy(dst, host.data(), sizeof(float2) * std::max(cnt, 1), hipMemcpyHostToDevice));
+      }
     }
     // beta_k = (tau_k - 1) / tau_{k+1}, tau_0 = 1, tau_{k+1} = (1 + sqrt(1 + 4 tau_k^2)) / 2
     std::vector<double> b(kBetaCap);
@@ -164,11 +178,14 @@ pwf_status validate_batch(const pwf_problem* probs, int32_t n) {
 // ------------------------------------------------------------------ workspace layout
 
 size_t field_bytes(const pwf_problem& p) { return align_up((size_t)p.geom.nx * p.geom.ny * sizeof(float2)); }
-int n_partials(const pwf_problem& p) { return p.geom.nx / pwf::col_cols_per_block(p.geom.ny); }
+int n_partials(const pwf_problem& p) { return p.geom.nx / col_width(p.geom.ny); }
+size_t table_bytes(const pwf_problem& p) {
+  return align_up((size_t)(p.geom.nx + p.geom.ny) * (2 * sizeof(float2) + 2 * sizeof(float)));
+}
 
 struct Layout {
   size_t status = 0, maxt2 = 0, maxt2_part = 0, desc = 0, partials = 0;
-  std::vector<size_t> W, psi_hat, z_hat, v, psi, y_hat, extra0, extra1, part;
+  std::vector<size_t> W, psi_hat, z_hat, v, psi, y_hat, extra0, extra1, part, tables;
   size_t total = 0;
 };
 
@@ -189,7 +206,13 @@ Layout make_layout(const pwf_problem* probs, int n) {
   L.partials = off;
   for (int i = 0; i < n; ++i) {
     L.part[i] = off;
-    off += align_up(sizeof(double) * std::max(n_partials(probs[i]), pwf::plain_elementwise_blocks()));
+    // room for the narrowest column tile (4 columns) and the plain path's partials
+    off += align_up(sizeof(double) * std::max(probs[i].geom.nx / 4, pwf::plain_elementwise_blocks()));
+  }
+  L.tables.resize(n);
+  for (int i = 0; i < n; ++i) {
+    L.tables[i] = off;
+    off += table_bytes(probs[i]);
   }
   auto region = [&](std::vector<size_t>& r) {
     r.resize(n);
@@ -228,6 +251,9 @@ Inst base_inst(const pwf_problem& p) {
   I.chirp2_rev = g.z2_m * g.wavelength_m / (2.0 * p2);
   I.s_coef = (g.wavelength_m / g.pixel_m) * (g.wavelength_m / g.pixel_m);
   I.series = (0.5 * I.s_coef < 1e-4) ? 1 : 0;
+  I.two_pi_a1 = (float)(2.0 * M_PI * I.chirp1_rev);
+  I.two_pi_a2 = (float)(2.0 * M_PI * I.chirp2_rev);
+  I.s_coef_f = (float)I.s_coef;
   const double pi2 = M_PI * M_PI;
   I.iotf_cx = (float)(2.0 * pi2 * p.source.sigma_x_px * p.source.sigma_x_px);
   I.iotf_cy = (float)(2.0 * pi2 * p.source.sigma_y_px * p.source.sigma_y_px);
@@ -240,6 +266,19 @@ Inst base_inst(const pwf_problem& p) {
   I.inv_m_d = 1.0 / ((double)g.nx * g.ny);
   I.inv_m = (float)I.inv_m_d;
   return I;
+}
+
+void attach_tables(Inst& I, char* ws, const Layout& L, int i) {
+  char* b = ws + L.tables[i];
+  const size_t nx = (size_t)I.nx, ny = (size_t)I.ny;
+  I.qx1 = (float2*)b;
+  I.qx2 = I.qx1 + nx;
+  I.qy1 = I.qx2 + nx;
+  I.qy2 = I.qy1 + ny;
+  I.ix = (float*)(I.qy2 + ny);
+  I.gx = I.ix + nx;
+  I.iy = I.gx + nx;
+  I.gy = I.iy + ny;
 }
 
 // Instances grouped by grid shape; each class is a contiguous run of the
@@ -285,7 +324,7 @@ struct Launcher {
     S.iter = iter;
     S.beta = ctx.beta;
     S.tw_row = ctx.tw[size_index(c.nx)];
-    S.tw_col = ctx.tw[size_index(c.ny)];
+    S.tw_col = ctx.twc[size_index(c.ny)];
     S.status = status();
     S.blocks_per_inst = 0;
     return S;
@@ -301,8 +340,9 @@ struct Launcher {
   pwf_status col(int op, int iter = 0) const {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
-      S.blocks_per_inst = c.nx / pwf::col_cols_per_block(c.ny);
-      PWF_HIP(pwf::launch_col(c.ny, op, S.blocks_per_inst * c.count, S, st));
+      const int width = col_width(c.ny);
+      S.blocks_per_inst = c.nx / width;
+      PWF_HIP(pwf::launch_col(c.ny, width, op, S.blocks_per_inst * c.count, S, st));
     }
     return PWF_OK;
   }
@@ -392,12 +432,14 @@ pwf_status pwf_forward(const pwf_problem* problems, int32_t n, const void* const
     const int i = B.order[s];
     Inst& I = desc[s];
     I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
     I.W = (float2*)(ws + L.W[i]);
     I.psi_src = (const float2*)psi[i];
     I.f_out = f_out[i];
     I.loss_partial = (double*)(ws + L.part[i]);
   }
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
   const Launcher K{*ctx, ws, L, B, st};
   PWF_TRY(K.row(pwf::ROW_START));
   PWF_TRY(K.col(pwf::COL_CHIRP1));
@@ -432,9 +474,10 @@ pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* cons
     const int i = B.order[s];
     Inst& I = desc[s];
     I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
     I.W = (float2*)(ws + L.W[i]);
     I.v = (float2*)(ws + L.v[i]);
-    I.psi = (float2*)psi[i];
+    I.x = (float2*)(ws + L.psi[i]);
     I.psi_src = (const float2*)psi[i];
     I.psi_hat = (float2*)(ws + L.psi_hat[i]);
     I.y_hat = (float2*)(ws + L.y_hat[i]);
@@ -447,9 +490,10 @@ pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* cons
   PWF_HIP(pwf::launch_fill_zero(ws + L.status, 16, st));
   PWF_TRY(launch_maxt2(problems, n, B, desc, ws, L, st));
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
   const Launcher K{*ctx, ws, L, B, st};
   if (want_d) {
-    // spectrum of psi for the regulariser (psi is not copied: I.psi == psi_src)
+    // spectrum of psi for the regulariser (I.psi is null: nothing is copied)
     PWF_TRY(K.row(pwf::ROW_CPLX_FFT));
     PWF_TRY(K.col(pwf::COL_SPEC_PSIHAT));
   }
@@ -492,6 +536,7 @@ pwf_status pwf_state_init(const pwf_problem* problems, int32_t n, pwf_state* sta
     const int i = B.order[s];
     Inst& I = desc[s];
     I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
     I.W = (float2*)(ws + L.W[i]);
     I.y = y[i];
     I.y_hat = (float2*)states[i].y_hat;
@@ -502,6 +547,7 @@ pwf_status pwf_state_init(const pwf_problem* problems, int32_t n, pwf_state* sta
     I.loss_partial = (double*)(ws + L.part[i]);
   }
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
   const Launcher K{*ctx, ws, L, B, st};
   PWF_TRY(K.row(pwf::ROW_REAL_FFT));
   PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
@@ -532,10 +578,11 @@ pwf_status pwf_step(const pwf_problem* problems, int32_t n, pwf_state* states, d
     const int i = B.order[s];
     Inst& I = desc[s];
     I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
     I.k0 = states[i].k;
     I.W = (float2*)(ws + L.W[i]);
     I.v = (float2*)(ws + L.v[i]);
-    I.psi = (float2*)states[i].psi;
+    I.x = (float2*)(ws + L.psi[i]);
     I.psi_src = (const float2*)states[i].psi;
     I.psi_hat = (float2*)states[i].psi_hat;
     I.z_hat = (float2*)states[i].z_hat;
@@ -547,6 +594,7 @@ pwf_status pwf_step(const pwf_problem* problems, int32_t n, pwf_state* states, d
   PWF_HIP(pwf::launch_fill_zero(ws + L.status, 16, st));
   PWF_TRY(launch_maxt2(problems, n, B, desc, ws, L, st));
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
   const Launcher K{*ctx, ws, L, B, st};
   PWF_TRY(K.row(pwf::ROW_START));
   PWF_TRY(K.col(pwf::COL_CHIRP1));
@@ -623,9 +671,10 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
     const int i = B.order[s];
     Inst& I = desc[s];
     I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
     I.W = (float2*)(ws + L.W[i]);
     I.v = (float2*)(ws + L.v[i]);
-    I.psi = (float2*)(ws + L.psi[i]);
+    I.x = (float2*)(ws + L.psi[i]);
     I.psi_hat = (float2*)(ws + L.psi_hat[i]);
     I.z_hat = (float2*)(ws + L.z_hat[i]);
     I.y_hat = (float2*)(ws + L.y_hat[i]);
@@ -650,6 +699,7 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
     }
   }
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
   if (iters_done)
     for (int i = 0; i < n; ++i) iters_done[i] = iters;
 
@@ -719,9 +769,10 @@ pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep
     const int i = B.order[s];
     Inst& I = desc[s];
     I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
     I.W = (float2*)(ws + L.W[i]);
     I.v = (float2*)(ws + L.v[i]);
-    I.psi = (float2*)(ws + L.psi[i]);
+    I.x = (float2*)(ws + L.psi[i]);
     I.psi_hat = (float2*)(ws + L.psi_hat[i]);
     I.z_hat = (float2*)(ws + L.z_hat[i]);
     I.y_hat = (float2*)(ws + L.y_hat[i]);
@@ -736,6 +787,7 @@ pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep
     I.maxt2 = (const float*)(ws + L.maxt2) + slot;
   }
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
   const Launcher K{*ctx, ws, L, B, st};
   static const int kOps[12][2] = {
       {0, pwf::ROW_PSI_UPDATE}, {1, pwf::COL_CHIRP1},      {0, pwf::ROW_MUL_T},      {1, pwf::COL_CHIRP2},
@@ -749,6 +801,96 @@ pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep
     }
   }
   return PWF_OK;
+}
+
+pwf_status pwf_set_column_tile(int32_t n, int32_t width) {
+  const int i = size_index(n);
+  if (i < 0) return PWF_ERR_SIZE;
+  if (width != 0 && !pwf::col_width_supported(n, width)) return PWF_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_col_width[i] = width;
+  return PWF_OK;
+}
+
+int32_t pwf_column_tile(int32_t n) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return col_width(n);
+}
+
+pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (reps < 1) return PWF_ERR_ARG;
+  Layout L;
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Batch B = group(problems, n);
+  std::vector<Inst> desc(n);
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
+    I.W = (float2*)(ws + L.W[i]);
+    I.v = (float2*)(ws + L.v[i]);
+    I.x = (float2*)(ws + L.psi[i]);
+    I.psi_hat = (float2*)(ws + L.psi_hat[i]);
+    I.z_hat = (float2*)(ws + L.z_hat[i]);
+    I.y_hat = (float2*)(ws + L.y_hat[i]);
+    I.loss_partial = (double*)(ws + L.part[i]);
+    I.maxt2 = (const float*)(ws + L.maxt2);
+  }
+  PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
+  // every field region (timing does not depend on the values)
+  PWF_HIP(pwf::launch_fill_zero(ws + L.W[0], L.extra0[0] - L.W[0], st));
+  hipEvent_t e0, e1;
+  PWF_HIP(hipEventCreate(&e0));
+  PWF_HIP(hipEventCreate(&e1));
+  pwf_status result = PWF_OK;
+  for (const Class& c : B.classes) {
+    Batch one;
+    one.order = B.order;
+    one.classes = {c};
+    const Launcher K{*ctx, ws, L, one, st};
+    const int idx = size_index(c.ny);
+    const int cands[2] = {pwf::col_default_width(c.ny), pwf::col_alt_width(c.ny)};
+    float best_ms = 0.f;
+    int best_w = cands[0];
+    for (int w : cands) {
+      if (c.nx % w) continue;
+      g_col_width[idx] = w;
+      auto run = [&]() -> pwf_status {
+        PWF_TRY(K.col(pwf::COL_CHIRP1));
+        PWF_TRY(K.col(pwf::COL_NESTEROV));
+        return PWF_OK;
+      };
+      result = run();  // warm-up
+      if (result != PWF_OK) break;
+      if (hipEventRecord(e0, st) != hipSuccess) { result = PWF_ERR_HIP; break; }
+      for (int r = 0; r < reps && result == PWF_OK; ++r) result = run();
+      if (result != PWF_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        result = PWF_ERR_HIP;
+        break;
+      }
+      if (best_ms == 0.f || ms < best_ms) {
+        best_ms = ms;
+        best_w = w;
+      }
+    }
+    g_col_width[idx] = best_w;
+    if (result != PWF_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return result;
 }
 
 pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi_out, int32_t iters,
@@ -781,7 +923,7 @@ pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi
   double* part = (double*)(ws + L.part[0]);
   int32_t* status = (int32_t*)(ws + L.status);
   const float2* twx = ctx->tw[size_index(nx)];
-  const float2* twy = ctx->tw[size_index(ny)];
+  const float2* twy = ctx->twc[size_index(ny)];
 
   PWF_HIP(pwf::launch_fill_zero(status, 16, st));
   PWF_HIP(pwf::launch_maxabs2((const float2*)p.diffuser, m, (float*)(ws + L.maxt2_part), (float*)(ws + L.maxt2), st));
@@ -841,6 +983,10 @@ void pwf_finalize(void) {
     for (auto& kv : c.graphs) hipGraphExecDestroy(kv.second);
     c.graphs.clear();
     for (float2*& t : c.tw) {
+      if (t) hipFree(t);
+      t = nullptr;
+    }
+    for (float2*& t : c.twc) {
       if (t) hipFree(t);
       t = nullptr;
     }

@@ -20,8 +20,9 @@ struct Inst {
   int32_t n_partials;   // number of loss partials (column tiles)
   float2* W;            // work field between sweeps
   float2* v;            // detector field v, saved by the forward for the gradient
-  float2* psi;          // real-space psi read by the gradient (x* = exp(psi)*)
+  float2* x;            // sample transmission x = exp(psi), saved for the gradient
   const float2* psi_src;// real-space psi that a forward pass starts from
+  float2* psi;          // real-space psi written by a state initialisation
   float2* psi_hat;      // spectrum of the extrapolated iterate psi
   float2* z_hat;        // spectrum of the gradient-step iterate z
   float2* y_hat;        // spectrum of the measured speckle
@@ -33,11 +34,18 @@ struct Inst {
   float2* out;          // real-space complex output of a final inverse pass
   double* loss_partial; // one FP64 partial per column tile
   double* loss_dst;     // loss destination (indexed by iteration), may be null
+  // 1-D factors of the separable windows, indexed by DFT bin (built per call)
+  float2* qx1; float2* qy1;  // exp(i theta_x), exp(i theta_y) of FreePropagation over L1
+  float2* qx2; float2* qy2;  // same over L2
+  float* ix; float* iy;      // IOTF factors exp(-c f^2)
+  float* gx; float* gy;      // 1 - STF factors, 1 - exp(-c f^2)
   // Fourier-domain constants (frequencies f in cycles/pixel)
   double chirp1_rev;    // L1 lambda / (2 p^2): revolutions per f^2 (paraxial part)
   double chirp2_rev;    // L2 lambda / (2 p^2)
   double s_coef;        // (lambda / p)^2: lambda^2 rho^2 = s_coef f^2
-  int32_t series;       // 1: evaluate 2/(1+sqrt(1-s)) by its power series
+  int32_t series;       // 1: separable chirp + power-series cross term; 0: direct FP64 chirp
+  float two_pi_a1, two_pi_a2;  // 2 pi chirp_rev (radians per f^2), FP32 copy for the cross term
+  float s_coef_f;
   float iotf_cx, iotf_cy;  // IOTF = exp(-(cx fx^2 + cy fy^2)), c = 2 pi^2 sigma^2
   float stf_cx, stf_cy;    // STF  = exp(-(cx fx^2 + cy fy^2)), c = 4 pi^2 gamma sigma^2
   float pinv_scale;        // s_P; negative: preconditioner off
@@ -113,14 +121,15 @@ template <> struct RowCfg<512>  { using Plan = FftPlan<512, 32, 16>;    static c
 template <> struct RowCfg<1024> { using Plan = FftPlan<1024, 32, 32>;   static constexpr int T = 32, RW = 8; };
 template <> struct RowCfg<2048> { using Plan = FftPlan<2048, 32, 8, 8>; static constexpr int T = 64, RW = 4; };
 
-// Column sweeps: T lanes per column, W adjacent columns per workgroup (lane
-// index = t * W + w, so the W columns of one row are one coalesced segment).
+// Column sweeps: T lanes per column and W adjacent columns per workgroup
+// (lane index = t * W + w, so the W columns of one row are one coalesced
+// segment).  Two tile widths are compiled per side; the launcher picks one.
 template <int N> struct ColCfg;
-template <> struct ColCfg<128>  { using Plan = FftPlan<128, 16, 8>;     static constexpr int T = 8,  W = 32; };
-template <> struct ColCfg<256>  { using Plan = FftPlan<256, 16, 16>;    static constexpr int T = 16, W = 16; };
-template <> struct ColCfg<512>  { using Plan = FftPlan<512, 32, 16>;    static constexpr int T = 16, W = 16; };
-template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 32, 32>;   static constexpr int T = 32, W = 16; };
-template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 32, 8, 8>; static constexpr int T = 64, W = 8; };
+template <> struct ColCfg<128>  { using Plan = FftPlan<128, 16, 8>;      static constexpr int T = 8,   WA = 32, WB = 16; };
+template <> struct ColCfg<256>  { using Plan = FftPlan<256, 16, 16>;     static constexpr int T = 16,  WA = 16, WB = 32; };
+template <> struct ColCfg<512>  { using Plan = FftPlan<512, 16, 8, 4>;   static constexpr int T = 32,  WA = 16, WB = 8; };
+template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  WA = 8,  WB = 4; };
+template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, WA = 4,  WB = 8; };
 
 // Arguments common to every sweep launch.
 struct Sweep {
@@ -129,7 +138,7 @@ struct Sweep {
   int32_t iter;           // iteration index within this call
   const double* beta;     // momentum table (Algorithm S1), indexed by k0 + iter
   const float2* tw_row;   // twiddles of the row plan (forward, then reversed plan)
-  const float2* tw_col;   // twiddles of the column plan
+  const float2* tw_col;   // twiddles of the column plan (forward, then reversed plan)
   int32_t* status;        // bit 0: non-finite loss seen
 };
 

@@ -45,9 +45,12 @@ enum PlainOp {
 };
 
 int row_rows_per_block(int n);
-int col_cols_per_block(int n);
+int col_default_width(int n);
+int col_alt_width(int n);
+bool col_width_supported(int n, int w);
 hipError_t launch_row(int nx, int op, int nblocks, const Sweep& S, hipStream_t st);
-hipError_t launch_col(int ny, int op, int nblocks, const Sweep& S, hipStream_t st);
+hipError_t launch_col(int ny, int width, int op, int nblocks, const Sweep& S, hipStream_t st);
+hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st);
 
 hipError_t launch_plain_rows(int nx, int dir, const float2* src, float2* dst, int ny, const float2* tw,
                              hipStream_t st);
@@ -64,8 +67,9 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 int maxabs2_blocks();
 hipError_t launch_maxabs2(const float2* t, size_t m, float* partial, float* out, hipStream_t st);
 
-// Number of float2 twiddles of the N-point plan (forward and reversed); fills
-// `out` when it is not null.  Returns -1 for unsupported N.
-int plan_twiddles(int n, float2* out);
+// Number of float2 twiddles of the N-point row (which = 0) or column (which =
+// 1) plan, forward and reversed; fills `out` when it is not null.  Returns -1
+// for unsupported N.
+int plan_twiddles(int n, int which, float2* out);
 
 }  // namespace pwf

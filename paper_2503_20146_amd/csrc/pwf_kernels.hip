@@ -133,20 +133,60 @@ __global__ void maxabs2_final(const float* __restrict__ partial, int np, float* 
   }
 }
 
+// 1-D factors of the separable windows of one instance (FP64 arguments).
+__global__ void build_tables_kernel(const Inst* __restrict__ insts) {
+  const Inst I = insts[blockIdx.x];
+  for (int k = threadIdx.x; k < I.nx + I.ny; k += blockDim.x) {
+    const bool isx = k < I.nx;
+    const int kk = isx ? k : k - I.nx;
+    const int n = isx ? I.nx : I.ny;
+    const double f = (double)(kk < (n >> 1) ? kk : kk - n) / (double)n;
+    const double f2 = f * f;
+    float2 q[2];
+    const double a[2] = {I.chirp1_rev, I.chirp2_rev};
+    for (int j = 0; j < 2; ++j) {
+      double rev = -a[j] * f2;
+      rev -= rint(rev);
+      float sn, cs;
+      sincosf((float)(rev * 6.283185307179586476925), &sn, &cs);
+      q[j] = make_float2(cs, sn);
+    }
+    const float cio = isx ? I.iotf_cx : I.iotf_cy;
+    const float cst = isx ? I.stf_cx : I.stf_cy;
+    const float ff = (float)f2;
+    if (isx) {
+      I.qx1[kk] = q[0];
+      I.qx2[kk] = q[1];
+      I.ix[kk] = expf(-cio * ff);
+      I.gx[kk] = -expm1f(-cst * ff);
+    } else {
+      I.qy1[kk] = q[0];
+      I.qy2[kk] = q[1];
+      I.iy[kk] = expf(-cio * ff);
+      I.gy[kk] = -expm1f(-cst * ff);
+    }
+  }
+}
+
+hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st) {
+  hipLaunchKernelGGL(build_tables_kernel, dim3(n), dim3(256), 0, st, insts);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ host dispatch
 
 #define PWF_DECLARE_SIDE(N)                                                                              \
   template <int M> hipError_t launch_row_n(int op, int nblocks, const Sweep& S, hipStream_t st);        \
-  template <int M> hipError_t launch_col_n(int op, int nblocks, const Sweep& S, hipStream_t st);        \
+  template <int M> hipError_t launch_col_n(int w, int op, int nblocks, const Sweep& S, hipStream_t st); \
   template <int M> hipError_t plain_rows_n(int dir, const float2* src, float2* dst, int ny,             \
                                            const float2* tw, hipStream_t st);                          \
   template <int M> hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, hipStream_t st); \
-  template <int M> int plan_twiddles_n(float2* out);                                                  \
+  template <int M> int plan_twiddles_n(int which, float2* out);                                       \
   extern template hipError_t launch_row_n<N>(int, int, const Sweep&, hipStream_t);                     \
-  extern template hipError_t launch_col_n<N>(int, int, const Sweep&, hipStream_t);                     \
+  extern template hipError_t launch_col_n<N>(int, int, int, const Sweep&, hipStream_t);                \
   extern template hipError_t plain_rows_n<N>(int, const float2*, float2*, int, const float2*, hipStream_t); \
   extern template hipError_t plain_cols_n<N>(int, float2*, int, const float2*, hipStream_t);           \
-  extern template int plan_twiddles_n<N>(float2*);
+  extern template int plan_twiddles_n<N>(int, float2*);
 PWF_DECLARE_SIDE(128)
 PWF_DECLARE_SIDE(256)
 PWF_DECLARE_SIDE(512)
@@ -165,13 +205,35 @@ int row_rows_per_block(int n) {
   }
 }
 
-int col_cols_per_block(int n) {
+int col_default_width(int n) {
   switch (n) {
-    case 128: return ColCfg<128>::W;
-    case 256: return ColCfg<256>::W;
-    case 512: return ColCfg<512>::W;
-    case 1024: return ColCfg<1024>::W;
-    case 2048: return ColCfg<2048>::W;
+    case 128: return ColCfg<128>::WA;
+    case 256: return ColCfg<256>::WA;
+    case 512: return ColCfg<512>::WA;
+    case 1024: return ColCfg<1024>::WA;
+    case 2048: return ColCfg<2048>::WA;
+    default: return 0;
+  }
+}
+
+bool col_width_supported(int n, int w) {
+  switch (n) {
+    case 128: return w == ColCfg<128>::WA || w == ColCfg<128>::WB;
+    case 256: return w == ColCfg<256>::WA || w == ColCfg<256>::WB;
+    case 512: return w == ColCfg<512>::WA || w == ColCfg<512>::WB;
+    case 1024: return w == ColCfg<1024>::WA || w == ColCfg<1024>::WB;
+    case 2048: return w == ColCfg<2048>::WA || w == ColCfg<2048>::WB;
+    default: return false;
+  }
+}
+
+int col_alt_width(int n) {
+  switch (n) {
+    case 128: return ColCfg<128>::WB;
+    case 256: return ColCfg<256>::WB;
+    case 512: return ColCfg<512>::WB;
+    case 1024: return ColCfg<1024>::WB;
+    case 2048: return ColCfg<2048>::WB;
     default: return 0;
   }
 }
@@ -187,13 +249,13 @@ hipError_t launch_row(int nx, int op, int nblocks, const Sweep& S, hipStream_t s
   }
 }
 
-hipError_t launch_col(int ny, int op, int nblocks, const Sweep& S, hipStream_t st) {
+hipError_t launch_col(int ny, int width, int op, int nblocks, const Sweep& S, hipStream_t st) {
   switch (ny) {
-    case 128: return launch_col_n<128>(op, nblocks, S, st);
-    case 256: return launch_col_n<256>(op, nblocks, S, st);
-    case 512: return launch_col_n<512>(op, nblocks, S, st);
-    case 1024: return launch_col_n<1024>(op, nblocks, S, st);
-    case 2048: return launch_col_n<2048>(op, nblocks, S, st);
+    case 128: return launch_col_n<128>(width, op, nblocks, S, st);
+    case 256: return launch_col_n<256>(width, op, nblocks, S, st);
+    case 512: return launch_col_n<512>(width, op, nblocks, S, st);
+    case 1024: return launch_col_n<1024>(width, op, nblocks, S, st);
+    case 2048: return launch_col_n<2048>(width, op, nblocks, S, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -260,13 +322,13 @@ hipError_t launch_maxabs2(const float2* t, size_t m, float* partial, float* out,
   return hipGetLastError();
 }
 
-int plan_twiddles(int n, float2* out) {
+int plan_twiddles(int n, int which, float2* out) {
   switch (n) {
-    case 128: return plan_twiddles_n<128>(out);
-    case 256: return plan_twiddles_n<256>(out);
-    case 512: return plan_twiddles_n<512>(out);
-    case 1024: return plan_twiddles_n<1024>(out);
-    case 2048: return plan_twiddles_n<2048>(out);
+    case 128: return plan_twiddles_n<128>(which, out);
+    case 256: return plan_twiddles_n<256>(which, out);
+    case 512: return plan_twiddles_n<512>(which, out);
+    case 1024: return plan_twiddles_n<1024>(which, out);
+    case 2048: return plan_twiddles_n<2048>(which, out);
     default: return -1;
   }
 }

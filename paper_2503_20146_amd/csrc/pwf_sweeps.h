@@ -1,7 +1,25 @@
 // Sweep kernel templates of the PWF hot path (instantiated once per grid side
 // in pwf_sweeps_<N>.hip so that the sides compile in parallel).
+//
+// Fused path: every iteration of Algorithm S1 is twelve sweeps over each
+// instance's fields.  A row sweep finishes the inverse 2-D FFT of the
+// previous Filter along x, applies the real-space step of the algorithm and
+// starts the next forward 2-D FFT along x; a column sweep does the y
+// transforms with the Fourier-domain window in between.  Sweeps S0..S11:
+//   S0 R  psi = IFFT(.); x = exp(psi) (saved); FFT      (Algorithm S1 loop head)
+//   S1 C  x Q_L1                                          (FreePropagation L1)
+//   S2 R  x t                                             (diffuser)
+//   S3 C  x Q_L2                                          (FreePropagation L2)
+//   S4 R  v saved; I = |v|^2                              (PhysicalModel)
+//   S5 C  R = IOTF I^ - Y^ (= F{-e}); loss += |R|^2/m; x IOTF   (Eq. 2, Filter(-e, IOTF))
+//   S6 R  h = Re(.); a = v h                              (WirtingerDerivative)
+//   S7 C  x conj Q_L2                                     (FreePropagation -L2)
+//   S8 R  x conj t
+//   S9 C  x conj Q_L1                                     (FreePropagation -L1)
+//   S10 R g = x* b / max|t|^2
+//   S11 C direction d (Preconditioner + Regularizer) and the Nesterov step on
+//         the spectra of psi and z; IFFT towards the next S0.
 #pragma once
-
 
 #include <hip/hip_runtime.h>
 
@@ -40,7 +58,7 @@ __device__ __forceinline__ float2 cexp_f(float2 p) {
 }
 
 template <int NX, int OP>
-__global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW) row_sweep(Sweep S) {
+__global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2) row_sweep(Sweep S) {
   using C = RowCfg<NX>;
   using Plan = typename C::Plan;
   constexpr int T = C::T, RW = C::RW, E = NX / T;
@@ -51,7 +69,7 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW) row_sweep(Swee
 
   const int inst = blockIdx.x / S.blocks_per_inst;
   const int blk = blockIdx.x - inst * S.blocks_per_inst;
-  const Inst& I = S.inst[inst];
+  const Inst I = S.inst[inst];  // by value: the fields stay in registers
   const int t = threadIdx.x % T, rw = threadIdx.x / T;
   const int row = blk * RW + rw;
   const LdsView lv{lds + rw * lds_len(NX), 1};
@@ -88,16 +106,16 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW) row_sweep(Swee
   }
 
   // real-space step; element e = c*R1 + q sits at x = t + T c + q M1
+  float inv_maxt2 = 0.f;
+  if constexpr (OP == ROW_GRAD) inv_maxt2 = 1.0f / *I.maxt2;
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
       constexpr int e = c * R1 + q;
       const size_t idx = rbase + t + T * c + q * M1;
-      if constexpr (OP == ROW_PSI_UPDATE) {
-        I.psi[idx] = v[e];
+      if constexpr (OP == ROW_PSI_UPDATE || OP == ROW_START) {
         v[e] = cexp_f(v[e]);
-      } else if constexpr (OP == ROW_START) {
-        v[e] = cexp_f(v[e]);
+        if (I.x) I.x[idx] = v[e];
       } else if constexpr (OP == ROW_MUL_T) {
         v[e] = cmul(v[e], I.t[idx]);
       } else if constexpr (OP == ROW_MUL_CONJ_T) {
@@ -110,14 +128,12 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW) row_sweep(Swee
         const float2 vv = I.v[idx];
         v[e] = make_float2(vv.x * h, vv.y * h);
       } else if constexpr (OP == ROW_GRAD) {
-        const float inv = 1.0f / *I.maxt2;
-        const float2 x = cexp_f(I.psi[idx]);
-        v[e] = cscale(cmulc(v[e], x), inv);
+        v[e] = cscale(cmulc(v[e], I.x[idx]), inv_maxt2);
         if (I.g_out) I.g_out[idx] = v[e];
       } else if constexpr (OP == ROW_FORWARD_OUT) {
         I.f_out[idx] = v[e].x;
       } else if constexpr (OP == ROW_CPLX_FFT) {
-        if (I.psi && I.psi != I.psi_src) I.psi[idx] = v[e];
+        if (I.psi) I.psi[idx] = v[e];
       } else if constexpr (OP == ROW_IFFT_OUT) {
         if (I.out) I.out[idx] = v[e];
       }
@@ -149,6 +165,13 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW) row_sweep(Swee
 
 // ------------------------------------------------------------------ column sweeps
 
+// Logical block of hardware block b in a grid of g blocks: XCD b % 8 gets the
+// contiguous range [(b % 8) g/8, (b % 8 + 1) g/8).  Identity when 8 does not divide g.
+__device__ __forceinline__ int xcd_contiguous(int b, int g) {
+  if (g & 7) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
 template <int OP> struct ColOpTraits;
 #define PWF_COL_TRAIT(op, inv) \
   template <> struct ColOpTraits<op> { static constexpr bool kInverse = inv; };
@@ -164,20 +187,42 @@ PWF_COL_TRAIT(COL_SPEC_YHAT, false)
 PWF_COL_TRAIT(COL_SPEC_PSIHAT, false)
 #undef PWF_COL_TRAIT
 
-template <int NY, int OP>
-__global__ void __launch_bounds__(ColCfg<NY>::T * ColCfg<NY>::W) col_sweep(Sweep S) {
+// Transfer function of FreePropagation at (fx, fy) from the 1-D factors:
+// Q = Qx(fx) Qy(fy) exp(i theta_c), where the cross term theta_c = -2 pi a rho^2
+// (2/(1+sqrt(1-s)) - 1) is below 1e-8 rad for X-ray geometries and is applied
+// as (1, theta_c).
+__device__ __forceinline__ float2 transfer_sep(float2 qx, float2 qy, float fx, float fy, float s_coef,
+                                               float two_pi_a) {
+  const float2 q = cmul(qx, qy);
+  const float rho2 = fx * fx + fy * fy;
+  const float s = s_coef * rho2;
+  const float thc = -two_pi_a * rho2 * s * (0.25f + 0.125f * s);
+  return make_float2(q.x - thc * q.y, q.y + thc * q.x);
+}
+
+// Geometries outside the series range use the FP64 formula per element.
+__device__ __noinline__ float2 transfer_direct(double chirp_rev, double s_coef, float fx, float fy) {
+  return transfer(chirp_rev, s_coef, 0, fx, fy, false);
+}
+
+template <int NY, int W, int OP>
+__global__ void __launch_bounds__(ColCfg<NY>::T * W, 2) col_sweep(Sweep S) {
   using C = ColCfg<NY>;
   using Plan = typename C::Plan;
-  constexpr int T = C::T, W = C::W, E = NY / T;
+  constexpr int T = C::T, E = NY / T;
   constexpr int R1 = Plan::radix[0], RL = Plan::radix[Plan::NPASS - 1];
   constexpr int M1 = NY / R1, ML = NY / RL;
   constexpr int NT = T * W;
   __shared__ float2 lds[W * lds_len(NY)];
-  __shared__ double red[NT / 64];
+  __shared__ double red[(NT + 63) / 64];
 
-  const int inst = blockIdx.x / S.blocks_per_inst;
-  const int tile = blockIdx.x - inst * S.blocks_per_inst;
-  const Inst& I = S.inst[inst];
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of tiles so that tiles sharing 128-byte lines meet in
+  // the same L2.
+  const int b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int inst = b / S.blocks_per_inst;
+  const int tile = b - inst * S.blocks_per_inst;
+  const Inst I = S.inst[inst];  // by value: the fields stay in registers
   const int nx = I.nx;
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int s = tile * W + w;
@@ -209,48 +254,40 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * ColCfg<NY>::W) col_sweep(Sweep
     const LdsView lm{lds + wm, W};
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      constexpr int c = e / RL, r = e % RL;
-      lv.at(t + T * c + r * ML) = v[e];
+      lv.at(t + T * (e / RL) + (e % RL) * ML) = v[e];
     });
     __syncthreads();
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      constexpr int c = e / RL, r = e % RL;
-      const int ky = t + T * c + r * ML;
-      const int kym = (NY - ky) & (NY - 1);
-      const float2 gm = lm.at(kym);
+      const int ky = t + T * (e / RL) + (e % RL) * ML;
+      const float2 gm = lm.at((NY - ky) & (NY - 1));
       const float P = pinv_of(I, fx, freq_of(ky, NY));
       const float a = 0.5f * (1.f + P), b = 0.5f * (1.f - P);
       // (1+P)/2 G + (1-P)/2 conj(G(-k)) = F{Re g} + i P F{Im g}
       v[e] = make_float2(a * v[e].x + b * gm.x, a * v[e].y - b * gm.y);
     });
     __syncthreads();
-    float2 ps[E];
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      constexpr int c = e / RL, r = e % RL;
-      const int ky = t + T * c + r * ML;
-      ps[e] = I.psi_hat[(size_t)ky * nx + s];
-      lv.at(ky) = ps[e];
+      const int ky = t + T * (e / RL) + (e % RL) * ML;
+      lv.at(ky) = I.psi_hat[(size_t)ky * nx + s];
     });
     __syncthreads();
-    const double beta = (OP == COL_NESTEROV) ? S.beta[I.k0 + S.iter] : 0.0;
-    const float bf = (float)beta;
+    const float bf = (OP == COL_NESTEROV) ? (float)S.beta[I.k0 + S.iter] : 0.f;
+    const float gxv = I.gx[kx];
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      constexpr int c = e / RL, r = e % RL;
-      const int ky = t + T * c + r * ML;
-      const int kym = (NY - ky) & (NY - 1);
-      const float2 pm = lm.at(kym);
-      const float g2 = gamma2_of(I, fx, freq_of(ky, NY));
+      const int ky = t + T * (e / RL) + (e % RL) * ML;
+      const float2 pk = lv.at(ky);
+      const float2 pm = lm.at((NY - ky) & (NY - 1));
+      const float g2 = gxv + (1.f - gxv) * I.gy[ky];   // 1 - STFx STFy without cancellation
       // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
-      const float2 reg = make_float2(I.alpha_c1 * ps[e].x + I.alpha_c2 * pm.x,
-                                     I.alpha_c1 * ps[e].y - I.alpha_c2 * pm.y);
+      const float2 reg = make_float2(I.alpha_c1 * pk.x + I.alpha_c2 * pm.x, I.alpha_c1 * pk.y - I.alpha_c2 * pm.y);
       const float2 d = make_float2(v[e].x + g2 * reg.x, v[e].y + g2 * reg.y);
       if constexpr (OP == COL_NESTEROV) {
         const size_t gi = (size_t)ky * nx + s;
         const float2 zp = I.z_hat[gi];
-        const float2 z = make_float2(ps[e].x - I.eta * d.x, ps[e].y - I.eta * d.y);
+        const float2 z = make_float2(pk.x - I.eta * d.x, pk.y - I.eta * d.y);
         const float2 pn = make_float2(z.x + bf * (z.x - zp.x), z.y + bf * (z.y - zp.y));
         I.z_hat[gi] = z;
         I.psi_hat[gi] = pn;
@@ -261,32 +298,55 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * ColCfg<NY>::W) col_sweep(Sweep
     });
     __syncthreads();
   } else {
-    static_for<0, E>([&](auto ee) {
-      constexpr int e = decltype(ee)::value;
-      constexpr int c = e / RL, r = e % RL;
-      const int ky = t + T * c + r * ML;
-      const float fy = freq_of(ky, NY);
-      if constexpr (OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ) {
-        const float2 q = transfer(I.chirp1_rev, I.s_coef, I.series, fx, fy, OP == COL_CHIRP1_CONJ);
-        v[e] = cscale(cmul(v[e], q), I.inv_m);
-      } else if constexpr (OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ) {
-        const float2 q = transfer(I.chirp2_rev, I.s_coef, I.series, fx, fy, OP == COL_CHIRP2_CONJ);
-        v[e] = cscale(cmul(v[e], q), I.inv_m);
-      } else if constexpr (OP == COL_BLUR) {
-        v[e] = cscale(v[e], iotf_of(I, fx, fy) * I.inv_m);
-      } else if constexpr (OP == COL_BLUR_LOSS) {
-        const float h = iotf_of(I, fx, fy);
-        const float2 yh = I.y_hat[(size_t)ky * nx + s];
-        const float2 rr = make_float2(h * v[e].x - yh.x, h * v[e].y - yh.y);
-        acc += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
-        v[e] = cscale(rr, h * I.inv_m);
-      } else if constexpr (OP == COL_SPEC_YHAT) {
-        I.y_hat[(size_t)ky * nx + s] = v[e];
-      } else if constexpr (OP == COL_SPEC_PSIHAT) {
-        I.psi_hat[(size_t)ky * nx + s] = v[e];
-        if (I.z_hat) I.z_hat[(size_t)ky * nx + s] = make_float2(0.f, 0.f);
+    float2 qx = make_float2(1.f, 0.f);
+    float ixv = 1.f;
+    if constexpr (OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ) qx = I.qx1[kx];
+    if constexpr (OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ) qx = I.qx2[kx];
+    if constexpr (OP == COL_BLUR || OP == COL_BLUR_LOSS) ixv = I.ix[kx];
+    constexpr bool CHIRP = OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ || OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ;
+    constexpr bool CONJ = OP == COL_CHIRP1_CONJ || OP == COL_CHIRP2_CONJ;
+    constexpr bool L1 = OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ;
+    if constexpr (CHIRP) {
+      const float2* __restrict__ qy = L1 ? I.qy1 : I.qy2;
+      const float two_pi_a = L1 ? I.two_pi_a1 : I.two_pi_a2;
+      if (I.series) {
+        static_for<0, E>([&](auto ee) {
+          constexpr int e = decltype(ee)::value;
+          const int ky = t + T * (e / RL) + (e % RL) * ML;
+          float2 q = transfer_sep(qx, qy[ky], fx, freq_of(ky, NY), I.s_coef_f, two_pi_a);
+          if (CONJ) q = cconj(q);
+          v[e] = cscale(cmul(v[e], q), I.inv_m);
+        });
+      } else {
+        const double a = L1 ? I.chirp1_rev : I.chirp2_rev;
+        static_for<0, E>([&](auto ee) {  // rare path: one out-of-line FP64 call per element
+          constexpr int e = decltype(ee)::value;
+          const int ky = t + T * (e / RL) + (e % RL) * ML;
+          float2 q = transfer_direct(a, I.s_coef, fx, freq_of(ky, NY));
+          if (CONJ) q = cconj(q);
+          v[e] = cscale(cmul(v[e], q), I.inv_m);
+        });
       }
-    });
+    } else {
+      static_for<0, E>([&](auto ee) {
+        constexpr int e = decltype(ee)::value;
+        const int ky = t + T * (e / RL) + (e % RL) * ML;
+        if constexpr (OP == COL_BLUR) {
+          v[e] = cscale(v[e], ixv * I.iy[ky] * I.inv_m);
+        } else if constexpr (OP == COL_BLUR_LOSS) {
+          const float h = ixv * I.iy[ky];
+          const float2 yh = I.y_hat[(size_t)ky * nx + s];
+          const float2 rr = make_float2(h * v[e].x - yh.x, h * v[e].y - yh.y);
+          acc += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
+          v[e] = cscale(rr, h * I.inv_m);
+        } else if constexpr (OP == COL_SPEC_YHAT) {
+          I.y_hat[(size_t)ky * nx + s] = v[e];
+        } else if constexpr (OP == COL_SPEC_PSIHAT) {
+          I.psi_hat[(size_t)ky * nx + s] = v[e];
+          if (I.z_hat) I.z_hat[(size_t)ky * nx + s] = make_float2(0.f, 0.f);
+        }
+      });
+    }
   }
 
   if constexpr (ColOpTraits<OP>::kInverse) {
@@ -317,7 +377,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * ColCfg<NY>::W) col_sweep(Sweep
 
 // Out-of-place FFT of every row (natural order in and out).
 template <int NX, int DIR>
-__global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW)
+__global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2)
 plain_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst, const float2* tw) {
   using C = RowCfg<NX>;
   using Plan = typename C::Plan;
@@ -354,11 +414,12 @@ plain_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst, const f
 
 // In-place FFT of every column (natural order).
 template <int NY, int DIR>
-__global__ void __launch_bounds__(ColCfg<NY>::T * ColCfg<NY>::W)
+__global__ void __launch_bounds__(ColCfg<NY>::T * ColCfg<NY>::WA, 2)
 plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw) {
   using C = ColCfg<NY>;
   using Plan = typename C::Plan;
-  constexpr int T = C::T, W = C::W, E = NY / T;
+  constexpr int T = C::T, W = C::WA, E = NY / T;
+  static_assert(T * W <= 1024, "workgroup too large");
   constexpr int R1 = Plan::radix[0], RL = Plan::radix[Plan::NPASS - 1];
   constexpr int M1 = NY / R1, ML = NY / RL;
   __shared__ float2 lds[W * lds_len(NY)];
@@ -404,12 +465,12 @@ hipError_t launch_row_n(int op, int nblocks, const Sweep& S, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int N>
-hipError_t launch_col_n(int op, int nblocks, const Sweep& S, hipStream_t st) {
+template <int N, int W>
+hipError_t launch_col_nw(int op, int nblocks, const Sweep& S, hipStream_t st) {
   using C = ColCfg<N>;
-  const dim3 grid(nblocks), block(C::T * C::W);
+  const dim3 grid(nblocks), block(C::T * W);
   switch (op) {
-#define PWF_CASE(o) case o: hipLaunchKernelGGL((col_sweep<N, o>), grid, block, 0, st, S); break;
+#define PWF_CASE(o) case o: hipLaunchKernelGGL((col_sweep<N, W, o>), grid, block, 0, st, S); break;
     PWF_CASE(COL_CHIRP1) PWF_CASE(COL_CHIRP2) PWF_CASE(COL_CHIRP2_CONJ) PWF_CASE(COL_CHIRP1_CONJ)
     PWF_CASE(COL_BLUR_LOSS) PWF_CASE(COL_BLUR) PWF_CASE(COL_NESTEROV) PWF_CASE(COL_DIRECTION)
     PWF_CASE(COL_SPEC_YHAT) PWF_CASE(COL_SPEC_PSIHAT)
@@ -417,6 +478,13 @@ hipError_t launch_col_n(int op, int nblocks, const Sweep& S, hipStream_t st) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_col_n(int width, int op, int nblocks, const Sweep& S, hipStream_t st) {
+  if (width == ColCfg<N>::WA) return launch_col_nw<N, ColCfg<N>::WA>(op, nblocks, S, st);
+  if (width == ColCfg<N>::WB) return launch_col_nw<N, ColCfg<N>::WB>(op, nblocks, S, st);
+  return hipErrorInvalidValue;
 }
 
 template <int N>
@@ -431,7 +499,7 @@ hipError_t plain_rows_n(int dir, const float2* src, float2* dst, int ny, const f
 template <int N>
 hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, hipStream_t st) {
   using C = ColCfg<N>;
-  const dim3 grid(nx / C::W), block(C::T * C::W);
+  const dim3 grid(nx / C::WA), block(C::T * C::WA);
   if (dir < 0) hipLaunchKernelGGL((plain_fft_cols<N, -1>), grid, block, 0, st, a, nx, tw);
   else hipLaunchKernelGGL((plain_fft_cols<N, 1>), grid, block, 0, st, a, nx, tw);
   return hipGetLastError();
@@ -449,18 +517,21 @@ static void fill_twiddles(float2* out) {
   }
 }
 
-// Twiddle tables of the N-point plan followed by those of its reversed plan.
+// Twiddle tables of an N-point plan followed by those of its reversed plan:
+// which = 0 for the row plan, 1 for the column plan.
 template <int N>
-int plan_twiddles_n(float2* out) {
-  using Plan = typename RowCfg<N>::Plan;
-  using RPlan = typename Reverse<Plan>::type;
-  static_assert(Plan::valid(), "radices must multiply to N");
-  static_assert(std::is_same<Plan, typename ColCfg<N>::Plan>::value, "row and column plans share tables");
-  if (out) {
-    fill_twiddles<Plan>(out);
-    fill_twiddles<RPlan>(out + Plan::tw_total());
-  }
-  return Plan::tw_total() + RPlan::tw_total();
+int plan_twiddles_n(int which, float2* out) {
+  auto emit = [&](auto tag) {
+    using Plan = decltype(tag);
+    using RPlan = typename Reverse<Plan>::type;
+    static_assert(Plan::valid(), "radices must multiply to N");
+    if (out) {
+      fill_twiddles<Plan>(out);
+      fill_twiddles<RPlan>(out + Plan::tw_total());
+    }
+    return Plan::tw_total() + RPlan::tw_total();
+  };
+  return which == 0 ? emit(typename RowCfg<N>::Plan{}) : emit(typename ColCfg<N>::Plan{});
 }
 
 }  // namespace pwf
