@@ -47,7 +47,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(sweep: int, pixels: int):
+def measured_traffic(sweep: int, pixels: int, width: int = 0):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None if stale."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
@@ -56,7 +56,8 @@ def measured_traffic(sweep: int, pixels: int):
         rec = json.load(fh)
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    ent = rec.get("sweeps", {}).get(str(sweep))
+    sweeps = rec.get("sweeps", {})
+    ent = sweeps.get(str(sweep)) or sweeps.get(f"{sweep}:{width}")
     if not ent:
         return None
     return ent["hbm_bytes_per_px"] * pixels
@@ -81,49 +82,52 @@ def autotune(batch) -> dict:
     return {n: lib.pwf_column_tile(n) for n in sorted({p.ny for p in batch.problems})}
 
 
-def _read_counter_csv(path: str, counter: str) -> dict:
-    """Per-kernel mean of `counter` over dispatches from a rocprofv3 counter_collection.csv."""
+def _read_counter_csv(path: str, counter: str):
+    """Per-kernel mean of `counter` over dispatches from a rocprofv3 counter_collection.csv,
+    and the largest single dispatch of a copy or fill kernel (the calibration launch)."""
     import csv
-    sums, counts = {}, {}
+    sums = {}
     with open(path) as fh:
         for row in csv.DictReader(fh):
             if row.get("Counter_Name") != counter:
                 continue
-            name = row["Kernel_Name"]
-            key = (name, row.get("Dispatch_Id"))
+            key = (row["Kernel_Name"], row.get("Dispatch_Id"))
             sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
     per_kernel = {}
+    calib = 0.0
     for (name, _), val in sums.items():
         per_kernel.setdefault(name, []).append(val)
-    return {k: sum(v) / len(v) for k, v in per_kernel.items()}
+        if "copy" in name.lower() or "elementwise" in name.lower():
+            calib = max(calib, val)
+    return {k: sum(v) / len(v) for k, v in per_kernel.items()}, calib
 
 
 def ingest_counters(fetch_csv: str, write_csv: str, projections: int) -> int:
     """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the copy-kernel calibration."""
-    fetch = _read_counter_csv(fetch_csv, "FETCH_SIZE")
-    write = _read_counter_csv(write_csv, "WRITE_SIZE")
-    copy_f = [v for k, v in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-    copy_w = [v for k, v in write.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-    if not copy_f or not copy_w:
-        print("no copy kernel in the counter files", file=sys.stderr)
+    fetch, copy_f = _read_counter_csv(fetch_csv, "FETCH_SIZE")
+    write, copy_w = _read_counter_csv(write_csv, "WRITE_SIZE")
+    if copy_f <= 0 or copy_w <= 0:
+        print("no calibration copy in the counter files", file=sys.stderr)
         return 1
+    # the calibration launch copies COPY_BYTES: scale each counter so it reads exactly that
     kib = COPY_BYTES / 1024.0
-    f_scale = kib / max(copy_f)
-    w_scale = kib / max(copy_w)
+    f_scale = kib / copy_f
+    w_scale = kib / copy_w
     pixels = projections * 1024 * 1024
     out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES,
            "fetch_scale": f_scale, "write_scale": w_scale, "pixels_per_launch": pixels, "sweeps": {}}
     for s, frag in enumerate(SWEEP_KERNELS):
-        names = [k for k in fetch if any(frag.format(w=w) in k for w in (4, 8, 16))]
-        if not names:
-            continue
-        name = names[0]
-        wname = [k for k in write if k == name]
-        fb = fetch[name] * 1024.0 * f_scale
-        wb = write[wname[0]] * 1024.0 * w_scale if wname else 0.0
-        out["sweeps"][str(s)] = {"kernel": name, "fetch_bytes": fb, "write_bytes": wb,
-                                 "hbm_bytes_per_px": (fb + wb) / pixels,
-                                 "algorithmic_bytes_per_px": SWEEP_BYTES_PER_PX[s]}
+        for w in (4, 8, 16):
+            names = [k for k in fetch if frag.format(w=w) in k]
+            if not names:
+                continue
+            name = names[0]
+            fb = fetch[name] * 1024.0 * f_scale
+            wb = write.get(name, 0.0) * 1024.0 * w_scale
+            key = f"{s}" if "row_sweep" in frag else f"{s}:{w}"
+            out["sweeps"][key] = {"kernel": name, "fetch_bytes": fb, "write_bytes": wb,
+                                  "hbm_bytes_per_px": (fb + wb) / pixels,
+                                  "algorithmic_bytes_per_px": SWEEP_BYTES_PER_PX[s]}
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
@@ -206,6 +210,8 @@ def main() -> int:
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs of a --sweep-only all run "
                          "into profiles/traffic_counters.json and exit")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--col-tile", type=int, default=0,
+                    help="fix the column-tile width at 1024 instead of autotuning (counter runs)")
     args = ap.parse_args()
 
     if args.ingest_counters:
@@ -224,7 +230,11 @@ def main() -> int:
     pixels = args.projections * geo.nx * geo.ny
 
     tiles = {}
-    if not args.no_autotune:
+    if args.col_tile:
+        from paper_2503_20146_amd import _lib
+        _lib.check(_lib.load().pwf_set_column_tile(1024, args.col_tile), "pwf_set_column_tile")
+        tiles = {1024: args.col_tile}
+    elif not args.no_autotune:
         tiles = autotune(batch)
         print(f"[bench] column tiles {tiles}", file=sys.stderr, flush=True)
 
@@ -272,7 +282,7 @@ def main() -> int:
     dom = max(range(12), key=lambda s: sweep_s[s])
     alg_bytes = SWEEP_BYTES_PER_PX[dom] * pixels
     achieved = alg_bytes / sweep_s[dom] / 1e9
-    traffic = measured_traffic(dom, pixels)
+    traffic = measured_traffic(dom, pixels, tiles.get(1024, 0))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": SWEEP_NAMES[dom], "launch_ms": round(sweep_s[dom] * 1e3, 4),
