@@ -137,6 +137,15 @@ pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* cons
                         void* const* g_out, void* const* d_out, double* loss_out, void* workspace,
                         size_t workspace_bytes, void* stream);
 
+/* Loss (Eq. 2) and its real gradient dL/dRe psi + i dL/dIm psi = 4 max|t|^2 g
+ * at psi, for automatic-differentiation wrappers (the forward fields are
+ * recomputed, nothing is kept between calls).
+ *   grad_out[i]  device complex64 [ny][nx]
+ *   loss_out     device float64 [n] or NULL */
+pwf_status pwf_loss_grad(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
+                         void* const* grad_out, double* loss_out, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
 /* Prepare states for pwf_step: psi = psi0 (or 0 when psi0 or psi0[i] is NULL),
  * z = 0, momentum scalar 1, k = 0 (Algorithm S1 initialisation), and the
  * spectrum of y.  states is a host array of n pwf_state. */
@@ -153,9 +162,15 @@ pwf_status pwf_step(const pwf_problem* problems, int32_t n, pwf_state* states, d
  *   psi_out[i]  device complex64 [ny][nx]: psi after the last iteration
  *   loss_hist   device float64 [n * iters] or NULL: loss at the psi entering
  *               each iteration, instance-major
- *   corr_tol    must be <= 0 (fixed iteration count); the correlation stop of
- *               the Methods section is not available in this entry point
- *   iters_done  host int32 [n] or NULL: receives iters for every instance
+ *   corr_tol    <= 0: fixed iteration count.  In (0, 1): stopping rule of the
+ *               Methods section ("Reconstruction procedure"; the paper uses
+ *               10^-0.00001): an instance stops after the first iteration whose
+ *               new exp(psi) has normalised correlation |<x_k, x_k-1>| /
+ *               (|x_k| |x_k-1|) above corr_tol with the previous one (FP64
+ *               sums); its later sweeps are skipped, psi_out holds that iterate
+ *               and loss_hist entries past its stop are left untouched.  The
+ *               call then synchronises on `stream` to fill iters_done.
+ *   iters_done  host int32 [n] or NULL: iterations done per instance
  * With graph mode on (the default) the whole loop is one hipGraph launch. */
 pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const* y, void* const* psi_out,
                      int32_t iters, double corr_tol, double* loss_hist, int32_t* iters_done, void* workspace,

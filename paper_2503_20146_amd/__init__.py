@@ -15,3 +15,4 @@ from .api import (  # noqa: F401
     set_graph_mode,
 )
 from ._lib import PwfError, load  # noqa: F401
+from .autograd import PWFLoss, pwf_loss  # noqa: F401

@@ -53,6 +53,7 @@ SIGNATURES = {
     "pwf_forward": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _vp, ctypes.c_size_t, _vp]),
     "pwf_gradient": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _P(_vp), _P(_vp), _vp, _vp,
                             ctypes.c_size_t, _vp]),
+    "pwf_loss_grad": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _P(_vp), _vp, _vp, ctypes.c_size_t, _vp]),
     "pwf_state_init": (_i32, [_P(pwf_problem), _i32, _P(pwf_state), _P(_vp), _P(_vp), _vp, ctypes.c_size_t, _vp]),
     "pwf_step": (_i32, [_P(pwf_problem), _i32, _P(pwf_state), _vp, _vp, ctypes.c_size_t, _vp]),
     "pwf_solve": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _i32, ctypes.c_double, _vp, _P(_i32), _vp,

@@ -159,16 +159,31 @@ class PWF:
             st["k"] = arr[i].k
         return loss
 
-    def solve(self, y, iters: int, psi_out=None, loss_hist: bool = True):
+    def solve(self, y, iters: int, psi_out=None, loss_hist: bool = True, corr_tol: float = 0.0,
+              return_iters: bool = False):
+        """Algorithm S1 from psi = 0.  ``corr_tol`` in (0, 1) enables the correlation stop."""
         psi_out = self._empty(torch.complex64) if psi_out is None else list(psi_out)
         hist = torch.empty((self.n, max(iters, 1)), dtype=torch.float64, device=self.device) if loss_hist else None
         done = (ctypes.c_int32 * self.n)()
         ws, nb = self._ws()
         check(self.lib.pwf_solve(self._c, self.n, _ptrs(y, torch.float32, self.shapes),
-                                 _ptrs(psi_out, torch.complex64, self.shapes), iters, 0.0,
+                                 _ptrs(psi_out, torch.complex64, self.shapes), iters, float(corr_tol),
                                  ctypes.c_void_p(hist.data_ptr()) if hist is not None else None, done, ws, nb,
                                  _stream(self.device)), "pwf_solve")
+        if return_iters:
+            return psi_out, hist, [done[i] for i in range(self.n)]
         return psi_out, hist
+
+    def loss_grad(self, psi, y):
+        """Loss and real gradient dL/dRe psi + i dL/dIm psi (forward fields recomputed)."""
+        grad = self._empty(torch.complex64)
+        loss = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        ws, nb = self._ws()
+        check(self.lib.pwf_loss_grad(self._c, self.n, _ptrs(psi, torch.complex64, self.shapes),
+                                     _ptrs(y, torch.float32, self.shapes), _ptrs(grad, torch.complex64, self.shapes),
+                                     ctypes.c_void_p(loss.data_ptr()), ws, nb, _stream(self.device)),
+              "pwf_loss_grad")
+        return loss, grad
 
     def solve_plain(self, y: torch.Tensor, iters: int, psi_out=None, loss_hist: bool = True):
         if self.n != 1:

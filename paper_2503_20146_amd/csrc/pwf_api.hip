@@ -185,7 +185,8 @@ size_t table_bytes(const pwf_problem& p) {
 
 struct Layout {
   size_t status = 0, maxt2 = 0, maxt2_part = 0, desc = 0, partials = 0;
-  std::vector<size_t> W, psi_hat, z_hat, v, psi, y_hat, extra0, extra1, part, tables;
+  std::vector<size_t> W, psi_hat, z_hat, v, psi, y_hat, extra0, extra1, part, tables, corr;
+  size_t stop = 0;
   size_t total = 0;
 };
 
@@ -214,6 +215,13 @@ Layout make_layout(const pwf_problem* probs, int n) {
     L.tables[i] = off;
     off += table_bytes(probs[i]);
   }
+  L.corr.resize(n);
+  for (int i = 0; i < n; ++i) {
+    L.corr[i] = off;
+    off += align_up(sizeof(double) * 4 * (size_t)probs[i].geom.ny);
+  }
+  L.stop = off;
+  off += align_up(sizeof(int32_t) * n);
   auto region = [&](std::vector<size_t>& r) {
     r.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -315,6 +323,7 @@ struct Launcher {
   const Layout& L;
   const Batch& B;
   hipStream_t st;
+  double corr_tol = 0.0;
   Inst* dev_desc() const { return (Inst*)(ws + L.desc); }
   int32_t* status() const { return (int32_t*)(ws + L.status); }
 
@@ -327,6 +336,7 @@ struct Launcher {
     S.tw_col = ctx.twc[size_index(c.ny)];
     S.status = status();
     S.blocks_per_inst = 0;
+    S.corr_tol = corr_tol;
     return S;
   }
   pwf_status row(int op, int iter = 0) const {
@@ -517,6 +527,59 @@ pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* cons
   return PWF_OK;
 }
 
+pwf_status pwf_loss_grad(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
+                         void* const* grad_out, double* loss_out, void* workspace, size_t workspace_bytes,
+                         void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!psi || !y || !grad_out) return PWF_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!psi[i] || !y[i] || !grad_out[i]) return PWF_ERR_ARG;
+  Layout L;
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const Batch B = group(problems, n);
+  std::vector<Inst> desc(n);
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
+    I.W = (float2*)(ws + L.W[i]);
+    I.v = (float2*)(ws + L.v[i]);
+    I.x = (float2*)(ws + L.psi[i]);
+    I.psi_src = (const float2*)psi[i];
+    I.y_hat = (float2*)(ws + L.y_hat[i]);
+    I.y = y[i];
+    I.g_out = (float2*)grad_out[i];
+    I.grad_mul = 4.0f;  // dL/dRe psi + i dL/dIm psi = 4 x* P1+(t* P2+(v Filter(-e)))
+    I.maxt2 = (const float*)(ws + L.maxt2);
+    I.loss_partial = (double*)(ws + L.part[i]);
+    I.loss_dst = loss_out ? loss_out + i : nullptr;
+  }
+  PWF_HIP(pwf::launch_fill_zero(ws + L.status, 16, st));
+  PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
+  const Launcher K{*ctx, ws, L, B, st};
+  PWF_TRY(K.row(pwf::ROW_REAL_FFT));
+  PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
+  PWF_TRY(K.row(pwf::ROW_START));
+  PWF_TRY(K.col(pwf::COL_CHIRP1));
+  PWF_TRY(K.row(pwf::ROW_MUL_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP2));
+  PWF_TRY(K.row(pwf::ROW_INTENSITY));
+  PWF_TRY(K.col(pwf::COL_BLUR_LOSS));
+  PWF_TRY(K.row(pwf::ROW_BACKBLUR));
+  PWF_TRY(K.col(pwf::COL_CHIRP2_CONJ));
+  PWF_TRY(K.row(pwf::ROW_MUL_CONJ_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP1_CONJ));
+  PWF_TRY(K.row(pwf::ROW_GRAD));
+  return PWF_OK;
+}
+
 pwf_status pwf_state_init(const pwf_problem* problems, int32_t n, pwf_state* states, const void* const* psi0,
                           const float* const* y, void* workspace, size_t workspace_bytes, void* stream) {
   PWF_TRY(validate_batch(problems, n));
@@ -655,7 +718,8 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
                      int32_t iters, double corr_tol, double* loss_hist, int32_t* iters_done, void* workspace,
                      size_t workspace_bytes, void* stream) {
   PWF_TRY(validate_batch(problems, n));
-  if (!y || !psi_out || iters < 0 || iters > kBetaCap || corr_tol > 0 || std::isnan(corr_tol)) return PWF_ERR_ARG;
+  if (!y || !psi_out || iters < 0 || iters > kBetaCap || std::isnan(corr_tol) || corr_tol >= 1.0) return PWF_ERR_ARG;
+  const bool corr_mode = corr_tol > 0.0;
   for (int i = 0; i < n; ++i)
     if (!y[i] || !psi_out[i]) return PWF_ERR_ARG;
   Layout L;
@@ -682,6 +746,11 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
     I.out = (float2*)psi_out[i];
     I.loss_partial = (double*)(ws + L.part[i]);
     I.loss_dst = loss_hist ? loss_hist + (size_t)i * iters : nullptr;
+    if (corr_mode) {
+      I.corr_partial = (double*)(ws + L.corr[i]);
+      I.n_corr_partials = problems[i].geom.ny / pwf::row_rows_per_block(problems[i].geom.nx);
+      I.stop_iter = (int32_t*)(ws + L.stop) + i;
+    }
   }
   // maxt2 slots depend only on the diffuser pointers; fill desc before upload
   {
@@ -704,15 +773,37 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
     for (int i = 0; i < n; ++i) iters_done[i] = iters;
 
   auto enqueue = [&](hipStream_t s) -> pwf_status {
-    const Launcher K{*ctx, ws, L, B, s};
+    Launcher K{*ctx, ws, L, B, s};
+    K.corr_tol = corr_tol;
+    if (corr_mode) PWF_HIP(pwf::launch_fill_zero(ws + L.stop, align_up(sizeof(int32_t) * n), s));
     std::vector<Inst> tmp = desc;
     PWF_TRY(launch_maxt2(problems, n, B, tmp, ws, L, s));
     return solve_sequence(K, problems, n, desc, iters);
   };
 
-  if (!g_graph_mode) return enqueue(st);
+  auto report = [&]() -> pwf_status {
+    if (!corr_mode || !iters_done) return PWF_OK;
+    std::vector<int32_t> stop(n);
+    PWF_HIP(hipMemcpyAsync(stop.data(), ws + L.stop, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    PWF_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) iters_done[i] = stop[i] > 0 ? stop[i] : iters;
+    return PWF_OK;
+  };
+
+  if (!g_graph_mode) {
+    PWF_TRY(enqueue(st));
+    return report();
+  }
 
   GraphKey key{workspace, n, iters, {}};
+  key.dims.push_back(corr_mode ? 1 : 0);
+  {
+    int64_t bits;
+    std::memcpy(&bits, &corr_tol, sizeof(bits));
+    key.dims.push_back((int)(bits & 0x7fffffff));
+    key.dims.push_back((int)((bits >> 31) & 0x7fffffff));
+    key.dims.push_back((int)(bits >> 62));
+  }
   for (int s = 0; s < n; ++s) {
     const pwf_problem& p = problems[B.order[s]];
     key.dims.push_back(p.geom.nx);
@@ -748,7 +839,7 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
   PWF_HIP(hipGraphLaunch(exec, ctx->side));
   PWF_HIP(hipEventRecord(ctx->ev_out, ctx->side));
   PWF_HIP(hipStreamWaitEvent(st, ctx->ev_out, 0));
-  return PWF_OK;
+  return report();
 }
 
 pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep, int32_t reps, void* workspace,

@@ -34,6 +34,10 @@ struct Inst {
   float2* out;          // real-space complex output of a final inverse pass
   double* loss_partial; // one FP64 partial per column tile
   double* loss_dst;     // loss destination (indexed by iteration), may be null
+  double* corr_partial; // 4 FP64 partials per row block for the stopping correlation, or null
+  int32_t* stop_iter;   // device: iteration at which the correlation stop fired (0 = running), or null
+  int32_t n_corr_partials;
+  float grad_mul;       // > 0: S10 scales by this instead of 1/max|t|^2
   // 1-D factors of the separable windows, indexed by DFT bin (built per call)
   float2* qx1; float2* qy1;  // exp(i theta_x), exp(i theta_y) of FreePropagation over L1
   float2* qx2; float2* qy2;  // same over L2
@@ -140,6 +144,12 @@ struct Sweep {
   const float2* tw_row;   // twiddles of the row plan (forward, then reversed plan)
   const float2* tw_col;   // twiddles of the column plan (forward, then reversed plan)
   int32_t* status;        // bit 0: non-finite loss seen
+  double corr_tol;        // stopping correlation threshold (used when corr_partial is set)
 };
+
+// True when the instance has met the correlation stop: its sweeps are skipped.
+__device__ __forceinline__ bool instance_stopped(const Inst& I) {
+  return I.stop_iter != nullptr && *(volatile const int32_t*)I.stop_iter != 0;
+}
 
 }  // namespace pwf

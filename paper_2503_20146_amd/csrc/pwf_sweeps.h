@@ -70,6 +70,7 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2) row_sweep(S
   const int inst = blockIdx.x / S.blocks_per_inst;
   const int blk = blockIdx.x - inst * S.blocks_per_inst;
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
+  if (instance_stopped(I)) return;  // uniform over the workgroup
   const int t = threadIdx.x % T, rw = threadIdx.x / T;
   const int row = blk * RW + rw;
   const LdsView lv{lds + rw * lds_len(NX), 1};
@@ -107,13 +108,29 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2) row_sweep(S
 
   // real-space step; element e = c*R1 + q sits at x = t + T c + q M1
   float inv_maxt2 = 0.f;
-  if constexpr (OP == ROW_GRAD) inv_maxt2 = 1.0f / *I.maxt2;
+  if constexpr (OP == ROW_GRAD) inv_maxt2 = I.grad_mul > 0.f ? I.grad_mul : 1.0f / *I.maxt2;
+  // stopping correlation of exp(psi) with the previous iterate (FP64 sums)
+  const bool corr = (OP == ROW_PSI_UPDATE) && I.corr_partial != nullptr;
+  const bool corr_sum = corr && S.iter > 0;
+  double c_re = 0.0, c_im = 0.0, n_new = 0.0, n_old = 0.0;
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
       constexpr int e = c * R1 + q;
       const size_t idx = rbase + t + T * c + q * M1;
-      if constexpr (OP == ROW_PSI_UPDATE || OP == ROW_START) {
+      if constexpr (OP == ROW_PSI_UPDATE) {
+        if (corr) I.out[idx] = v[e];  // psi of this iterate, kept in case the stop fires
+        const float2 xn = cexp_f(v[e]);
+        if (corr_sum) {
+          const float2 xo = I.x[idx];
+          c_re += (double)xn.x * xo.x + (double)xn.y * xo.y;
+          c_im += (double)xn.x * xo.y - (double)xn.y * xo.x;
+          n_new += (double)xn.x * xn.x + (double)xn.y * xn.y;
+          n_old += (double)xo.x * xo.x + (double)xo.y * xo.y;
+        }
+        v[e] = xn;
+        if (I.x) I.x[idx] = v[e];
+      } else if constexpr (OP == ROW_START) {
         v[e] = cexp_f(v[e]);
         if (I.x) I.x[idx] = v[e];
       } else if constexpr (OP == ROW_MUL_T) {
@@ -149,6 +166,25 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2) row_sweep(S
         dst[col_of_kx(t + T * c + r * ML, NX)] = v[c * RL + r];
       });
     });
+  }
+
+  if constexpr (OP == ROW_PSI_UPDATE) {
+    if (corr_sum) {
+      // deterministic block reduction of the four sums -> corr_partial[blk]
+      __shared__ double cred[4][RW * T / 64 + 1];
+      double vals[4] = {c_re, c_im, n_new, n_old};
+      for (int j = 0; j < 4; ++j) {
+        double a = vals[j];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        if ((threadIdx.x & 63) == 0) cred[j][threadIdx.x >> 6] = a;
+      }
+      __syncthreads();
+      if (threadIdx.x < 4) {
+        double a = 0.0;
+        for (int i = 0; i < RW * T / 64; ++i) a += cred[threadIdx.x][i];
+        I.corr_partial[4 * blk + threadIdx.x] = a;
+      }
+    }
   }
 
   if constexpr (OP == ROW_BACKBLUR) {
@@ -223,7 +259,19 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, 2) col_sweep(Sweep S) {
   const int inst = b / S.blocks_per_inst;
   const int tile = b - inst * S.blocks_per_inst;
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
+  if (instance_stopped(I)) return;  // uniform over the workgroup
   const int nx = I.nx;
+  if constexpr (OP == COL_CHIRP1) {
+    // Stopping rule (Methods, "Reconstruction procedure"): |<x_k, x_k-1>| /
+    // (|x_k| |x_k-1|) above the threshold, from the FP64 partials of S0.
+    if (I.corr_partial && S.iter > 0 && tile == 0 && threadIdx.x == 0) {
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < I.n_corr_partials; ++i)
+        for (int j = 0; j < 4; ++j) a[j] += I.corr_partial[4 * i + j];
+      const double c = sqrt(a[0] * a[0] + a[1] * a[1]) / sqrt(a[2] * a[3]);
+      if (c > S.corr_tol) *I.stop_iter = S.iter;
+    }
+  }
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int s = tile * W + w;
   const LdsView lv{lds + w, W};

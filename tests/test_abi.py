@@ -100,7 +100,9 @@ def test_bad_workspace_and_pointers(lib):
     assert lib.pwf_forward(arr, 1, null, ptrs, ctypes.c_void_p(0x100000), size, None) == -1
     assert lib.pwf_forward(None, 1, ptrs, ptrs, ctypes.c_void_p(0x100000), size, None) == -1
     assert lib.pwf_solve(arr, 1, ptrs, ptrs, -1, 0.0, None, None, ctypes.c_void_p(0x100000), size, None) == -1
-    assert lib.pwf_solve(arr, 1, ptrs, ptrs, 5, 0.5, None, None, ctypes.c_void_p(0x100000), size, None) == -1
+    assert lib.pwf_solve(arr, 1, ptrs, ptrs, 5, 1.5, None, None, ctypes.c_void_p(0x100000), size, None) == -1
+    assert lib.pwf_solve(arr, 1, ptrs, ptrs, 5, float("nan"), None, None, ctypes.c_void_p(0x100000), size,
+                         None) == -1
     assert lib.pwf_sync_status(ctypes.c_void_p(0x100001), None) == -4
 
 

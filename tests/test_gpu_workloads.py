@@ -1,0 +1,134 @@
+"""Parity at the workloads' full sizes and launch configurations, on sampled outputs.
+
+* 180 projections x 1024^2 in one batched, graph-captured solve of 100 iterations (the
+  configuration bench.py times): projection 90 against the oracle, projection 0 bit for
+  bit against its unbatched solve.
+* 64 uneven ROIs (24 x 512^2, 32 x 1024^2, 8 x 2048^2) in one batch: one instance per
+  size class against the oracle and bit for bit against its unbatched solve.
+* The correlation stop of the Methods section against the oracle's.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from gpu_helpers import device, gpu_problem, instance, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+PHASE_TOL = 1e-3
+
+
+def _rms(a, b):
+    return float(np.sqrt(np.mean(np.abs(np.asarray(a) - np.asarray(b)) ** 2)))
+
+
+def test_tomographic_batch_180x1024_in_bench_configuration():
+    import torch
+    from paper_2503_20146_amd import PWF, problem_from_geometry
+    dev = device()
+    n_proj, iters, checked = 180, 100, (0, 90)
+    say("workload 180 x 1024^2: generating projections")
+    d = S.tomo_projection_inputs(2, range(n_proj))
+    geo = d["geometry"]
+    t = torch.from_numpy(d["t"]).to(dev)
+    probs = [problem_from_geometry(geo, t) for _ in range(n_proj)]
+    batch = PWF(probs)
+    # measured speckle: oracle forward for the checked projections, GPU forward elsewhere
+    psi_true = [torch.from_numpy(p.astype(np.complex64)).to(dev) for p in d["psi_true"]]
+    f = batch.forward(psi_true)
+    oprob = O.make_problem(d["t"], geo)
+    ys = []
+    for j in range(n_proj):
+        if j in checked:
+            fj, _, _ = O.physical_model(d["psi_true"][j], oprob)
+        else:
+            fj = f[j].cpu().numpy()
+        ys.append(to_dev(S.poisson_intensity(fj, d["seed_keys"][j]), dev))
+    del f, psi_true
+    say("workload 180 x 1024^2: batched solve, 100 iterations")
+    out, hist = batch.solve(ys, iters)
+    torch.cuda.synchronize()
+    psi90 = out[90].cpu().numpy()
+    psi0 = out[0].clone()
+    h90 = hist[90].cpu().numpy()
+    del out
+    say("workload 180 x 1024^2: projection 0 unbatched")
+    one, _ = PWF([probs[0]]).solve([ys[0]], iters)
+    assert torch.equal(one[0], psi0)
+    say("workload 180 x 1024^2: oracle on projection 90")
+    y90 = ys[90].cpu().numpy()
+    psi_ref, hist_ref, _ = O.pwf(y90, oprob, iters)
+    assert _rms(psi90.imag, psi_ref.imag) <= PHASE_TOL
+    assert _rms(psi90.real, psi_ref.real) <= PHASE_TOL
+    assert np.max(np.abs(h90 - hist_ref) / hist_ref) <= 1e-4
+
+
+def test_uneven_roi_batch_64_instances():
+    import torch
+    from paper_2503_20146_amd import PWF
+    dev = device()
+    iters = 20
+    specs = S.roi_batch_specs()
+    say("uneven ROI batch: generating 64 instances")
+    probs, ys, keep = [], [], {}
+    checked = {0: None, 24: None, 56: None}   # first instance of each size class
+    for i, (side, sigma) in enumerate(specs):
+        inp = S.instance_inputs(3, side, instance=i, sigma_px=sigma)
+        geo = inp["geometry"]
+        prob = O.make_problem(inp["t"], geo)
+        f, _, _ = O.physical_model(inp["psi_true"], prob)
+        y = S.poisson_intensity(f, inp["seed_key"])
+        probs.append(gpu_problem(geo, inp["t"], dev))
+        ys.append(to_dev(y, dev))
+        if i in checked:
+            keep[i] = (prob, y)
+    say("uneven ROI batch: batched solve")
+    out, hist = PWF(probs).solve(ys, iters)
+    torch.cuda.synchronize()
+    for i, (prob, y) in keep.items():
+        say(f"uneven ROI batch: instance {i} ({specs[i][0]}^2) unbatched and oracle")
+        one, _ = PWF([probs[i]]).solve([ys[i]], iters)
+        assert torch.equal(one[0], out[i]), i
+        psi_ref, hist_ref, _ = O.pwf(y, prob, iters)
+        psi = out[i].cpu().numpy()
+        assert _rms(psi.imag, psi_ref.imag) <= PHASE_TOL, i
+        assert _rms(psi.real, psi_ref.real) <= PHASE_TOL, i
+        assert np.max(np.abs(hist[i].cpu().numpy() - hist_ref) / hist_ref) <= 1e-4, i
+
+
+# On the 128^2 workload 1 - correlation runs 1.0e-4, 1.5e-5, 5.9e-6, ... 9.9e-7 (10th
+# iteration), ... 6.0e-7 (17th): the paper's threshold stops after 2 iterations, the
+# others after 10 and 17, each with a clear margin to the neighbouring iterations.
+@pytest.mark.parametrize("tol", [O.PAPER_STOP_CORR, 1.0 - 1e-6, 1.0 - 6e-7])
+def test_correlation_stop_matches_oracle(tol):
+    from paper_2503_20146_amd import PWF
+    dev = device()
+    inp, geo, prob, y = instance(0)
+    say(f"correlation stop {tol}")
+    psi_ref, hist_ref, st = O.pwf(y, prob, 400, corr_tol=tol)
+    k_ref = len(hist_ref)
+    batch = PWF([gpu_problem(geo, inp["t"], dev)])
+    out, hist, done = batch.solve([to_dev(y, dev)], 400, corr_tol=tol, return_iters=True)
+    assert 1 <= k_ref < 400
+    assert done[0] == k_ref, (done[0], k_ref)
+    assert _rms(out[0].cpu().numpy(), psi_ref) <= PHASE_TOL
+    assert np.max(np.abs(hist[0, :k_ref].cpu().numpy() - hist_ref) / hist_ref) <= 1e-4
+
+
+def test_correlation_stop_per_instance_in_a_batch():
+    """Instances stop independently; stopped ones keep their iterate while others run."""
+    import torch
+    from paper_2503_20146_amd import PWF
+    dev = device()
+    say("correlation stop, batch of 3")
+    items = [instance(0, instance=i) for i in range(3)]
+    probs = [gpu_problem(x[1], x[0]["t"], dev) for x in items]
+    ys = [to_dev(x[3], dev) for x in items]
+    tol = 1.0 - 6e-7
+    out, hist, done = PWF(probs).solve(ys, 300, corr_tol=tol, return_iters=True)
+    for i in range(3):
+        one, _, d1 = PWF([probs[i]]).solve([ys[i]], 300, corr_tol=tol, return_iters=True)
+        assert d1[0] == done[i]
+        assert torch.equal(one[0], out[i])
