@@ -57,6 +57,7 @@ struct Context {
   bool ready = false;
   float2* tw[5] = {};          // row-plan twiddle tables per supported side
   float2* twc[5] = {};         // column-plan twiddle tables per supported side
+  float2* twa[5] = {};         // alternative row-plan twiddle tables per supported side
   double* beta = nullptr;      // momentum table
   hipStream_t side = nullptr;  // internal stream for graph launches
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -97,8 +98,8 @@ pwf_status context_for_current(Context** out) {
   Context& c = g_ctx[dev];
   if (!c.ready) {
     for (int i = 0; i < 5; ++i) {
-      for (int which = 0; which < 2; ++which) {
-        float2*& dst = which == 0 ? c.tw[i] : c.twc[i];
+      for (int which = 0; which < 3; ++which) {
+        float2*& dst = which == 0 ? c.tw[i] : which == 1 ? c.twc[i] : c.twa[i];
         const int cnt = pwf::plan_twiddles(kSizes[i], which, nullptr);
         std::vector<float2> host(std::max(cnt, 1));
         pwf::plan_twiddles(kSizes[i], which, host.data());
@@ -259,6 +260,14 @@ Inst base_inst(const pwf_problem& p) {
   I.chirp2_rev = g.z2_m * g.wavelength_m / (2.0 * p2);
   I.s_coef = (g.wavelength_m / g.pixel_m) * (g.wavelength_m / g.pixel_m);
   I.series = (0.5 * I.s_coef < 1e-4) ? 1 : 0;
+  {
+    // cross term of the separable chirp at the corner bin (rho^2 = 1/2), its
+    // largest value: applied only where it reaches a quarter ulp of 1 (2^-26)
+    const double s_max = 0.5 * I.s_coef;
+    const double a_max = 2.0 * M_PI * std::max(I.chirp1_rev, I.chirp2_rev);
+    const double th_max = a_max * 0.5 * s_max * (0.25 + 0.125 * s_max);
+    I.cross = th_max >= std::ldexp(1.0, -26) ? 1 : 0;
+  }
   I.two_pi_a1 = (float)(2.0 * M_PI * I.chirp1_rev);
   I.two_pi_a2 = (float)(2.0 * M_PI * I.chirp2_rev);
   I.s_coef_f = (float)I.s_coef;
@@ -333,6 +342,7 @@ struct Launcher {
     S.iter = iter;
     S.beta = ctx.beta;
     S.tw_row = ctx.tw[size_index(c.nx)];
+    S.tw_alt = ctx.twa[size_index(c.nx)];
     S.tw_col = ctx.twc[size_index(c.ny)];
     S.status = status();
     S.blocks_per_inst = 0;
@@ -342,7 +352,7 @@ struct Launcher {
   pwf_status row(int op, int iter = 0) const {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
-      S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx);
+      S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx, op);
       PWF_HIP(pwf::launch_row(c.nx, op, S.blocks_per_inst * c.count, S, st));
     }
     return PWF_OK;
@@ -748,7 +758,7 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
     I.loss_dst = loss_hist ? loss_hist + (size_t)i * iters : nullptr;
     if (corr_mode) {
       I.corr_partial = (double*)(ws + L.corr[i]);
-      I.n_corr_partials = problems[i].geom.ny / pwf::row_rows_per_block(problems[i].geom.nx);
+      I.n_corr_partials = problems[i].geom.ny / pwf::row_rows_per_block(problems[i].geom.nx, pwf::ROW_PSI_UPDATE);
       I.stop_iter = (int32_t*)(ws + L.stop) + i;
     }
   }
@@ -1078,6 +1088,10 @@ void pwf_finalize(void) {
       t = nullptr;
     }
     for (float2*& t : c.twc) {
+      if (t) hipFree(t);
+      t = nullptr;
+    }
+    for (float2*& t : c.twa) {
       if (t) hipFree(t);
       t = nullptr;
     }

@@ -48,6 +48,7 @@ struct Inst {
   double chirp2_rev;    // L2 lambda / (2 p^2)
   double s_coef;        // (lambda / p)^2: lambda^2 rho^2 = s_coef f^2
   int32_t series;       // 1: separable chirp + power-series cross term; 0: direct FP64 chirp
+  int32_t cross;        // 1: the cross term can change an FP32 result and is applied
   float two_pi_a1, two_pi_a2;  // 2 pi chirp_rev (radians per f^2), FP32 copy for the cross term
   float s_coef_f;
   float iotf_cx, iotf_cy;  // IOTF = exp(-(cx fx^2 + cy fy^2)), c = 2 pi^2 sigma^2
@@ -58,6 +59,29 @@ struct Inst {
   float inv_m;             // 1/(nx ny)
   double inv_m_d;
 };
+
+// Loads and stores through the global address space, element i of a field
+// at a 32-bit byte offset from its base.  Descriptor fields are generic
+// pointers; without the cast the compiler emits flat instructions, which count
+// against both the memory and the LDS wait counters.  With a workgroup-uniform
+// base and a 32-bit offset it uses the scalar-base form of the global access
+// instead of a 64-bit address per element.  Every field is below 4 GiB
+// (sides up to 2048).
+typedef float pwf_fv2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) pwf_fv2 pwf_gfv2;
+typedef __attribute__((address_space(1))) float pwf_gf;
+__device__ __forceinline__ float2 gld(const float2* p, uint32_t i) {
+  const pwf_fv2 v = *(const pwf_gfv2*)((const char*)p + (i << 3));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(float2* p, uint32_t i, float2 a) {
+  pwf_fv2 v;
+  v.x = a.x;
+  v.y = a.y;
+  *(pwf_gfv2*)((char*)p + (i << 3)) = v;
+}
+__device__ __forceinline__ float gldf(const float* p, uint32_t i) { return *(const pwf_gf*)((const char*)p + (i << 2)); }
+__device__ __forceinline__ void gstf(float* p, uint32_t i, float a) { *(pwf_gf*)((char*)p + (i << 2)) = a; }
 
 // Paired column order of x-spectra: kx = 0 -> 0, kx = n/2 -> 1,
 // 0 < kx < n/2 -> 2 kx, n/2 < kx < n -> 2 (n - kx) + 1.
@@ -117,13 +141,19 @@ __device__ __forceinline__ float pinv_of(const Inst& I, float fx, float fy) {
 
 // ------------------------------------------------------------------ FFT configurations
 
-// Row sweeps: T lanes per row, RW rows per workgroup.
+// Row sweeps: T lanes per row, RW rows per workgroup.  RowCfgAlt is a second
+// plan per side with fewer elements per lane, for the sweeps whose real-space
+// step is heavy (exp(psi) and FP64 correlation sums in the update sweep);
+// row_uses_alt names the sweeps that take it.
 template <int N> struct RowCfg;
-template <> struct RowCfg<128>  { using Plan = FftPlan<128, 16, 8>;     static constexpr int T = 8,  RW = 32; };
-template <> struct RowCfg<256>  { using Plan = FftPlan<256, 16, 16>;    static constexpr int T = 16, RW = 16; };
-template <> struct RowCfg<512>  { using Plan = FftPlan<512, 32, 16>;    static constexpr int T = 16, RW = 16; };
-template <> struct RowCfg<1024> { using Plan = FftPlan<1024, 32, 32>;   static constexpr int T = 32, RW = 8; };
-template <> struct RowCfg<2048> { using Plan = FftPlan<2048, 32, 8, 8>; static constexpr int T = 64, RW = 4; };
+template <> struct RowCfg<128>  { using Plan = FftPlan<128, 16, 8>;      static constexpr int T = 8,   RW = 32; };
+template <> struct RowCfg<256>  { using Plan = FftPlan<256, 16, 16>;     static constexpr int T = 16,  RW = 16; };
+template <> struct RowCfg<512>  { using Plan = FftPlan<512, 16, 8, 4>;   static constexpr int T = 32,  RW = 8; };
+template <> struct RowCfg<1024> { using Plan = FftPlan<1024, 32, 32>;    static constexpr int T = 32,  RW = 8; };
+template <> struct RowCfg<2048> { using Plan = FftPlan<2048, 32, 8, 8>;  static constexpr int T = 64,  RW = 4; };
+template <int N> struct RowCfgAlt : RowCfg<N> {};
+template <> struct RowCfgAlt<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  RW = 4; };
+template <> struct RowCfgAlt<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, RW = 2; };
 
 // Column sweeps: T lanes per column and W adjacent columns per workgroup
 // (lane index = t * W + w, so the W columns of one row are one coalesced
@@ -133,7 +163,7 @@ template <> struct ColCfg<128>  { using Plan = FftPlan<128, 16, 8>;      static 
 template <> struct ColCfg<256>  { using Plan = FftPlan<256, 16, 16>;     static constexpr int T = 16,  WA = 16, WB = 32; };
 template <> struct ColCfg<512>  { using Plan = FftPlan<512, 16, 8, 4>;   static constexpr int T = 32,  WA = 16, WB = 8; };
 template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  WA = 8,  WB = 4; };
-template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, WA = 4,  WB = 8; };
+template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, WA = 4,  WB = 2; };
 
 // Arguments common to every sweep launch.
 struct Sweep {
@@ -142,6 +172,7 @@ struct Sweep {
   int32_t iter;           // iteration index within this call
   const double* beta;     // momentum table (Algorithm S1), indexed by k0 + iter
   const float2* tw_row;   // twiddles of the row plan (forward, then reversed plan)
+  const float2* tw_alt;   // twiddles of the alternative row plan (forward, then reversed plan)
   const float2* tw_col;   // twiddles of the column plan (forward, then reversed plan)
   int32_t* status;        // bit 0: non-finite loss seen
   double corr_tol;        // stopping correlation threshold (used when corr_partial is set)

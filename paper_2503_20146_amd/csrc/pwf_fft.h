@@ -108,6 +108,14 @@ __device__ __forceinline__ float2 twiddle_const(float2 a) {
     return make_float2(-a.x, -a.y);
   } else if constexpr (4 * k == 3 * NN) {  // w = +i (fwd) / -i (inv)
     return DIR < 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+  } else if constexpr ((8 * k) % NN == 0) {  // odd multiple of 45 degrees: |cos| = |sin|
+    constexpr float c = (float)cx_trig(k, NN, 0);
+    constexpr float s = (float)(DIR * cx_trig(k, NN, 1));
+    if constexpr ((c > 0) == (s > 0)) {  // s = c
+      return make_float2(c * (a.x - a.y), c * (a.x + a.y));
+    } else {  // s = -c
+      return make_float2(c * (a.x + a.y), c * (a.y - a.x));
+    }
   } else {
     constexpr float c = (float)cx_trig(k, NN, 0);
     constexpr float s = (float)(DIR * cx_trig(k, NN, 1));  // exp(DIR i 2 pi k / n)
@@ -115,10 +123,28 @@ __device__ __forceinline__ float2 twiddle_const(float2 a) {
   }
 }
 
-// In-register radix-R DFT (decimation in frequency).  On entry a[OFF + q] holds
-// input q; on exit a[OFF + bitrev(r)] holds output r.
+// Register position of output r of the in-register R-point DFT below.
+__host__ __device__ constexpr int dft_pos(int R, int r) {
+  return R == 4 ? r : R == 8 ? 4 * (r % 2) + r / 2 : R == 16 ? 4 * (r % 4) + r / 4 : bitrev(r, ilog2(R));
+}
+
+// 4-point DFT on the registers at compile-time positions P0..P3; outputs in
+// natural order at the same positions.
+template <int DIR, int P0, int P1, int P2, int P3, int E>
+__device__ __forceinline__ void dft4_at(float2 (&a)[E]) {
+  const float2 t0 = cadd(a[P0], a[P2]), t1 = csub(a[P0], a[P2]);
+  const float2 t2 = cadd(a[P1], a[P3]), t3 = csub(a[P1], a[P3]);
+  a[P0] = cadd(t0, t2);
+  a[P2] = csub(t0, t2);
+  // forward: X1 = t1 - i t3, X3 = t1 + i t3 (inverse: signs swapped)
+  const float2 it3 = DIR < 0 ? make_float2(t3.y, -t3.x) : make_float2(-t3.y, t3.x);
+  a[P1] = cadd(t1, it3);
+  a[P3] = csub(t1, it3);
+}
+
+// Generic radix-2 decimation-in-frequency network (outputs bit-reversed).
 template <int R, int DIR, int OFF, int E>
-__device__ __forceinline__ void dft_reg(float2 (&a)[E]) {
+__device__ __forceinline__ void dft_radix2(float2 (&a)[E]) {
   constexpr int LOGR = ilog2(R);
   static_for<0, LOGR>([&](auto st) {
     constexpr int half = R >> (decltype(st)::value + 1);
@@ -133,6 +159,43 @@ __device__ __forceinline__ void dft_reg(float2 (&a)[E]) {
       });
     });
   });
+}
+
+// In-register radix-R DFT.  On entry a[OFF + q] holds input q; on exit
+// a[OFF + dft_pos(R, r)] holds output r.  R = 4, 8, 16 use radix-4 codelets
+// (8 = 2 x 4, 16 = 4 x 4, decimation in frequency); other R the radix-2 network.
+template <int R, int DIR, int OFF, int E>
+__device__ __forceinline__ void dft_reg(float2 (&a)[E]) {
+  if constexpr (R == 4) {
+    dft4_at<DIR, OFF, OFF + 1, OFF + 2, OFF + 3>(a);
+  } else if constexpr (R == 8) {
+    // stage 1: 2-point DFTs over n1 for each n2, twiddle w8^(n2 k1)
+    static_for<0, 4>([&](auto nn) {
+      constexpr int n2 = decltype(nn)::value;
+      const float2 u = a[OFF + n2], w = a[OFF + n2 + 4];
+      a[OFF + n2] = cadd(u, w);
+      a[OFF + n2 + 4] = twiddle_const<DIR, n2, 8>(csub(u, w));
+    });
+    // stage 2: 4-point DFTs over n2 for each k1; X[k1 + 2 k2] lands at 4 k1 + k2
+    dft4_at<DIR, OFF + 0, OFF + 1, OFF + 2, OFF + 3>(a);
+    dft4_at<DIR, OFF + 4, OFF + 5, OFF + 6, OFF + 7>(a);
+  } else if constexpr (R == 16) {
+    // stage 1: 4-point DFTs over n1 (stride 4) for each n2, twiddle w16^(n2 k1)
+    static_for<0, 4>([&](auto nn) {
+      constexpr int n2 = decltype(nn)::value;
+      dft4_at<DIR, OFF + n2, OFF + n2 + 4, OFF + n2 + 8, OFF + n2 + 12>(a);
+      a[OFF + n2 + 4] = twiddle_const<DIR, n2 * 1, 16>(a[OFF + n2 + 4]);
+      a[OFF + n2 + 8] = twiddle_const<DIR, n2 * 2, 16>(a[OFF + n2 + 8]);
+      a[OFF + n2 + 12] = twiddle_const<DIR, n2 * 3, 16>(a[OFF + n2 + 12]);
+    });
+    // stage 2: 4-point DFTs over n2 for each k1; X[k1 + 4 k2] lands at 4 k1 + k2
+    static_for<0, 4>([&](auto kk) {
+      constexpr int b = 4 * decltype(kk)::value;
+      dft4_at<DIR, OFF + b, OFF + b + 1, OFF + b + 2, OFF + b + 3>(a);
+    });
+  } else {
+    dft_radix2<R, DIR, OFF>(a);
+  }
 }
 
 // ------------------------------------------------------------------ Stockham passes
@@ -175,7 +238,7 @@ struct FftPlan {
 
 // One pass over registers.  v holds B = E/R butterflies' inputs at v[c*R + q].
 // Applies the inter-pass twiddle and the radix-R DFT; leaves outputs at
-// v[c*R + bitrev(r)].
+// v[c*R + dft_pos(R, r)].
 template <class Plan, int P, int T, int DIR, int E>
 __device__ __forceinline__ void pass_compute(float2 (&v)[E], int t, const float2* __restrict__ tw) {
   constexpr int N = E * T;
@@ -201,13 +264,12 @@ __device__ __forceinline__ void pass_compute(float2 (&v)[E], int t, const float2
   });
 }
 
-// Write pass-P outputs (bit-reversed in registers) to LDS at Stockham positions.
+// Write pass-P outputs (permuted in registers, see dft_pos) to LDS at Stockham positions.
 template <class Plan, int P, int T, int E>
 __device__ __forceinline__ void pass_store_lds(const float2 (&v)[E], int t, LdsView lds) {
   constexpr int R = Plan::radix[P];
   constexpr int L = Plan::stride_before(P);
   constexpr int B = E / R;
-  constexpr int LOGR = ilog2(R);
   static_for<0, B>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     const int j = t + T * c;
@@ -215,7 +277,7 @@ __device__ __forceinline__ void pass_store_lds(const float2 (&v)[E], int t, LdsV
     const int base = (j / L) * L * R + k;
     static_for<0, R>([&](auto rr) {
       constexpr int r = decltype(rr)::value;
-      lds.at(base + r * L) = v[c * R + bitrev(r, LOGR)];
+      lds.at(base + r * L) = v[c * R + dft_pos(R, r)];
     });
   });
 }
@@ -237,11 +299,10 @@ __device__ __forceinline__ void pass_load_lds(float2 (&v)[E], int t, LdsView lds
   });
 }
 
-// Put the last pass's bit-reversed outputs back in natural register order so
+// Put the last pass's permuted outputs back in natural register order so
 // that v[c*R + r] holds frequency t + T c + r m.
 template <int R, int E>
 __device__ __forceinline__ void unscramble(float2 (&v)[E]) {
-  constexpr int LOGR = ilog2(R);
   constexpr int B = E / R;
   float2 tmp[R];
   static_for<0, B>([&](auto cc) {
@@ -249,7 +310,7 @@ __device__ __forceinline__ void unscramble(float2 (&v)[E]) {
     static_for<0, R>([&](auto rr) { tmp[decltype(rr)::value] = v[c * R + decltype(rr)::value]; });
     static_for<0, R>([&](auto rr) {
       constexpr int r = decltype(rr)::value;
-      v[c * R + r] = tmp[bitrev(r, LOGR)];
+      v[c * R + r] = tmp[dft_pos(R, r)];
     });
   });
 }

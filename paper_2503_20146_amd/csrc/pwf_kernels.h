@@ -24,6 +24,13 @@ enum RowOp {
   ROW_IFFT_OUT,        // out = IFFT_x(W)
 };
 
+// Row sweeps that run with the alternative plan of their side (RowCfgAlt):
+// the update sweep on every side, the gradient sweep from 1024 up and the
+// intensity sweep at 2048.
+template <int N> constexpr bool row_uses_alt(int op) {
+  return op == ROW_PSI_UPDATE || (N >= 1024 && op == ROW_GRAD) || (N == 2048 && op == ROW_INTENSITY);
+}
+
 enum ColOp {
   COL_CHIRP1 = 0,      // S1
   COL_CHIRP2,          // S3
@@ -44,7 +51,7 @@ enum PlainOp {
   PLAIN_GRAD, PLAIN_IMAG, PLAIN_DIRECTION, PLAIN_NESTEROV
 };
 
-int row_rows_per_block(int n);
+int row_rows_per_block(int n, int op);
 int col_default_width(int n);
 int col_alt_width(int n);
 bool col_width_supported(int n, int w);

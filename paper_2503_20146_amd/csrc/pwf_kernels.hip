@@ -157,11 +157,12 @@ __global__ void build_tables_kernel(const Inst* __restrict__ insts) {
     if (isx) {
       I.qx1[kk] = q[0];
       I.qx2[kk] = q[1];
+      // (y factors below carry the 1/m of the inverse 2-D transform: exact, m = 2^k)
       I.ix[kk] = expf(-cio * ff);
       I.gx[kk] = -expm1f(-cst * ff);
     } else {
-      I.qy1[kk] = q[0];
-      I.qy2[kk] = q[1];
+      I.qy1[kk] = make_float2(q[0].x * I.inv_m, q[0].y * I.inv_m);
+      I.qy2[kk] = make_float2(q[1].x * I.inv_m, q[1].y * I.inv_m);
       I.iy[kk] = expf(-cio * ff);
       I.gy[kk] = -expm1f(-cst * ff);
     }
@@ -194,13 +195,13 @@ PWF_DECLARE_SIDE(1024)
 PWF_DECLARE_SIDE(2048)
 #undef PWF_DECLARE_SIDE
 
-int row_rows_per_block(int n) {
+int row_rows_per_block(int n, int op) {
   switch (n) {
-    case 128: return RowCfg<128>::RW;
-    case 256: return RowCfg<256>::RW;
-    case 512: return RowCfg<512>::RW;
-    case 1024: return RowCfg<1024>::RW;
-    case 2048: return RowCfg<2048>::RW;
+    case 128: return row_uses_alt<128>(op) ? RowCfgAlt<128>::RW : RowCfg<128>::RW;
+    case 256: return row_uses_alt<256>(op) ? RowCfgAlt<256>::RW : RowCfg<256>::RW;
+    case 512: return row_uses_alt<512>(op) ? RowCfgAlt<512>::RW : RowCfg<512>::RW;
+    case 1024: return row_uses_alt<1024>(op) ? RowCfgAlt<1024>::RW : RowCfg<1024>::RW;
+    case 2048: return row_uses_alt<2048>(op) ? RowCfgAlt<2048>::RW : RowCfg<2048>::RW;
     default: return 0;
   }
 }

@@ -57,9 +57,19 @@ __device__ __forceinline__ float2 cexp_f(float2 p) {
   return make_float2(a * c, a * s);
 }
 
+// Waves per SIMD the compiler must leave room for (launch bound).
+template <int NX, int OP> constexpr int row_min_waves() {
+  return OP == ROW_PSI_UPDATE ? 3 : OP == ROW_GRAD ? (NX >= 2048 ? 2 : 3) : 4;
+}
+
 template <int NX, int OP>
-__global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2) row_sweep(Sweep S) {
-  using C = RowCfg<NX>;
+using RowCfgOf = typename std::conditional<row_uses_alt<NX>(OP), RowCfgAlt<NX>, RowCfg<NX>>::type;
+
+template <int NX, int OP> constexpr int row_threads() { return RowCfgOf<NX, OP>::T * RowCfgOf<NX, OP>::RW; }
+
+template <int NX, int OP>
+__global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP>())) row_sweep(Sweep S) {
+  using C = RowCfgOf<NX, OP>;
   using Plan = typename C::Plan;
   constexpr int T = C::T, RW = C::RW, E = NX / T;
   constexpr int R1 = Plan::radix[0], RL = Plan::radix[Plan::NPASS - 1];
@@ -74,26 +84,41 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2) row_sweep(S
   const int t = threadIdx.x % T, rw = threadIdx.x / T;
   const int row = blk * RW + rw;
   const LdsView lv{lds + rw * lds_len(NX), 1};
-  const float2* tw = S.tw_row;
-  const float2* twr = S.tw_row + Plan::tw_total();
-  const size_t rbase = (size_t)row * NX;
+  const float2* tw = row_uses_alt<NX>(OP) ? S.tw_alt : S.tw_row;
+  const float2* twr = tw + Plan::tw_total();
+  const uint32_t rbase = (uint32_t)row * NX;
 
+  // Side input of the real-space step (t, v or x at this row), loaded after
+  // the row spectrum so that its latency overlaps the inverse FFT.  The
+  // gradient sweep at 32 elements per lane loads it at its use instead: held
+  // through the FFT it would not fit the register file.
+  constexpr bool SIDE = OP == ROW_MUL_T || OP == ROW_MUL_CONJ_T || OP == ROW_BACKBLUR ||
+                        (OP == ROW_GRAD && E <= 16);
+  float2 side[SIDE ? E : 1];
   float2 v[E];
   if constexpr (IN_FREQ) {
-    const float2* __restrict__ src = I.W + rbase;
     static_for<0, E / RL>([&](auto cc) {
       static_for<0, RL>([&](auto rr) {
         constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
-        v[c * RL + r] = src[col_of_kx(t + T * c + r * ML, NX)];
+        v[c * RL + r] = gld(I.W, rbase + col_of_kx(t + T * c + r * ML, NX));
       });
     });
+    if constexpr (SIDE) {
+      const float2* __restrict__ sp = (OP == ROW_MUL_T || OP == ROW_MUL_CONJ_T) ? I.t
+                                     : (OP == ROW_BACKBLUR ? I.v : I.x);
+      static_for<0, E / R1>([&](auto cc) {
+        static_for<0, R1>([&](auto qq) {
+          constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
+          side[c * R1 + q] = gld(sp, rbase + t + T * c + q * M1);
+        });
+      });
+    }
     fft_inverse<Plan, T>(v, t, twr, lv);
   } else if constexpr (OP == ROW_REAL_FFT) {
-    const float* __restrict__ src = I.y + rbase;
     static_for<0, E / R1>([&](auto cc) {
       static_for<0, R1>([&](auto qq) {
         constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-        v[c * R1 + q] = make_float2(src[t + T * c + q * M1], 0.f);
+        v[c * R1 + q] = make_float2(gldf(I.y, rbase + t + T * c + q * M1), 0.f);
       });
     });
   } else {  // ROW_START / ROW_CPLX_FFT: complex real-space input (null = zeros)
@@ -101,7 +126,7 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2) row_sweep(S
     static_for<0, E / R1>([&](auto cc) {
       static_for<0, R1>([&](auto qq) {
         constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-        v[c * R1 + q] = src ? src[rbase + t + T * c + q * M1] : make_float2(0.f, 0.f);
+        v[c * R1 + q] = src ? gld(src, rbase + t + T * c + q * M1) : make_float2(0.f, 0.f);
       });
     });
   }
@@ -117,53 +142,52 @@ __global__ void __launch_bounds__(RowCfg<NX>::T * RowCfg<NX>::RW, 2) row_sweep(S
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
       constexpr int e = c * R1 + q;
-      const size_t idx = rbase + t + T * c + q * M1;
+      const uint32_t idx = rbase + t + T * c + q * M1;
       if constexpr (OP == ROW_PSI_UPDATE) {
-        if (corr) I.out[idx] = v[e];  // psi of this iterate, kept in case the stop fires
+        if (corr) gst(I.out, idx, v[e]);  // psi of this iterate, kept in case the stop fires
         const float2 xn = cexp_f(v[e]);
         if (corr_sum) {
-          const float2 xo = I.x[idx];
+          const float2 xo = gld(I.x, idx);
           c_re += (double)xn.x * xo.x + (double)xn.y * xo.y;
           c_im += (double)xn.x * xo.y - (double)xn.y * xo.x;
           n_new += (double)xn.x * xn.x + (double)xn.y * xn.y;
           n_old += (double)xo.x * xo.x + (double)xo.y * xo.y;
         }
         v[e] = xn;
-        if (I.x) I.x[idx] = v[e];
+        if (I.x) gst(I.x, idx, v[e]);
       } else if constexpr (OP == ROW_START) {
         v[e] = cexp_f(v[e]);
-        if (I.x) I.x[idx] = v[e];
+        if (I.x) gst(I.x, idx, v[e]);
       } else if constexpr (OP == ROW_MUL_T) {
-        v[e] = cmul(v[e], I.t[idx]);
+        v[e] = cmul(v[e], side[e]);
       } else if constexpr (OP == ROW_MUL_CONJ_T) {
-        v[e] = cmulc(v[e], I.t[idx]);
+        v[e] = cmulc(v[e], side[e]);
       } else if constexpr (OP == ROW_INTENSITY) {
-        if (I.v) I.v[idx] = v[e];
+        if (I.v) gst(I.v, idx, v[e]);
         v[e] = make_float2(v[e].x * v[e].x + v[e].y * v[e].y, 0.f);
       } else if constexpr (OP == ROW_BACKBLUR) {
         const float h = v[e].x;
-        const float2 vv = I.v[idx];
-        v[e] = make_float2(vv.x * h, vv.y * h);
+        v[e] = make_float2(side[e].x * h, side[e].y * h);
       } else if constexpr (OP == ROW_GRAD) {
-        v[e] = cscale(cmulc(v[e], I.x[idx]), inv_maxt2);
-        if (I.g_out) I.g_out[idx] = v[e];
+        const float2 xs = SIDE ? side[SIDE ? e : 0] : gld(I.x, idx);
+        v[e] = cscale(cmulc(v[e], xs), inv_maxt2);
+        if (I.g_out) gst(I.g_out, idx, v[e]);
       } else if constexpr (OP == ROW_FORWARD_OUT) {
-        I.f_out[idx] = v[e].x;
+        gstf(I.f_out, idx, v[e].x);
       } else if constexpr (OP == ROW_CPLX_FFT) {
-        if (I.psi) I.psi[idx] = v[e];
+        if (I.psi) gst(I.psi, idx, v[e]);
       } else if constexpr (OP == ROW_IFFT_OUT) {
-        if (I.out) I.out[idx] = v[e];
+        if (I.out) gst(I.out, idx, v[e]);
       }
     });
   });
 
   if constexpr (OUT_FREQ) {
     fft_forward<Plan, T>(v, t, tw, lv);
-    float2* __restrict__ dst = I.W + rbase;
     static_for<0, E / RL>([&](auto cc) {
       static_for<0, RL>([&](auto rr) {
         constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
-        dst[col_of_kx(t + T * c + r * ML, NX)] = v[c * RL + r];
+        gst(I.W, rbase + col_of_kx(t + T * c + r * ML, NX), v[c * RL + r]);
       });
     });
   }
@@ -225,8 +249,8 @@ PWF_COL_TRAIT(COL_SPEC_PSIHAT, false)
 
 // Transfer function of FreePropagation at (fx, fy) from the 1-D factors:
 // Q = Qx(fx) Qy(fy) exp(i theta_c), where the cross term theta_c = -2 pi a rho^2
-// (2/(1+sqrt(1-s)) - 1) is below 1e-8 rad for X-ray geometries and is applied
-// as (1, theta_c).
+// (2/(1+sqrt(1-s)) - 1) is applied as (1, theta_c).  For hard X-ray geometries
+// it stays below a quarter ulp of 1 everywhere and the sweep skips it.
 __device__ __forceinline__ float2 transfer_sep(float2 qx, float2 qy, float fx, float fy, float s_coef,
                                                float two_pi_a) {
   const float2 q = cmul(qx, qy);
@@ -241,8 +265,11 @@ __device__ __noinline__ float2 transfer_direct(double chirp_rev, double s_coef, 
   return transfer(chirp_rev, s_coef, 0, fx, fy, false);
 }
 
+// Column sweeps keep the 2-wave bound: with 128 registers the FFT spills.
+template <int OP> constexpr int col_min_waves() { return 2; }
+
 template <int NY, int W, int OP>
-__global__ void __launch_bounds__(ColCfg<NY>::T * W, 2) col_sweep(Sweep S) {
+__global__ void __launch_bounds__(ColCfg<NY>::T * W, col_min_waves<OP>()) col_sweep(Sweep S) {
   using C = ColCfg<NY>;
   using Plan = typename C::Plan;
   constexpr int T = C::T, E = NY / T;
@@ -279,15 +306,12 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, 2) col_sweep(Sweep S) {
   const float2* twr = S.tw_col + Plan::tw_total();
 
   float2 v[E];
-  {
-    const float2* __restrict__ src = I.W + s;
-    static_for<0, E / R1>([&](auto cc) {
-      static_for<0, R1>([&](auto qq) {
-        constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-        v[c * R1 + q] = src[(size_t)(t + T * c + q * M1) * nx];
-      });
+  static_for<0, E / R1>([&](auto cc) {
+    static_for<0, R1>([&](auto qq) {
+      constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
+      v[c * R1 + q] = gld(I.W, (uint32_t)((t + T * c + q * M1) * nx + s));
     });
-  }
+  });
   fft_forward<Plan, T>(v, t, tw, lv);
 
   // Fourier-domain step; element e = c*RL + r holds ky = t + T c + r ML.
@@ -318,27 +342,27 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, 2) col_sweep(Sweep S) {
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       const int ky = t + T * (e / RL) + (e % RL) * ML;
-      lv.at(ky) = I.psi_hat[(size_t)ky * nx + s];
+      lv.at(ky) = gld(I.psi_hat, (uint32_t)(ky * nx + s));
     });
     __syncthreads();
     const float bf = (OP == COL_NESTEROV) ? (float)S.beta[I.k0 + S.iter] : 0.f;
-    const float gxv = I.gx[kx];
+    const float gxv = gldf(I.gx, kx);
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       const int ky = t + T * (e / RL) + (e % RL) * ML;
       const float2 pk = lv.at(ky);
       const float2 pm = lm.at((NY - ky) & (NY - 1));
-      const float g2 = gxv + (1.f - gxv) * I.gy[ky];   // 1 - STFx STFy without cancellation
+      const float g2 = gxv + (1.f - gxv) * gldf(I.gy, ky);   // 1 - STFx STFy without cancellation
       // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
       const float2 reg = make_float2(I.alpha_c1 * pk.x + I.alpha_c2 * pm.x, I.alpha_c1 * pk.y - I.alpha_c2 * pm.y);
       const float2 d = make_float2(v[e].x + g2 * reg.x, v[e].y + g2 * reg.y);
       if constexpr (OP == COL_NESTEROV) {
-        const size_t gi = (size_t)ky * nx + s;
-        const float2 zp = I.z_hat[gi];
+        const uint32_t gi = (uint32_t)(ky * nx + s);
+        const float2 zp = gld(I.z_hat, gi);
         const float2 z = make_float2(pk.x - I.eta * d.x, pk.y - I.eta * d.y);
         const float2 pn = make_float2(z.x + bf * (z.x - zp.x), z.y + bf * (z.y - zp.y));
-        I.z_hat[gi] = z;
-        I.psi_hat[gi] = pn;
+        gst(I.z_hat, gi, z);
+        gst(I.psi_hat, gi, pn);
         v[e] = cscale(pn, I.inv_m);
       } else {
         v[e] = cscale(d, I.inv_m);
@@ -348,22 +372,31 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, 2) col_sweep(Sweep S) {
   } else {
     float2 qx = make_float2(1.f, 0.f);
     float ixv = 1.f;
-    if constexpr (OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ) qx = I.qx1[kx];
-    if constexpr (OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ) qx = I.qx2[kx];
-    if constexpr (OP == COL_BLUR || OP == COL_BLUR_LOSS) ixv = I.ix[kx];
+    if constexpr (OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ) qx = gld(I.qx1, kx);
+    if constexpr (OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ) qx = gld(I.qx2, kx);
+    if constexpr (OP == COL_BLUR || OP == COL_BLUR_LOSS) ixv = gldf(I.ix, kx);
     constexpr bool CHIRP = OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ || OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ;
     constexpr bool CONJ = OP == COL_CHIRP1_CONJ || OP == COL_CHIRP2_CONJ;
     constexpr bool L1 = OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ;
     if constexpr (CHIRP) {
       const float2* __restrict__ qy = L1 ? I.qy1 : I.qy2;
       const float two_pi_a = L1 ? I.two_pi_a1 : I.two_pi_a2;
-      if (I.series) {
+      // the y factors carry the 1/m of the inverse transform
+      if (I.series && I.cross) {
         static_for<0, E>([&](auto ee) {
           constexpr int e = decltype(ee)::value;
           const int ky = t + T * (e / RL) + (e % RL) * ML;
-          float2 q = transfer_sep(qx, qy[ky], fx, freq_of(ky, NY), I.s_coef_f, two_pi_a);
+          float2 q = transfer_sep(qx, gld(qy, ky), fx, freq_of(ky, NY), I.s_coef_f, two_pi_a);
           if (CONJ) q = cconj(q);
-          v[e] = cscale(cmul(v[e], q), I.inv_m);
+          v[e] = cmul(v[e], q);
+        });
+      } else if (I.series) {
+        static_for<0, E>([&](auto ee) {
+          constexpr int e = decltype(ee)::value;
+          const int ky = t + T * (e / RL) + (e % RL) * ML;
+          float2 q = cmul(qx, gld(qy, ky));
+          if (CONJ) q = cconj(q);
+          v[e] = cmul(v[e], q);
         });
       } else {
         const double a = L1 ? I.chirp1_rev : I.chirp2_rev;
@@ -380,18 +413,18 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, 2) col_sweep(Sweep S) {
         constexpr int e = decltype(ee)::value;
         const int ky = t + T * (e / RL) + (e % RL) * ML;
         if constexpr (OP == COL_BLUR) {
-          v[e] = cscale(v[e], ixv * I.iy[ky] * I.inv_m);
+          v[e] = cscale(v[e], ixv * gldf(I.iy, ky) * I.inv_m);
         } else if constexpr (OP == COL_BLUR_LOSS) {
-          const float h = ixv * I.iy[ky];
-          const float2 yh = I.y_hat[(size_t)ky * nx + s];
+          const float h = ixv * gldf(I.iy, ky);
+          const float2 yh = gld(I.y_hat, (uint32_t)(ky * nx + s));
           const float2 rr = make_float2(h * v[e].x - yh.x, h * v[e].y - yh.y);
           acc += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
           v[e] = cscale(rr, h * I.inv_m);
         } else if constexpr (OP == COL_SPEC_YHAT) {
-          I.y_hat[(size_t)ky * nx + s] = v[e];
+          gst(I.y_hat, (uint32_t)(ky * nx + s), v[e]);
         } else if constexpr (OP == COL_SPEC_PSIHAT) {
-          I.psi_hat[(size_t)ky * nx + s] = v[e];
-          if (I.z_hat) I.z_hat[(size_t)ky * nx + s] = make_float2(0.f, 0.f);
+          gst(I.psi_hat, (uint32_t)(ky * nx + s), v[e]);
+          if (I.z_hat) gst(I.z_hat, (uint32_t)(ky * nx + s), make_float2(0.f, 0.f));
         }
       });
     }
@@ -399,11 +432,10 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, 2) col_sweep(Sweep S) {
 
   if constexpr (ColOpTraits<OP>::kInverse) {
     fft_inverse<Plan, T>(v, t, twr, lv);
-    float2* __restrict__ dst = I.W + s;
     static_for<0, E / R1>([&](auto cc) {
       static_for<0, R1>([&](auto qq) {
         constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-        dst[(size_t)(t + T * c + q * M1) * nx] = v[c * R1 + q];
+        gst(I.W, (uint32_t)((t + T * c + q * M1) * nx + s), v[c * R1 + q]);
       });
     });
   }
@@ -500,10 +532,12 @@ plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw) {
 
 template <int N>
 hipError_t launch_row_n(int op, int nblocks, const Sweep& S, hipStream_t st) {
-  using C = RowCfg<N>;
-  const dim3 grid(nblocks), block(C::T * C::RW);
+  const dim3 grid(nblocks);
   switch (op) {
-#define PWF_CASE(o) case o: hipLaunchKernelGGL((row_sweep<N, o>), grid, block, 0, st, S); break;
+#define PWF_CASE(o)                                                                        \
+  case o:                                                                                  \
+    hipLaunchKernelGGL((row_sweep<N, o>), grid, dim3(row_threads<N, o>()), 0, st, S);     \
+    break;
     PWF_CASE(ROW_PSI_UPDATE) PWF_CASE(ROW_START) PWF_CASE(ROW_MUL_T) PWF_CASE(ROW_MUL_CONJ_T)
     PWF_CASE(ROW_INTENSITY) PWF_CASE(ROW_BACKBLUR) PWF_CASE(ROW_GRAD) PWF_CASE(ROW_FORWARD_OUT)
     PWF_CASE(ROW_REAL_FFT) PWF_CASE(ROW_CPLX_FFT) PWF_CASE(ROW_IFFT_OUT)
@@ -566,7 +600,7 @@ static void fill_twiddles(float2* out) {
 }
 
 // Twiddle tables of an N-point plan followed by those of its reversed plan:
-// which = 0 for the row plan, 1 for the column plan.
+// which = 0 for the row plan, 1 for the column plan, 2 for the alternative row plan.
 template <int N>
 int plan_twiddles_n(int which, float2* out) {
   auto emit = [&](auto tag) {
@@ -579,7 +613,8 @@ int plan_twiddles_n(int which, float2* out) {
     }
     return Plan::tw_total() + RPlan::tw_total();
   };
-  return which == 0 ? emit(typename RowCfg<N>::Plan{}) : emit(typename ColCfg<N>::Plan{});
+  return which == 0 ? emit(typename RowCfg<N>::Plan{})
+                    : which == 1 ? emit(typename ColCfg<N>::Plan{}) : emit(typename RowCfgAlt<N>::Plan{});
 }
 
 }  // namespace pwf

@@ -45,3 +45,17 @@ def to_dev(a, dev):
 def gpu_problem(geo, t, dev, **kw):
     from paper_2503_20146_amd import problem_from_geometry
     return problem_from_geometry(geo, to_dev(np.asarray(t, np.complex64), dev), **kw)
+
+
+def loss_tolerance(y, f_ref, fwd_tol=1e-5):
+    """Relative tolerance of L = sum (y - f)^2 implied by the forward tolerance on f:
+    |dL| <= 2 ||y - f|| ||df||, so |dL|/L <= 2 fwd_tol ||f|| / ||y - f||."""
+    y = np.asarray(y, np.float64)
+    return 2.0 * fwd_tol * float(np.linalg.norm(f_ref) / np.linalg.norm(y - f_ref))
+
+
+def loss_history_tolerance(y, hist_ref, fwd_tol=1e-5):
+    """Per-iteration relative tolerance of a loss history: ||y - f_k|| = sqrt(L_k), so the
+    forward tolerance gives |dL_k| / L_k <= 2 fwd_tol ||y|| / sqrt(L_k) (||f_k|| ~ ||y||)."""
+    y = np.asarray(y, np.float64)
+    return 2.0 * fwd_tol * float(np.linalg.norm(y)) / np.sqrt(np.asarray(hist_ref, np.float64))

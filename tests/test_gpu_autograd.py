@@ -12,14 +12,26 @@ import pytest
 
 import oracle as O
 import synthetic as S
-from gpu_helpers import device, gpu_problem, instance, rel, say, to_dev
+from gpu_helpers import device, gpu_problem, instance, loss_tolerance, rel, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
 
+GRAD_TOL = 1e-4
+
+
 def _fd_check(psi, y, prob, grad, pixels, h=1e-4, rtol=1e-3):
-    """Central differences of the FP64 oracle loss at the listed pixels."""
+    """Central differences of the FP64 oracle loss at the listed pixels.
+
+    Allowed deviation: rtol of the difference quotient (its O(h^2) truncation
+    and FP64 cancellation; at 2048^2 the quotient agrees with the oracle's
+    analytic derivative to 3e-4) plus a floor of 5 GRAD_TOL RMS(grad), five
+    times the per-pixel RMS error that the relative-L2 budget of the gradient
+    allows.  FP32 rounding of the GPU gradient is spread evenly over pixels,
+    so small entries carry errors of that absolute size.
+    """
     psi = psi.astype(np.complex128)
+    floor = 5 * GRAD_TOL * float(np.sqrt(np.mean(np.abs(grad) ** 2)))
     for (r, c) in pixels:
         for unit in (1.0, 1j):
             dp = np.zeros(psi.shape, complex)
@@ -28,8 +40,7 @@ def _fd_check(psi, y, prob, grad, pixels, h=1e-4, rtol=1e-3):
             lm = O.loss(y, O.physical_model(psi - dp, prob)[0])
             fd = (lp - lm) / (2 * h)
             an = grad[r, c].real if unit == 1.0 else grad[r, c].imag
-            scale = np.max(np.abs(grad))
-            assert abs(fd - an) <= rtol * max(abs(fd), 1e-2 * scale), (r, c, unit, fd, an)
+            assert abs(fd - an) <= rtol * abs(fd) + floor, (r, c, unit, fd, an)
 
 
 def test_autograd_small_matches_oracle_and_fd():
@@ -46,7 +57,7 @@ def test_autograd_small_matches_oracle_and_fd():
     grad = p.grad[0].cpu().numpy()
     l_ref, g_ref, _ = O.gradient(psi.astype(np.complex128), y, prob)
     assert abs(float(loss[0]) - l_ref) <= 1e-5 * l_ref
-    assert rel(grad, 4 * np.max(np.abs(prob.t) ** 2) * g_ref) <= 1e-4
+    assert rel(grad, 4 * np.max(np.abs(prob.t) ** 2) * g_ref) <= GRAD_TOL
     rng = np.random.default_rng(11)
     pix = [tuple(int(v) for v in divmod(int(k), 128)) for k in rng.choice(128 * 128, 8, replace=False)]
     _fd_check(psi, y, prob, grad, pix)
@@ -68,7 +79,7 @@ def test_autograd_chain_rule_with_weights():
     for i, w in enumerate((3.0, -0.5)):
         _, g_ref, _ = O.gradient(psi[i].astype(np.complex128), items[i][3], items[i][2])
         expect = w * 4 * np.max(np.abs(items[i][2].t) ** 2) * g_ref
-        assert rel(p.grad[i].cpu().numpy(), expect) <= 1e-4
+        assert rel(p.grad[i].cpu().numpy(), expect) <= GRAD_TOL
 
 
 def test_autograd_2048_projection_fd_and_oracle():
@@ -95,8 +106,11 @@ def test_autograd_2048_projection_fd_and_oracle():
     say("autograd 2048^2: oracle gradient")
     y0 = ys[0].cpu().numpy()
     l_ref, g_ref, _ = O.gradient(psis[0].astype(np.complex128), y0, prob)
-    assert abs(float(loss[0]) - l_ref) <= 1e-5 * l_ref
-    assert rel(grad0, 4 * np.max(np.abs(prob.t) ** 2) * g_ref) <= 1e-4
+    f_ref, _, _ = O.physical_model(psis[0].astype(np.complex128), prob)
+    assert abs(float(loss[0]) - l_ref) <= loss_tolerance(y0, f_ref) * l_ref
+    r = rel(grad0, 4 * np.max(np.abs(prob.t) ** 2) * g_ref)
+    say(f"autograd 2048^2: gradient rel-L2 {r:.2e}")
+    assert r <= GRAD_TOL
     say("autograd 2048^2: central differences on 16 pixels")
     rng = np.random.default_rng(2048)
     pix = [tuple(int(v) for v in divmod(int(k), 2048)) for k in rng.choice(2048 * 2048, 16, replace=False)]

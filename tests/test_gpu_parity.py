@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 import synthetic as S
-from gpu_helpers import device, gpu_problem, instance, rel, say, to_dev
+from gpu_helpers import device, gpu_problem, instance, loss_history_tolerance, rel, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -56,10 +56,16 @@ def test_forward_parity_workload1_zero_and_truth():
 
 
 def test_forward_special_geometries():
-    """z = 0 (identity propagation) and sigma = 0 (no blur) run through the same kernels."""
+    """z = 0 (identity propagation) and sigma = 0 (no blur) run through the same kernels.
+
+    A 1 nm wavelength makes the cross term of the separable chirp significant
+    (about 4e-5 rad at the corner bin), and 20 nm at 1 um pixels
+    ((lambda/p)^2 / 2 = 2e-4) switches to the per-element FP64 chirp.
+    """
     dev = device()
     rng = np.random.default_rng(5)
-    for kw in (dict(z1_m=0.0, z2_m=0.0), dict(sigma_x_px=0.0, sigma_y_px=0.0), dict(z1_m=0.0)):
+    for kw in (dict(z1_m=0.0, z2_m=0.0), dict(sigma_x_px=0.0, sigma_y_px=0.0), dict(z1_m=0.0),
+               dict(wavelength_m=1e-9), dict(wavelength_m=2e-8, z1_m=1e-3, z2_m=5e-3)):
         say(f"forward special {kw}")
         geo = S.Geometry(ny=256, nx=256, **kw)
         t = S.diffuser(rng, 256, 256)
@@ -145,7 +151,7 @@ def test_solve_parity_workload0_50_iterations():
     psi = out[0].cpu().numpy()
     assert np.sqrt(np.mean((psi.imag - psi_ref.imag) ** 2)) <= PHASE_TOL
     assert np.sqrt(np.mean((psi.real - psi_ref.real) ** 2)) <= PHASE_TOL
-    assert np.max(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref) <= 1e-4
+    assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
 def test_solve_parity_workload1_100_iterations():
@@ -158,7 +164,7 @@ def test_solve_parity_workload1_100_iterations():
     psi_ref, hist_ref, _ = O.pwf(y, prob, 100)
     assert np.sqrt(np.mean((psi.imag - psi_ref.imag) ** 2)) <= PHASE_TOL
     assert np.sqrt(np.mean((psi.real - psi_ref.real) ** 2)) <= PHASE_TOL
-    assert np.max(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref) <= 1e-4
+    assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
 def test_plain_path_parity():
@@ -170,7 +176,7 @@ def test_plain_path_parity():
     psi, hist = batch.solve_plain(to_dev(y, dev), 30)
     psi = psi.cpu().numpy()
     assert np.sqrt(np.mean(np.abs(psi - psi_ref) ** 2)) <= PHASE_TOL
-    assert np.max(np.abs(hist.cpu().numpy() - hist_ref) / hist_ref) <= 1e-4
+    assert np.all(np.abs(hist.cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
 def test_step_matches_solve_and_oracle_state():

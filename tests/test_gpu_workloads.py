@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 import synthetic as S
-from gpu_helpers import device, gpu_problem, instance, say, to_dev
+from gpu_helpers import device, gpu_problem, instance, loss_history_tolerance, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,7 @@ def test_tomographic_batch_180x1024_in_bench_configuration():
     psi_ref, hist_ref, _ = O.pwf(y90, oprob, iters)
     assert _rms(psi90.imag, psi_ref.imag) <= PHASE_TOL
     assert _rms(psi90.real, psi_ref.real) <= PHASE_TOL
-    assert np.max(np.abs(h90 - hist_ref) / hist_ref) <= 1e-4
+    assert np.all(np.abs(h90 - hist_ref) / hist_ref <= loss_history_tolerance(y90, hist_ref))
 
 
 def test_uneven_roi_batch_64_instances():
@@ -95,7 +95,7 @@ def test_uneven_roi_batch_64_instances():
         psi = out[i].cpu().numpy()
         assert _rms(psi.imag, psi_ref.imag) <= PHASE_TOL, i
         assert _rms(psi.real, psi_ref.real) <= PHASE_TOL, i
-        assert np.max(np.abs(hist[i].cpu().numpy() - hist_ref) / hist_ref) <= 1e-4, i
+        assert np.all(np.abs(hist[i].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref)), i
 
 
 # On the 128^2 workload 1 - correlation runs 1.0e-4, 1.5e-5, 5.9e-6, ... 9.9e-7 (10th
@@ -114,7 +114,7 @@ def test_correlation_stop_matches_oracle(tol):
     assert 1 <= k_ref < 400
     assert done[0] == k_ref, (done[0], k_ref)
     assert _rms(out[0].cpu().numpy(), psi_ref) <= PHASE_TOL
-    assert np.max(np.abs(hist[0, :k_ref].cpu().numpy() - hist_ref) / hist_ref) <= 1e-4
+    assert np.all(np.abs(hist[0, :k_ref].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
 def test_correlation_stop_per_instance_in_a_batch():
