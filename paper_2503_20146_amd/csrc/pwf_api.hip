@@ -58,6 +58,7 @@ struct Context {
   float2* tw[5] = {};          // row-plan twiddle tables per supported side
   float2* twc[5] = {};         // column-plan twiddle tables per supported side
   float2* twa[5] = {};         // alternative row-plan twiddle tables per supported side
+  float2* twn[5] = {};         // w_N^m, m = 0..N-1, per supported side
   double* beta = nullptr;      // momentum table
   hipStream_t side = nullptr;  // internal stream for graph launches
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -106,6 +107,16 @@ pwf_status context_for_current(Context** out) {
         PWF_HIP(hipMalloc(&dst, sizeof(float2) * std::max(cnt, 1)));
         PWF_HIP(hipMemcpy(dst, host.data(), sizeof(float2) * std::max(cnt, 1), hipMemcpyHostToDevice));
       }
+    }
+    for (int i = 0; i < 5; ++i) {
+      const int n = kSizes[i];
+      std::vector<float2> host(n);
+      for (int m = 0; m < n; ++m) {
+        const double ang = -2.0 * M_PI * (double)m / (double)n;
+        host[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      }
+      PWF_HIP(hipMalloc(&c.twn[i], sizeof(float2) * n));
+      PWF_HIP(hipMemcpy(c.twn[i], host.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
     }
     // beta_k = (tau_k - 1) / tau_{k+1}, tau_0 = 1, tau_{k+1} = (1 + sqrt(1 + 4 tau_k^2)) / 2
     std::vector<double> b(kBetaCap);
@@ -343,6 +354,8 @@ struct Launcher {
     S.beta = ctx.beta;
     S.tw_row = ctx.tw[size_index(c.nx)];
     S.tw_alt = ctx.twa[size_index(c.nx)];
+    S.twn_row = ctx.twn[size_index(c.nx)];
+    S.twn_col = ctx.twn[size_index(c.ny)];
     S.tw_col = ctx.twc[size_index(c.ny)];
     S.status = status();
     S.blocks_per_inst = 0;
@@ -1088,6 +1101,10 @@ void pwf_finalize(void) {
       t = nullptr;
     }
     for (float2*& t : c.twc) {
+      if (t) hipFree(t);
+      t = nullptr;
+    }
+    for (float2*& t : c.twn) {
       if (t) hipFree(t);
       t = nullptr;
     }

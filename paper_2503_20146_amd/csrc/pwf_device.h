@@ -173,6 +173,8 @@ struct Sweep {
   const double* beta;     // momentum table (Algorithm S1), indexed by k0 + iter
   const float2* tw_row;   // twiddles of the row plan (forward, then reversed plan)
   const float2* tw_alt;   // twiddles of the alternative row plan (forward, then reversed plan)
+  const float2* twn_row;  // w_nx^m, m = 0..nx-1
+  const float2* twn_col;  // w_ny^m, m = 0..ny-1
   const float2* tw_col;   // twiddles of the column plan (forward, then reversed plan)
   int32_t* status;        // bit 0: non-finite loss seen
   double corr_tol;        // stopping correlation threshold (used when corr_partial is set)

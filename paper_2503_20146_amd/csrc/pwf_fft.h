@@ -216,6 +216,7 @@ struct LdsView {
 // plan are concatenated; offsets are compile-time.
 template <int N, int... RS>
 struct FftPlan {
+  static constexpr int kN = N;
   static constexpr int NPASS = sizeof...(RS);
   static constexpr int radix[NPASS] = {RS...};
   static constexpr int stride_before(int p) {
@@ -236,11 +237,35 @@ struct FftPlan {
   }
 };
 
+// Twiddle sources.  A pass with stride L and radix R needs w_{LR}^{qk} for
+// 0 < q < R, 0 <= k < L (forward sign; the inverse conjugates).
+//
+// TwPass: per-pass tables in global memory, table[tw_offset(P) + q L + k]
+// (the layout plan_twiddles writes).
+struct TwPass {
+  const float2* tw;
+  template <class Plan, int P, int q>
+  __device__ __forceinline__ float2 get(int k) const {
+    return tw[Plan::tw_offset(P) + q * Plan::stride_before(P) + k];
+  }
+};
+
+// TwTable: one table of w_N^m (m = 0..N-1) for every pass of both
+// directions: w_{LR}^{qk} = w_N^{qk N/(LR)}, and qk N/(LR) < N.
+template <int N>
+struct TwTable {
+  const float2* tab;
+  template <class Plan, int P, int q>
+  __device__ __forceinline__ float2 get(int k) const {
+    return tab[q * (N / (Plan::stride_before(P) * Plan::radix[P])) * k];
+  }
+};
+
 // One pass over registers.  v holds B = E/R butterflies' inputs at v[c*R + q].
 // Applies the inter-pass twiddle and the radix-R DFT; leaves outputs at
 // v[c*R + dft_pos(R, r)].
-template <class Plan, int P, int T, int DIR, int E>
-__device__ __forceinline__ void pass_compute(float2 (&v)[E], int t, const float2* __restrict__ tw) {
+template <class Plan, int P, int T, int DIR, int E, class TW>
+__device__ __forceinline__ void pass_compute(float2 (&v)[E], int t, const TW& tw) {
   constexpr int N = E * T;
   constexpr int R = Plan::radix[P];
   constexpr int L = Plan::stride_before(P);
@@ -252,10 +277,9 @@ __device__ __forceinline__ void pass_compute(float2 (&v)[E], int t, const float2
     if constexpr (L > 1) {
       const int j = t + T * c;
       const int k = j & (L - 1);
-      const float2* twp = tw + Plan::tw_offset(P) + k;
       static_for<1, R>([&](auto qq) {
         constexpr int q = decltype(qq)::value;
-        float2 w = twp[q * L];
+        float2 w = tw.template get<Plan, P, q>(k);
         if constexpr (DIR > 0) w.y = -w.y;
         v[c * R + q] = cmul(v[c * R + q], w);
       });
@@ -319,8 +343,8 @@ __device__ __forceinline__ void unscramble(float2 (&v)[E]) {
 // + q N/R0]) -> registers in "last-radix layout" (v[c*RL + r] = X[t + T c + r
 // N/RL]).  The LDS region must be free on entry; it is free again on exit
 // (a trailing barrier is issued only between passes).
-template <class Plan, int T, int E>
-__device__ __forceinline__ void fft_forward(float2 (&v)[E], int t, const float2* __restrict__ tw, LdsView lds) {
+template <class Plan, int T, int E, class TW>
+__device__ __forceinline__ void fft_forward(float2 (&v)[E], int t, const TW& tw, LdsView lds) {
   static_for<0, Plan::NPASS>([&](auto pp) {
     constexpr int P = decltype(pp)::value;
     if constexpr (P > 0) {
@@ -347,10 +371,43 @@ struct Reverse<FftPlan<N, RS...>> {
   using type = decltype(make(std::make_integer_sequence<int, sizeof...(RS)>{}));
 };
 
+// Per-pass twiddle tables of a plan followed by those of its reversed plan,
+// as plan_twiddles lays them out.  A palindromic plan (e.g. 32 x 32) is its
+// own reverse, and the inverse then reads the forward tables (conjugated).
+template <class Plan>
+struct TwLayout {
+  using RP = typename Reverse<Plan>::type;
+  static constexpr bool kSelfReverse = std::is_same<Plan, RP>::value;
+  static constexpr int kInverseAt = kSelfReverse ? 0 : Plan::tw_total();   // offset of the inverse tables
+  static constexpr int kUsed = kSelfReverse ? Plan::tw_total() : Plan::tw_total() + RP::tw_total();
+};
+
+// Where a sweep kernel reads its twiddles from.  Mode 1: the per-pass tables
+// of a palindromic plan staged in LDS (conflict-free reads; the inverse shares
+// them).  Mode 2: the single table w_N^m staged in LDS (N entries, fewer than
+// the per-pass tables of both directions).  Mode 0: per-pass tables in global
+// memory, where no staged table fits beside the exchange buffer (N > 1024).
+template <class Plan>
+struct TwSel {
+  static constexpr int N = Plan::kN;
+  static constexpr int kMode = N > 1024 ? 0 : (TwLayout<Plan>::kSelfReverse ? 1 : 2);
+  static constexpr int kLds = kMode == 1 ? TwLayout<Plan>::kUsed : kMode == 2 ? N : 1;
+  using View = typename std::conditional<kMode == 2, TwTable<N>, TwPass>::type;
+  // pass: per-pass tables in global memory (forward, then reversed plan);
+  // full: w_N^m in global memory; lds: the staged copy.
+  __device__ static const float2* staged_from(const float2* pass, const float2* full) {
+    return kMode == 1 ? pass : full;
+  }
+  __device__ static View forward(const float2* lds, const float2* pass) { return View{kMode == 0 ? pass : lds}; }
+  __device__ static View inverse(const float2* lds, const float2* pass) {
+    return View{kMode == 0 ? pass + Plan::tw_total() : kMode == 1 ? lds + TwLayout<Plan>::kInverseAt : lds};
+  }
+};
+
 // Inverse transform: registers in last-radix layout of Plan -> registers in
-// first-radix layout of Plan.  `twr` is the twiddle table of the reversed plan.
-template <class Plan, int T, int E>
-__device__ __forceinline__ void fft_inverse(float2 (&v)[E], int t, const float2* __restrict__ twr, LdsView lds) {
+// first-radix layout of Plan.  `twr` gives the twiddles of the reversed plan.
+template <class Plan, int T, int E, class TW>
+__device__ __forceinline__ void fft_inverse(float2 (&v)[E], int t, const TW& twr, LdsView lds) {
   using RP = typename Reverse<Plan>::type;
   static_for<0, RP::NPASS>([&](auto pp) {
     constexpr int P = decltype(pp)::value;

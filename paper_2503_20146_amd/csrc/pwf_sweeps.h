@@ -84,9 +84,20 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
   const int t = threadIdx.x % T, rw = threadIdx.x / T;
   const int row = blk * RW + rw;
   const LdsView lv{lds + rw * lds_len(NX), 1};
-  const float2* tw = row_uses_alt<NX>(OP) ? S.tw_alt : S.tw_row;
-  const float2* twr = tw + Plan::tw_total();
+  using TS = TwSel<Plan>;
+  __shared__ float2 twl[TS::kLds];
+  const float2* twg = row_uses_alt<NX>(OP) ? S.tw_alt : S.tw_row;
+  const auto tw = TS::forward(twl, twg);
+  const auto twr = TS::inverse(twl, twg);
   const uint32_t rbase = (uint32_t)row * NX;
+  // Twiddles to LDS; the first pass needs none, and the barrier after its
+  // LDS exchange orders these writes before the first use.
+  auto load_twiddles = [&]() {
+    if constexpr (TS::kMode != 0) {
+      const float2* src = TS::staged_from(twg, S.twn_row);
+      for (int i = threadIdx.x; i < TS::kLds; i += row_threads<NX, OP>()) twl[i] = gld(src, i);
+    }
+  };
 
   // Side input of the real-space step (t, v or x at this row), loaded after
   // the row spectrum so that its latency overlaps the inverse FFT.  The
@@ -103,6 +114,7 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
         v[c * RL + r] = gld(I.W, rbase + col_of_kx(t + T * c + r * ML, NX));
       });
     });
+    load_twiddles();
     if constexpr (SIDE) {
       const float2* __restrict__ sp = (OP == ROW_MUL_T || OP == ROW_MUL_CONJ_T) ? I.t
                                      : (OP == ROW_BACKBLUR ? I.v : I.x);
@@ -121,6 +133,7 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
         v[c * R1 + q] = make_float2(gldf(I.y, rbase + t + T * c + q * M1), 0.f);
       });
     });
+    load_twiddles();
   } else {  // ROW_START / ROW_CPLX_FFT: complex real-space input (null = zeros)
     const float2* __restrict__ src = I.psi_src;
     static_for<0, E / R1>([&](auto cc) {
@@ -129,6 +142,7 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
         v[c * R1 + q] = src ? gld(src, rbase + t + T * c + q * M1) : make_float2(0.f, 0.f);
       });
     });
+    load_twiddles();
   }
 
   // real-space step; element e = c*R1 + q sits at x = t + T c + q M1
@@ -302,8 +316,10 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, col_min_waves<OP>()) col_sw
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int s = tile * W + w;
   const LdsView lv{lds + w, W};
-  const float2* tw = S.tw_col;
-  const float2* twr = S.tw_col + Plan::tw_total();
+  using TS = TwSel<Plan>;
+  __shared__ float2 twl[TS::kLds];
+  const auto tw = TS::forward(twl, S.tw_col);
+  const auto twr = TS::inverse(twl, S.tw_col);
 
   float2 v[E];
   static_for<0, E / R1>([&](auto cc) {
@@ -312,6 +328,12 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, col_min_waves<OP>()) col_sw
       v[c * R1 + q] = gld(I.W, (uint32_t)((t + T * c + q * M1) * nx + s));
     });
   });
+  // Twiddles to LDS; the first pass needs none, and the barrier after its
+  // LDS exchange orders these writes before the first use.
+  if constexpr (TS::kMode != 0) {
+    const float2* src = TS::staged_from(S.tw_col, S.twn_col);
+    for (int i = threadIdx.x; i < TS::kLds; i += NT) twl[i] = gld(src, i);
+  }
   fft_forward<Plan, T>(v, t, tw, lv);
 
   // Fourier-domain step; element e = c*RL + r holds ky = t + T c + r ML.
@@ -474,7 +496,7 @@ plain_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst, const f
       constexpr int e = decltype(ee)::value;
       v[e] = src[rbase + t + T * (e / R1) + (e % R1) * M1];
     });
-    fft_forward<Plan, T>(v, t, tw, lv);
+    fft_forward<Plan, T>(v, t, TwPass{tw}, lv);
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       dst[rbase + t + T * (e / RL) + (e % RL) * ML] = v[e];
@@ -484,7 +506,7 @@ plain_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst, const f
       constexpr int e = decltype(ee)::value;
       v[e] = src[rbase + t + T * (e / RL) + (e % RL) * ML];
     });
-    fft_inverse<Plan, T>(v, t, tw + Plan::tw_total(), lv);
+    fft_inverse<Plan, T>(v, t, TwPass{tw + Plan::tw_total()}, lv);
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       dst[rbase + t + T * (e / R1) + (e % R1) * M1] = v[e];
@@ -512,7 +534,7 @@ plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw) {
       constexpr int e = decltype(ee)::value;
       v[e] = a[(size_t)(t + T * (e / R1) + (e % R1) * M1) * nx + s];
     });
-    fft_forward<Plan, T>(v, t, tw, lv);
+    fft_forward<Plan, T>(v, t, TwPass{tw}, lv);
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       a[(size_t)(t + T * (e / RL) + (e % RL) * ML) * nx + s] = v[e];
@@ -522,7 +544,7 @@ plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw) {
       constexpr int e = decltype(ee)::value;
       v[e] = a[(size_t)(t + T * (e / RL) + (e % RL) * ML) * nx + s];
     });
-    fft_inverse<Plan, T>(v, t, tw + Plan::tw_total(), lv);
+    fft_inverse<Plan, T>(v, t, TwPass{tw + Plan::tw_total()}, lv);
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       a[(size_t)(t + T * (e / R1) + (e % R1) * M1) * nx + s] = v[e];
