@@ -389,3 +389,61 @@ def pwf_joint(ys, prob: Problem, iters: int, eta_t: float, psi0s=None):
             norm += mj
         t = t - eta_t * g_t / norm
     return [s.psi for s in states], t, hist
+
+
+# --------------------------------------------------------------------------- calibration front end
+#
+# Methods ("Intensity optical transfer function (IOTF)", Eq. 3) and Results
+# ("Diffuser transmission function"): the coherence lengths come from the
+# normalised autocorrelation of the reference speckle through the Siegert
+# relation g2 = 1 + |g1|^2 and the Gaussian model g2 = 1 + exp(-pi dx^2 /
+# x_coh^2), one axis at a time, averaged along the other axis; the diffuser
+# is the reference speckle deconvolved by the IOTF (Wiener), square-rooted
+# with zero phase and propagated back over L2.  Readings:
+#
+# * g2 is taken circularly (periodic images), g2(d) = <I(r) I(r + d)> / <I>^2;
+# * the fit allows a contrast c (blurred or noisy speckle is not fully
+#   developed): ln(g2(d) - 1) = ln c - pi d^2 p^2 / x_coh^2, least squares
+#   over d = 1 .. K (K >= 2), K the last shift before g2 - 1 first drops
+#   below FIT_FLOOR (g2(1) - 1); d = 0 carries the noise variance and is
+#   left out;
+# * Wiener filter IOTF / (IOTF^2 + eps) with eps given by the caller
+#   (relative to IOTF(0) = 1); negative deconvolved intensities are clipped
+#   to 0 before the square root.
+
+FIT_FLOOR = 0.02
+
+
+def speckle_g2(I, max_shift: int):
+    """Normalised circular autocorrelations ``(g2_x[d], g2_y[d])``, d = 0 .. max_shift."""
+    I = np.asarray(I, np.float64)
+    m2 = np.mean(I) ** 2
+    gx = np.array([np.mean(I * np.roll(I, -d, axis=1)) / m2 for d in range(max_shift + 1)])
+    gy = np.array([np.mean(I * np.roll(I, -d, axis=0)) / m2 for d in range(max_shift + 1)])
+    return gx, gy
+
+
+def fit_coherence_length(g2, pixel_m: float):
+    """``(x_coh, c)`` of the Gaussian model fitted to ``g2`` (see the readings above)."""
+    s = np.asarray(g2, np.float64) - 1.0
+    k = 1
+    while k + 1 < len(s) and s[k + 1] >= FIT_FLOOR * s[1]:
+        k += 1
+    if k < 2:
+        raise ValueError("autocorrelation too narrow to fit")
+    d = np.arange(1, k + 1, dtype=np.float64)
+    A = np.stack([np.ones_like(d), (d * pixel_m) ** 2], axis=1)
+    coef, *_ = np.linalg.lstsq(A, np.log(s[1:k + 1]), rcond=None)
+    return math.sqrt(-math.pi / coef[1]), math.exp(coef[0])
+
+
+def wiener_deconvolve(I, iotf, eps: float):
+    """``Re F^-1{ F{I} IOTF / (IOTF^2 + eps) }``."""
+    return np.real(filter_(I, iotf / (iotf * iotf + eps)))
+
+
+def diffuser_from_reference(I_ref, prob: Problem, eps: float):
+    """Diffuser estimate: back-propagation over L2 of the zero-phase field
+    ``sqrt(max(Wiener(I_ref), 0))``."""
+    a = np.sqrt(np.maximum(wiener_deconvolve(I_ref, prob.iotf, eps), 0.0))
+    return free_propagation(a, prob, -prob.z2_m)
