@@ -447,3 +447,89 @@ def diffuser_from_reference(I_ref, prob: Problem, eps: float):
     ``sqrt(max(Wiener(I_ref), 0))``."""
     a = np.sqrt(np.maximum(wiener_deconvolve(I_ref, prob.iotf, eps), 0.0))
     return free_propagation(a, prob, -prob.z2_m)
+
+
+# --------------------------------------------------------------------------- tomography
+#
+# Methods ("Reconstruction procedure"): filtered back-projection with the
+# Ram-Lak filter applied slice by slice (every detector row is one parallel-
+# beam sinogram over the angles in [0, pi)), then the constant lambda / (2 pi p)
+# turns the reconstructed phase and attenuation into delta and beta.
+# Readings:
+#
+# * the Ram-Lak filter is the band-limited ramp in the sample domain (unit
+#   detector spacing): h(0) = 1/4, h(n odd) = -1/(pi^2 n^2), h(n even) = 0,
+#   i.e. the inverse transform of |f| on |f| <= 1/2, applied by circular
+#   convolution of rows zero-padded to n_pad = max(64, next power of two of
+#   2 nx) (the padding of MATLAB's iradon);
+# * geometry of the synthetic phantom: detector pixel i sees u = i + 1/2 -
+#   nx/2 (voxel units); a sample point (X, Z) of a slice projects at
+#   u = X cos(theta) - Z sin(theta); reconstruction voxel centres X, Z =
+#   k + 1/2 - N/2; back-projection interpolates linearly in u and treats
+#   samples outside the detector as 0;
+# * f(X, Z) = (pi / P) sum_j q_j(u_j(X, Z)) for P equally spaced angles;
+# * psi = -mu + i phi is reconstructed as one complex sinogram (the filter is
+#   real): delta = Im(f) lambda / (2 pi p), beta = -Re(f) lambda / (2 pi p);
+# * the quadratic background fit of the paper is not part of this step.
+
+
+def fbp_pad_length(nx: int) -> int:
+    return max(64, 1 << int(math.ceil(math.log2(2 * nx))))
+
+
+def ramp_kernel(n_pad: int) -> np.ndarray:
+    """Band-limited ramp h(n) on a circular grid of ``n_pad`` samples."""
+    n = np.arange(n_pad)
+    n = np.where(n <= n_pad // 2, n, n - n_pad)
+    h = np.zeros(n_pad)
+    h[n == 0] = 0.25
+    odd = (n % 2) != 0
+    h[odd] = -1.0 / (math.pi ** 2 * n[odd].astype(np.float64) ** 2)
+    return h
+
+
+def fbp_filter(sino, n_pad: int | None = None) -> np.ndarray:
+    """Rows of ``sino`` [P, nx] convolved with the ramp (zero-padded, circular)."""
+    sino = np.asarray(sino)
+    p, nx = sino.shape
+    n_pad = fbp_pad_length(nx) if n_pad is None else n_pad
+    pad = np.zeros((p, n_pad), np.complex128)
+    pad[:, :nx] = sino
+    H = np.real(np.fft.fft(ramp_kernel(n_pad)))
+    return np.fft.ifft(np.fft.fft(pad, axis=1) * H[None, :], axis=1)[:, :nx]
+
+
+def backproject(q, angles, n_out: int) -> np.ndarray:
+    """``(pi / P) sum_j q_j(X cos theta_j - Z sin theta_j)`` on the n_out x n_out grid [Z, X]."""
+    q = np.asarray(q)
+    p, nx = q.shape
+    c = np.arange(n_out) + 0.5 - n_out / 2.0
+    X = c[None, :]
+    Z = c[:, None]
+    out = np.zeros((n_out, n_out), np.complex128)
+    for j, th in enumerate(angles):
+        idx = X * math.cos(th) - Z * math.sin(th) + nx / 2.0 - 0.5
+        i0 = np.floor(idx).astype(np.int64)
+        w = idx - i0
+        lo = np.where((i0 >= 0) & (i0 < nx), q[j][np.clip(i0, 0, nx - 1)], 0.0)
+        hi = np.where((i0 + 1 >= 0) & (i0 + 1 < nx), q[j][np.clip(i0 + 1, 0, nx - 1)], 0.0)
+        out += (1.0 - w) * lo + w * hi
+    return out * (math.pi / p)
+
+
+def fbp_slice(sino, angles, n_out: int) -> np.ndarray:
+    return backproject(fbp_filter(sino), angles, n_out)
+
+
+def fbp_volume(psis, angles, n_out: int, rows=None) -> np.ndarray:
+    """Slices ``rows`` (default all) of the tomogram of the projections ``psis``: [row, Z, X]."""
+    psis = [np.asarray(p) for p in psis]
+    ny = psis[0].shape[0]
+    rows = range(ny) if rows is None else rows
+    return np.stack([fbp_slice(np.stack([p[y] for p in psis]), angles, n_out) for y in rows])
+
+
+def refractive_index(vol, wavelength_m: float, pixel_m: float):
+    """``(delta, beta)`` of a tomogram of psi = -mu + i phi."""
+    c = wavelength_m / (2.0 * math.pi * pixel_m)
+    return np.imag(vol) * c, -np.real(vol) * c
