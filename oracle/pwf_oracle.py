@@ -533,3 +533,47 @@ def refractive_index(vol, wavelength_m: float, pixel_m: float):
     """``(delta, beta)`` of a tomogram of psi = -mu + i phi."""
     c = wavelength_m / (2.0 * math.pi * pixel_m)
     return np.imag(vol) * c, -np.real(vol) * c
+
+
+# --------------------------------------------------------------------------- diagnostics
+#
+# Methods ("Reconstruction procedure"): the RMSE image of one measurement is
+# |y - f(x)| normalised by the mean intensity of the reference speckle, in
+# percent.  Methods ("Fourier shell correlation", Eq. 16): the normalised
+# cross-correlation of two tomograms' transforms over shells |k| = kappa; the
+# paper's resolution criterion is FSC = 1/4 (its Eqs. 17-18).  Readings: the
+# shells are integer bins of |k| in frequency-index units, kappa =
+# round(sqrt(kx^2 + ky^2 + kz^2)) with signed indices of a cubic grid, up to
+# n/2; the numerator is the real part of the shell sum (exact for real
+# volumes); FRC is the same on square images.
+
+
+def rmse_image(y, psi, prob: Problem, ref_mean: float):
+    f, _, _ = physical_model(psi, prob)
+    return 100.0 * np.abs(np.asarray(y, np.float64) - f) / ref_mean
+
+
+def shell_correlation(g1, g2):
+    """FSC (3-D) or FRC (2-D) of two real arrays on a cubic / square grid, shells 0..n/2."""
+    g1 = np.asarray(g1, np.float64)
+    g2 = np.asarray(g2, np.float64)
+    n = g1.shape[0]
+    G1 = np.fft.fftn(g1)
+    G2 = np.fft.fftn(g2)
+    k = np.fft.fftfreq(n) * n
+    grids = np.meshgrid(*([k] * g1.ndim), indexing="ij")
+    shell = np.rint(np.sqrt(sum(g * g for g in grids))).astype(np.int64)
+    nsh = n // 2 + 1
+    keep = shell < nsh
+    num = np.bincount(shell[keep], np.real(np.conj(G1) * G2)[keep], nsh)
+    a = np.bincount(shell[keep], (np.abs(G1) ** 2)[keep], nsh)
+    b = np.bincount(shell[keep], (np.abs(G2) ** 2)[keep], nsh)
+    return num / np.sqrt(a * b)
+
+
+def resolution_from_fsc(fsc, n: int, pixel_m: float, criterion: float = 0.25):
+    """Length ``n p / kappa`` at the first shell (from 1) where the FSC falls below ``criterion``."""
+    for kappa in range(1, len(fsc)):
+        if fsc[kappa] < criterion:
+            return n * pixel_m / kappa
+    return 2.0 * pixel_m
