@@ -64,14 +64,15 @@ def measured_traffic(sweep: int, pixels: int, width: int = 0):
 
 
 COPY_BYTES = 1 << 30
-# kernel-name fragments of each fused sweep at 1024^2 (template op ids of row_sweep / col_sweep)
-SWEEP_KERNELS = ["row_sweep<1024, 0>", "col_sweep<1024, {w}, 0>", "row_sweep<1024, 2>", "col_sweep<1024, {w}, 1>",
-                 "row_sweep<1024, 4>", "col_sweep<1024, {w}, 4>", "row_sweep<1024, 5>", "col_sweep<1024, {w}, 2>",
-                 "row_sweep<1024, 3>", "col_sweep<1024, {w}, 3>", "row_sweep<1024, 6>", "col_sweep<1024, {w}, 6>"]
+# kernel-name fragments of each fused sweep at 1024^2 (template op ids of row_sweep / col_sweep;
+# a row sweep's third template argument is its radix plan)
+SWEEP_KERNELS = ["row_sweep<1024, 0,", "col_sweep<1024, {w}, 0>", "row_sweep<1024, 2,", "col_sweep<1024, {w}, 1>",
+                 "row_sweep<1024, 4,", "col_sweep<1024, {w}, 4>", "row_sweep<1024, 5,", "col_sweep<1024, {w}, 2>",
+                 "row_sweep<1024, 3,", "col_sweep<1024, {w}, 3>", "row_sweep<1024, 6,", "col_sweep<1024, {w}, 6>"]
 
 
 def autotune(batch) -> dict:
-    """Pick the column-tile width per grid side (pwf_autotune) and report the choice."""
+    """Pick column-tile widths and row plans per grid side (pwf_autotune); report the widths."""
     from paper_2503_20146_amd import _lib
     lib = _lib.load()
     ws, nb = batch._ws()
@@ -79,7 +80,7 @@ def autotune(batch) -> dict:
     _lib.check(lib.pwf_autotune(batch._c, batch.n, 5, ws, nb,
                                 __import__("ctypes").c_void_p(torch.cuda.current_stream().cuda_stream)),
                "pwf_autotune")
-    return {n: lib.pwf_column_tile(n) for n in sorted({p.ny for p in batch.problems})}
+    return {n: [lib.pwf_column_tile(n, s) for s in range(1, 12, 2)] for n in sorted({p.ny for p in batch.problems})}
 
 
 def _read_counter_csv(path: str, counter: str):
@@ -232,11 +233,13 @@ def main() -> int:
     tiles = {}
     if args.col_tile:
         from paper_2503_20146_amd import _lib
-        _lib.check(_lib.load().pwf_set_column_tile(1024, args.col_tile), "pwf_set_column_tile")
-        tiles = {1024: args.col_tile}
+        _lib.check(_lib.load().pwf_set_column_tile(1024, -1, args.col_tile), "pwf_set_column_tile")
+        tiles = {1024: [args.col_tile] * 6}
     elif not args.no_autotune:
         tiles = autotune(batch)
         print(f"[bench] column tiles {tiles}", file=sys.stderr, flush=True)
+    from paper_2503_20146_amd import _lib as _l
+    row_plans = {1024: [_l.load().pwf_row_plan(1024, s) for s in range(0, 12, 2)]}
 
     if args.sweep_only is not None:
         batch.solve(ys, 2)
@@ -282,7 +285,7 @@ def main() -> int:
     dom = max(range(12), key=lambda s: sweep_s[s])
     alg_bytes = SWEEP_BYTES_PER_PX[dom] * pixels
     achieved = alg_bytes / sweep_s[dom] / 1e9
-    traffic = measured_traffic(dom, pixels, tiles.get(1024, 0))
+    traffic = measured_traffic(dom, pixels, _l.load().pwf_column_tile(1024, dom) if dom % 2 else 0)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": SWEEP_NAMES[dom], "launch_ms": round(sweep_s[dom] * 1e3, 4),
@@ -319,7 +322,8 @@ def main() -> int:
         "config": {"workload": f"{args.projections} projections x 1024^2 of a 40-ellipsoid phantom over 0-180 deg, "
                                f"shared diffuser, {args.iters} PWF iterations per step in one hipGraph",
                    "projections": args.projections, "grid": [geo.ny, geo.nx], "iterations_per_step": args.iters,
-                   "column_tiles": tiles, "parallelism": "single GPU"},
+                   "column_tiles_S1_S3_S5_S7_S9_S11": tiles, "row_plans_S0_S2_S4_S6_S8_S10": row_plans,
+                   "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "plain_baseline": plain,
     }
     print(json.dumps(rec), flush=True)

@@ -125,6 +125,15 @@ size_t pwf_workspace_size(const pwf_problem* problems, int32_t n);
 pwf_status pwf_forward(const pwf_problem* problems, int32_t n, const void* const* psi, float* const* f_out,
                        void* workspace, size_t workspace_bytes, void* stream);
 
+/* RMSE image of the retrieved fields (Methods, "Reconstruction procedure"):
+ * out[i] = 100 |y_i - f(psi_i)| / ref_mean[i], the misfit of the forward model
+ * in percent of the reference speckle's mean intensity (one measurement, so
+ * the root-mean-square over measurements is the absolute value).  y: device
+ * float32 [ny][nx]; ref_mean: host float64 [n] (> 0); out: device float32. */
+pwf_status pwf_rmse_image(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
+                          const double* ref_mean, float* const* out, void* workspace, size_t workspace_bytes,
+                          void* stream);
+
 /* Loss (Eq. 2), Wirtinger derivative g (WirtingerDerivative of Algorithm S2,
  * normalised by max|t|^2) and update direction d = Preconditioner(g) +
  * Regularizer(psi) at psi.  The real gradient of the loss is
@@ -176,6 +185,27 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
                      int32_t iters, double corr_tol, double* loss_hist, int32_t* iters_done, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* Workspace bytes for pwf_solve_joint (pwf_workspace_size plus one field per
+ * instance and the diffuser-step reductions); 0 if the batch is invalid. */
+size_t pwf_joint_workspace_size(const pwf_problem* problems, int32_t n);
+
+/* Joint diffuser refinement (Results, "Diffuser transmission function";
+ * Fig. S12): Algorithm S1 on every instance, as pwf_solve with a fixed
+ * iteration count, and after each iteration a gradient step on the shared
+ * diffuser t:
+ *   t <- t - eta_t sum_j conj(u1_j) a2_j / sum_j max|u1_j|^2
+ * where u1_j is instance j's field incident on the diffuser and a2_j its
+ * misfit back-propagated to the diffuser plane (conj(u1) a2 = dL/dt*; the
+ * paper gives no rule, this is the library's reading).  All instances must
+ * share one diffuser pointer and one grid shape (else PWF_ERR_ARG); that
+ * device array is READ AND WRITTEN in place and holds the refined t on
+ * return.  eta_t >= 0 (0: t unchanged, the result equals pwf_solve's).
+ * Sums over instances run in instance order in FP64 (deterministic).
+ * workspace: pwf_joint_workspace_size bytes. */
+pwf_status pwf_solve_joint(const pwf_problem* problems, int32_t n, const float* const* y, void* const* psi_out,
+                           int32_t iters, double eta_t, double* loss_hist, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
 /* Reference GPU path for speed comparisons: the literal Algorithm S1/S2 on
  * ONE instance, one kernel per operation (16 two-dimensional FFTs plus
  * element-wise kernels per iteration), no fusion, no batching, no graph.
@@ -193,18 +223,34 @@ pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi
 pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep, int32_t reps, void* workspace,
                            size_t workspace_bytes, void* stream);
 
-/* Column-sweep tile width (columns per workgroup) for grid side n.  Two
- * widths are compiled per side (128: 32/16, 256-1024: 16/8, 2048: 8/4); 0
- * restores the default.  PWF_ERR_SIZE / PWF_ERR_ARG for an unsupported side
- * or width.  Process-wide; applies to calls issued afterwards. */
-pwf_status pwf_set_column_tile(int32_t n, int32_t width);
+/* Tile width (columns per workgroup) of the column sweep S`sweep` of the
+ * iteration (sweep = 1, 3, 5, 7, 9 or 11; -1: every column sweep, including
+ * those of pwf_forward / pwf_gradient) for grid side n.  Two widths are
+ * compiled per side (128: 32/16, 256: 16/32, 512: 16/8, 1024: 8/4,
+ * 2048: 4/2); 0 restores the default.  PWF_ERR_SIZE / PWF_ERR_ARG for an
+ * unsupported side, sweep or width.  Process-wide; applies to calls issued
+ * afterwards. */
+pwf_status pwf_set_column_tile(int32_t n, int32_t sweep, int32_t width);
 
-/* Current column-sweep tile width for grid side n (0 if unsupported). */
-int32_t pwf_column_tile(int32_t n);
+/* Current tile width of column sweep S`sweep` for side n (0 if unsupported). */
+int32_t pwf_column_tile(int32_t n, int32_t sweep);
 
-/* Autotuner: for each grid shape in the batch, time the column sweeps at
- * every compiled tile width (`reps` launches each, HIP events on `stream`,
- * synchronous) and keep the fastest, as pwf_set_column_tile would.  Clobbers
+/* FFT plan of the row sweep S`sweep` of the iteration (sweep = 0, 2, 4, 6, 8
+ * or 10) for grid side n: plan 0 is the side's default radix plan, 1 its
+ * alternative plan with fewer elements per lane (e.g. 32x32 and 16x16x4 at
+ * 1024), -1 restores the built-in choice.  PWF_ERR_SIZE / PWF_ERR_ARG for an
+ * unsupported side, sweep or plan.  Process-wide; applies to calls issued
+ * afterwards. */
+pwf_status pwf_set_row_plan(int32_t n, int32_t sweep, int32_t plan);
+
+/* Current plan (0 or 1) of row sweep S`sweep` for side n; -1 if unsupported. */
+int32_t pwf_row_plan(int32_t n, int32_t sweep);
+
+/* Autotuner: for each grid shape in the batch, time each of the twelve
+ * sweeps of the iteration with every compiled tile width (column sweeps) or
+ * radix plan (row sweeps), `reps` launches each, HIP events on `stream`,
+ * synchronous, and keep the fastest per sweep, as pwf_set_column_tile /
+ * pwf_set_row_plan would.  Clobbers
  * the workspace contents. */
 pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, void* workspace,
                         size_t workspace_bytes, void* stream);
@@ -217,6 +263,67 @@ void pwf_set_graph_mode(int32_t on);
  * error, else PWF_OK.  Every loss-computing call clears the flag when it
  * starts. */
 pwf_status pwf_sync_status(void* workspace, void* stream);
+
+/* ---------------------------------------------------------------- calibration
+ * The steps before the iteration, run once per dataset (Methods, "Intensity
+ * optical transfer function (IOTF)", Eq. 3; Results, "Diffuser transmission
+ * function"). */
+
+/* Device workspace bytes for pwf_speckle_g2 (independent of the image). */
+size_t pwf_speckle_workspace_size(void);
+
+/* Normalised circular autocorrelations of the reference speckle `ref`
+ * (device float32 [ny][nx]) along x and along y, each averaged over the other
+ * axis: g2x[d] = <I(x,y) I(x+d,y)> / <I>^2 and likewise g2y, d = 0..max_shift
+ * (0 <= max_shift <= 32, < nx, ny).  Sums in FP64 in a fixed order
+ * (deterministic).  g2x, g2y: HOST float64 [max_shift + 1]; the call
+ * synchronises on `stream`.  PWF_ERR_ARG for bad sizes or a non-positive
+ * mean, PWF_ERR_WORKSPACE for a missing / misaligned / short workspace. */
+pwf_status pwf_speckle_g2(const float* ref, int32_t nx, int32_t ny, int32_t max_shift, double* g2x, double* g2y,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Coherence length from g2 (host arrays, count >= 3 shifts from d = 0) by the
+ * Siegert relation and the Gaussian model of Eq. 3 with a free contrast c:
+ * least squares of ln(g2(d) - 1) = ln c - pi (d p)^2 / coh^2 over d = 1..K,
+ * K the last shift before g2 - 1 first drops below 2% of g2(1) - 1 (d = 0
+ * holds the noise variance).  coh_m: metres; contrast may be NULL.  Host-only;
+ * PWF_ERR_ARG when fewer than two shifts qualify or the fit does not decay.
+ * The IOTF of a source with x_coh has sigma_x_px = x_coh / (2 sqrt(pi) p). */
+pwf_status pwf_fit_coherence(const double* g2, int32_t count, double pixel_m, double* coh_m, double* contrast);
+
+/* Diffuser estimate from the reference speckle `ref` (device float32):
+ *   t = FreePropagation( sqrt(max(Re F^-1{F{ref} IOTF / (IOTF^2 + eps)}, 0)), -L2 )
+ * i.e. Wiener deconvolution by the problem's IOTF, zero phase (the paper
+ * fixes the unknown phase of the reference to zero) and back-propagation
+ * over L2.  problem->diffuser is not read; t_out: device complex64 [ny][nx].
+ * workspace: pwf_workspace_size(problem, 1) bytes.  eps >= 0. */
+pwf_status pwf_diffuser_from_reference(const pwf_problem* problem, const float* ref, double eps, void* t_out,
+                                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------- tomography
+ * The step after the iteration (Methods, "Reconstruction procedure"). */
+
+/* Workspace bytes for pwf_fbp; 0 when unsupported (1 <= n_proj <= 4096,
+ * 64 <= nx <= 1024, ny a positive multiple of 32). */
+size_t pwf_fbp_workspace_size(int32_t n_proj, int32_t nx, int32_t ny);
+
+/* Filtered back-projection of n_proj retrieved projections psi[j] (device
+ * complex64 [ny][nx], psi = -mu + i phi) taken at angles_rad[j] (host) about
+ * the detector's y axis, slice by slice (every detector row y is one
+ * parallel-beam sinogram):
+ *   vol[y][Z][X] = scale (pi / n_proj) sum_j q_j,y(X cos th_j - Z sin th_j)
+ * q: each row zero-padded to the next power of two of 2 nx (at least 64) and
+ * circularly convolved with the band-limited (Ram-Lak) ramp h(0) = 1/4,
+ * h(odd n) = -1/(pi^2 n^2); detector pixel i at u = i + 1/2 - nx/2, voxel
+ * centres X, Z = k + 1/2 - n_out/2 (pixel units), linear interpolation, 0
+ * outside the detector.  With scale = lambda / (2 pi p), vol = -beta + i delta.
+ * vol_out: device complex64 [ny][n_out][n_out], n_out a multiple of 16.
+ * Angles should be equally spaced over [0, pi) for the pi / n_proj weight.
+ * FP32 sums.  PWF_ERR_SIZE for unsupported shapes, PWF_ERR_ARG for null or
+ * non-finite arguments, PWF_ERR_WORKSPACE for a missing / short workspace. */
+pwf_status pwf_fbp(const void* const* psi, int32_t n_proj, int32_t nx, int32_t ny, const double* angles_rad,
+                   int32_t n_out, double scale, void* vol_out, void* workspace, size_t workspace_bytes,
+                   void* stream);
 
 /* Release the library's twiddle tables and cached graphs. */
 void pwf_finalize(void);

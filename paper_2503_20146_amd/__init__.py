@@ -7,12 +7,20 @@ The computation lives in ``libpwf.so`` (hand-written HIP for gfx950, C ABI in
 from .api import (  # noqa: F401
     DEFAULT_ALPHA,
     DEFAULT_ETA,
+    DEFAULT_ETA_T,
     DEFAULT_GAMMA,
     DEFAULT_PRECOND_SCALE,
     PWF,
     Problem,
+    calibrate_source,
+    diffuser_from_reference,
+    fbp,
+    fit_coherence,
+    speckle_g2,
     problem_from_geometry,
+    set_column_tile,
     set_graph_mode,
+    set_row_plan,
 )
 from ._lib import PwfError, load  # noqa: F401
 from .autograd import PWFLoss, pwf_loss  # noqa: F401

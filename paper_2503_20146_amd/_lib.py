@@ -58,13 +58,29 @@ SIGNATURES = {
     "pwf_step": (_i32, [_P(pwf_problem), _i32, _P(pwf_state), _vp, _vp, ctypes.c_size_t, _vp]),
     "pwf_solve": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _i32, ctypes.c_double, _vp, _P(_i32), _vp,
                          ctypes.c_size_t, _vp]),
+    "pwf_joint_workspace_size": (ctypes.c_size_t, [_P(pwf_problem), _i32]),
+    "pwf_solve_joint": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _i32, ctypes.c_double, _vp, _vp,
+                               ctypes.c_size_t, _vp]),
     "pwf_solve_plain": (_i32, [_P(pwf_problem), _vp, _vp, _i32, _vp, _vp, ctypes.c_size_t, _vp]),
     "pwf_bench_sweep": (_i32, [_P(pwf_problem), _i32, _i32, _i32, _vp, ctypes.c_size_t, _vp]),
-    "pwf_set_column_tile": (_i32, [_i32, _i32]),
-    "pwf_column_tile": (_i32, [_i32]),
+    "pwf_set_column_tile": (_i32, [_i32, _i32, _i32]),
+    "pwf_column_tile": (_i32, [_i32, _i32]),
+    "pwf_set_row_plan": (_i32, [_i32, _i32, _i32]),
+    "pwf_row_plan": (_i32, [_i32, _i32]),
     "pwf_autotune": (_i32, [_P(pwf_problem), _i32, _i32, _vp, ctypes.c_size_t, _vp]),
     "pwf_set_graph_mode": (None, [_i32]),
     "pwf_sync_status": (_i32, [_vp, _vp]),
+    "pwf_speckle_workspace_size": (ctypes.c_size_t, []),
+    "pwf_speckle_g2": (_i32, [_vp, _i32, _i32, _i32, _P(ctypes.c_double), _P(ctypes.c_double), _vp, ctypes.c_size_t,
+                              _vp]),
+    "pwf_fit_coherence": (_i32, [_P(ctypes.c_double), _i32, ctypes.c_double, _P(ctypes.c_double),
+                                 _P(ctypes.c_double)]),
+    "pwf_rmse_image": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _P(ctypes.c_double), _P(_vp), _vp,
+                              ctypes.c_size_t, _vp]),
+    "pwf_fbp_workspace_size": (ctypes.c_size_t, [_i32, _i32, _i32]),
+    "pwf_fbp": (_i32, [_P(_vp), _i32, _i32, _i32, _P(ctypes.c_double), _i32, ctypes.c_double, _vp, _vp,
+                       ctypes.c_size_t, _vp]),
+    "pwf_diffuser_from_reference": (_i32, [_P(pwf_problem), _vp, ctypes.c_double, _vp, _vp, ctypes.c_size_t, _vp]),
     "pwf_finalize": (None, []),
 }
 

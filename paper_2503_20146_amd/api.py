@@ -21,6 +21,7 @@ DEFAULT_ETA = 0.5
 DEFAULT_ALPHA = complex(0.1, 0.01)
 DEFAULT_GAMMA = 1.0
 DEFAULT_PRECOND_SCALE = 1.0 / (4.0 * math.pi ** 2)
+DEFAULT_ETA_T = 0.5  # diffuser step of the joint refinement (pwf_solve_joint)
 
 
 @dataclasses.dataclass
@@ -117,6 +118,17 @@ class PWF:
               "pwf_forward")
         return out
 
+    def rmse_image(self, psi: Sequence[torch.Tensor], y: Sequence[torch.Tensor], ref_mean: Sequence[float]):
+        """RMSE images 100 |y - f(psi)| / ref_mean (pwf_rmse_image)."""
+        out = self._empty(torch.float32)
+        ws, nb = self._ws()
+        means = (ctypes.c_double * self.n)(*[float(m) for m in ref_mean])
+        check(self.lib.pwf_rmse_image(self._c, self.n, _ptrs(psi, torch.complex64, self.shapes),
+                                      _ptrs(y, torch.float32, self.shapes), means,
+                                      _ptrs(out, torch.float32, self.shapes), ws, nb, _stream(self.device)),
+              "pwf_rmse_image")
+        return out
+
     def gradient(self, psi, y, want_g: bool = True, want_d: bool = True):
         g = self._empty(torch.complex64) if want_g else None
         d = self._empty(torch.complex64) if want_d else None
@@ -174,6 +186,27 @@ class PWF:
             return psi_out, hist, [done[i] for i in range(self.n)]
         return psi_out, hist
 
+    def solve_joint(self, y, iters: int, eta_t: float = DEFAULT_ETA_T, psi_out=None, loss_hist: bool = True):
+        """Joint diffuser refinement: Algorithm S1 on every instance plus a diffuser
+        step per iteration (pwf_solve_joint).  All instances must share one diffuser
+        tensor, which is updated in place."""
+        d0 = self.problems[0].diffuser
+        if any(p.diffuser.data_ptr() != d0.data_ptr() for p in self.problems):
+            raise ValueError("joint refinement needs one diffuser tensor shared by every instance")
+        size = self.lib.pwf_joint_workspace_size(self._c, self.n)
+        if size == 0:
+            raise ValueError("invalid problem description")
+        if self.workspace.numel() < size:
+            self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        psi_out = self._empty(torch.complex64) if psi_out is None else list(psi_out)
+        hist = torch.empty((self.n, max(iters, 1)), dtype=torch.float64, device=self.device) if loss_hist else None
+        ws, nb = self._ws()
+        check(self.lib.pwf_solve_joint(self._c, self.n, _ptrs(y, torch.float32, self.shapes),
+                                       _ptrs(psi_out, torch.complex64, self.shapes), iters, float(eta_t),
+                                       ctypes.c_void_p(hist.data_ptr()) if hist is not None else None, ws, nb,
+                                       _stream(self.device)), "pwf_solve_joint")
+        return psi_out, hist
+
     def loss_grad(self, psi, y):
         """Loss and real gradient dL/dRe psi + i dL/dIm psi (forward fields recomputed)."""
         grad = self._empty(torch.complex64)
@@ -209,3 +242,86 @@ class PWF:
 
 def set_graph_mode(on: bool) -> None:
     _lib.load().pwf_set_graph_mode(1 if on else 0)
+
+
+def set_column_tile(n: int, width: int, sweep: int = -1) -> None:
+    """Tile width of column sweep S`sweep` (1, 3, ..., 11; -1 all) for side n (0: built-in default)."""
+    check(_lib.load().pwf_set_column_tile(n, sweep, width), "pwf_set_column_tile")
+
+
+def set_row_plan(n: int, sweep: int, plan: int) -> None:
+    """Radix plan of row sweep S`sweep` (0, 2, ..., 10) for side n: 0 default, 1 alternative, -1 built-in."""
+    check(_lib.load().pwf_set_row_plan(n, sweep, plan), "pwf_set_row_plan")
+
+
+# ---------------------------------------------------------------- calibration front end
+
+def speckle_g2(ref: torch.Tensor, max_shift: int = 32):
+    """Normalised autocorrelations (g2_x, g2_y) of a reference speckle (pwf_speckle_g2)."""
+    if not ref.is_cuda or ref.dtype != torch.float32 or not ref.is_contiguous() or ref.dim() != 2:
+        raise ValueError("ref must be a contiguous float32 GPU image")
+    lib = _lib.load()
+    ws = torch.empty(lib.pwf_speckle_workspace_size(), dtype=torch.uint8, device=ref.device)
+    gx = (ctypes.c_double * (max_shift + 1))()
+    gy = (ctypes.c_double * (max_shift + 1))()
+    ny, nx = ref.shape
+    check(lib.pwf_speckle_g2(ctypes.c_void_p(ref.data_ptr()), nx, ny, max_shift, gx, gy,
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref.device)), "pwf_speckle_g2")
+    return list(gx), list(gy)
+
+
+def fit_coherence(g2, pixel_m: float):
+    """(coherence length in metres, contrast) of the Gaussian Siegert model (pwf_fit_coherence)."""
+    arr = (ctypes.c_double * len(g2))(*g2)
+    coh, c = ctypes.c_double(), ctypes.c_double()
+    check(_lib.load().pwf_fit_coherence(arr, len(g2), pixel_m, ctypes.byref(coh), ctypes.byref(c)),
+          "pwf_fit_coherence")
+    return coh.value, c.value
+
+
+def calibrate_source(ref: torch.Tensor, pixel_m: float, max_shift: int = 32):
+    """Coherence lengths (x_coh, y_coh) in metres and the IPSF sigmas in pixels."""
+    gx, gy = speckle_g2(ref, max_shift)
+    xc, _ = fit_coherence(gx, pixel_m)
+    yc, _ = fit_coherence(gy, pixel_m)
+    k = 2.0 * math.sqrt(math.pi) * pixel_m
+    return {"x_coh_m": xc, "y_coh_m": yc, "sigma_x_px": xc / k, "sigma_y_px": yc / k, "g2x": gx, "g2y": gy}
+
+
+def diffuser_from_reference(problem: Problem, ref: torch.Tensor, eps: float = 1e-3) -> torch.Tensor:
+    """Diffuser estimate from the reference speckle (pwf_diffuser_from_reference)."""
+    lib = _lib.load()
+    c = (_lib.pwf_problem * 1)(problem.to_c())
+    size = lib.pwf_workspace_size(c, 1)
+    if size == 0:
+        raise ValueError("invalid problem description")
+    ws = torch.empty(size, dtype=torch.uint8, device=ref.device)
+    t = torch.empty((problem.ny, problem.nx), dtype=torch.complex64, device=ref.device)
+    check(lib.pwf_diffuser_from_reference(c, ctypes.c_void_p(ref.data_ptr()), float(eps), ctypes.c_void_p(t.data_ptr()),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref.device)),
+          "pwf_diffuser_from_reference")
+    return t
+
+
+# ---------------------------------------------------------------- tomography
+
+def fbp(psis: Sequence[torch.Tensor], angles_rad: Sequence[float], n_out: int | None = None,
+        scale: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Filtered back-projection of retrieved projections (pwf_fbp): [ny, n_out, n_out] complex64.
+
+    With ``scale = wavelength / (2 pi pixel)`` the result is ``-beta + i delta``."""
+    lib = _lib.load()
+    n = len(psis)
+    ny, nx = psis[0].shape
+    n_out = nx if n_out is None else n_out
+    size = lib.pwf_fbp_workspace_size(n, nx, ny)
+    if size == 0:
+        raise ValueError("unsupported tomography shape (see pwf_fbp_workspace_size)")
+    dev = psis[0].device
+    ws = torch.empty(size, dtype=torch.uint8, device=dev)
+    vol = torch.empty((ny, n_out, n_out), dtype=torch.complex64, device=dev) if out is None else out
+    ang = (ctypes.c_double * n)(*[float(a) for a in angles_rad])
+    check(lib.pwf_fbp(_ptrs(psis, torch.complex64, [(ny, nx)] * n), n, nx, ny, ang, n_out, float(scale),
+                      ctypes.c_void_p(vol.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                      _stream(dev)), "pwf_fbp")
+    return vol

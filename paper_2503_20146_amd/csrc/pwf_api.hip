@@ -71,15 +71,62 @@ struct Context {
   int next_slot = 0;
 };
 
-// Column-tile width per supported side (0: compiled default); set by
-// pwf_set_column_tile or pwf_autotune.
-int g_col_width[5] = {0, 0, 0, 0, 0};
+// Column-tile width per supported side and column sweep op (0: compiled
+// default); set by pwf_set_column_tile or pwf_autotune.
+int g_col_width[5][16] = {};
 
-int col_width(int n) {
+int col_width(int n, int op) {
   const int i = size_index(n);
-  if (i < 0) return 0;
-  return g_col_width[i] ? g_col_width[i] : pwf::col_default_width(n);
+  if (i < 0 || op < 0 || op >= 16) return 0;
+  return g_col_width[i][op] ? g_col_width[i][op] : pwf::col_default_width(n);
 }
+
+// Column op of iteration sweep S1, S3, ..., S11 (-1 for other indices).
+int col_op_of_sweep(int sweep) {
+  switch (sweep) {
+    case 1: return pwf::COL_CHIRP1;
+    case 3: return pwf::COL_CHIRP2;
+    case 5: return pwf::COL_BLUR_LOSS;
+    case 7: return pwf::COL_CHIRP2_CONJ;
+    case 9: return pwf::COL_CHIRP1_CONJ;
+    case 11: return pwf::COL_NESTEROV;
+    default: return -1;
+  }
+}
+
+// Row plan per side and row sweep: -1 = default, 0 = RowCfg, 1 = RowCfgAlt.
+// Set by pwf_set_row_plan or pwf_autotune.
+int g_row_plan[5][16];
+struct RowPlanInit {
+  RowPlanInit() {
+    for (auto& r : g_row_plan)
+      for (int& v : r) v = -1;
+  }
+} g_row_plan_init;
+
+bool row_alt(int n, int op) {
+  const int i = size_index(n);
+  if (i < 0 || !pwf::row_plan_tunable(op) || g_row_plan[i][op] < 0) return pwf::row_alt_default_n(n, op);
+  return g_row_plan[i][op] == 1;
+}
+
+// Row op of iteration sweep S0, S2, ..., S10 (-1 for other indices).
+int row_op_of_sweep(int sweep) {
+  switch (sweep) {
+    case 0: return pwf::ROW_PSI_UPDATE;
+    case 2: return pwf::ROW_MUL_T;
+    case 4: return pwf::ROW_INTENSITY;
+    case 6: return pwf::ROW_BACKBLUR;
+    case 8: return pwf::ROW_MUL_CONJ_T;
+    case 10: return pwf::ROW_GRAD;
+    default: return -1;
+  }
+}
+
+// Bumped by every change of a tuning setting; part of the graph cache key, so
+// that a cached graph never mixes launch shapes with descriptors computed
+// under other settings.
+int g_tune_gen = 0;
 
 std::mutex g_mu;
 Context g_ctx[kMaxDevices];
@@ -190,7 +237,8 @@ pwf_status validate_batch(const pwf_problem* probs, int32_t n) {
 // ------------------------------------------------------------------ workspace layout
 
 size_t field_bytes(const pwf_problem& p) { return align_up((size_t)p.geom.nx * p.geom.ny * sizeof(float2)); }
-int n_partials(const pwf_problem& p) { return p.geom.nx / col_width(p.geom.ny); }
+// loss partials: one per column tile of the residual sweep
+int n_partials(const pwf_problem& p) { return p.geom.nx / col_width(p.geom.ny, pwf::COL_BLUR_LOSS); }
 size_t table_bytes(const pwf_problem& p) {
   return align_up((size_t)(p.geom.nx + p.geom.ny) * (2 * sizeof(float2) + 2 * sizeof(float)));
 }
@@ -198,13 +246,15 @@ size_t table_bytes(const pwf_problem& p) {
 struct Layout {
   size_t status = 0, maxt2 = 0, maxt2_part = 0, desc = 0, partials = 0;
   std::vector<size_t> W, psi_hat, z_hat, v, psi, y_hat, extra0, extra1, part, tables, corr;
+  std::vector<size_t> u1;            // joint diffuser mode only
+  size_t u1max = 0, dsum = 0;        // joint diffuser mode only
   size_t stop = 0;
   size_t total = 0;
 };
 
 // Region order keeps W, psi_hat and z_hat of all instances contiguous so that
 // one fill kernel clears them.
-Layout make_layout(const pwf_problem* probs, int n) {
+Layout make_layout(const pwf_problem* probs, int n, bool joint = false) {
   Layout L;
   size_t off = 0;
   L.status = off;
@@ -219,8 +269,9 @@ Layout make_layout(const pwf_problem* probs, int n) {
   L.partials = off;
   for (int i = 0; i < n; ++i) {
     L.part[i] = off;
-    // room for the narrowest column tile (4 columns) and the plain path's partials
-    off += align_up(sizeof(double) * std::max(probs[i].geom.nx / 4, pwf::plain_elementwise_blocks()));
+    // room for the narrowest compiled column tile and the plain path's partials
+    const int narrow = std::min(pwf::col_default_width(probs[i].geom.ny), pwf::col_alt_width(probs[i].geom.ny));
+    off += align_up(sizeof(double) * std::max(probs[i].geom.nx / narrow, pwf::plain_elementwise_blocks()));
   }
   L.tables.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -252,6 +303,15 @@ Layout make_layout(const pwf_problem* probs, int n) {
   off += field_bytes(probs[0]);
   L.extra1.assign(1, off);
   off += field_bytes(probs[0]);
+  if (joint) {
+    // u1 then conj(u1) a2 per instance (contiguous, one field apart), the S2
+    // workgroup maxima (ny floats per instance) and the normalisation
+    region(L.u1);
+    L.u1max = off;
+    off += align_up(sizeof(float) * (size_t)probs[0].geom.ny * n);
+    L.dsum = off;
+    off += kAlign;
+  }
   L.total = off;
   return L;
 }
@@ -365,15 +425,16 @@ struct Launcher {
   pwf_status row(int op, int iter = 0) const {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
-      S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx, op);
-      PWF_HIP(pwf::launch_row(c.nx, op, S.blocks_per_inst * c.count, S, st));
+      const bool alt = row_alt(c.nx, op);
+      S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx, alt);
+      PWF_HIP(pwf::launch_row(c.nx, op, alt, S.blocks_per_inst * c.count, S, st));
     }
     return PWF_OK;
   }
   pwf_status col(int op, int iter = 0) const {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
-      const int width = col_width(c.ny);
+      const int width = col_width(c.ny, op);
       S.blocks_per_inst = c.nx / width;
       PWF_HIP(pwf::launch_col(c.ny, width, op, S.blocks_per_inst * c.count, S, st));
     }
@@ -387,9 +448,9 @@ struct Launcher {
     if (s_ != PWF_OK) return s_;        \
   } while (0)
 
-pwf_status check_ws(const pwf_problem* probs, int n, void* ws, size_t ws_bytes, Layout* out) {
+pwf_status check_ws(const pwf_problem* probs, int n, void* ws, size_t ws_bytes, Layout* out, bool joint = false) {
   if (!ws || ((uintptr_t)ws % kAlign) != 0) return PWF_ERR_WORKSPACE;
-  *out = make_layout(probs, n);
+  *out = make_layout(probs, n, joint);
   if (ws_bytes < out->total) return PWF_ERR_WORKSPACE;
   return PWF_OK;
 }
@@ -446,12 +507,20 @@ void pwf_set_graph_mode(int32_t on) {
   g_graph_mode = on != 0;
 }
 
-pwf_status pwf_forward(const pwf_problem* problems, int32_t n, const void* const* psi, float* const* f_out,
-                       void* workspace, size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+// PhysicalModel (Eq. 1) for every instance; with y and ref_mean the output is
+// the RMSE image 100 |y - f| / ref_mean instead of f.
+pwf_status forward_impl(const pwf_problem* problems, int32_t n, const void* const* psi, float* const* f_out,
+                        const float* const* y, const double* ref_mean, void* workspace, size_t workspace_bytes,
+                        void* stream) {
   PWF_TRY(validate_batch(problems, n));
   if (!psi || !f_out) return PWF_ERR_ARG;
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     if (!psi[i] || !f_out[i]) return PWF_ERR_ARG;
+    if (y && (!y[i] || !(ref_mean[i] > 0.0) || !std::isfinite(ref_mean[i]))) return PWF_ERR_ARG;
+  }
   Layout L;
   PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
   std::lock_guard<std::mutex> lk(g_mu);
@@ -470,6 +539,10 @@ pwf_status pwf_forward(const pwf_problem* problems, int32_t n, const void* const
     I.psi_src = (const float2*)psi[i];
     I.f_out = f_out[i];
     I.loss_partial = (double*)(ws + L.part[i]);
+    if (y) {
+      I.y = y[i];
+      I.rmse_scale = (float)(100.0 / ref_mean[i]);
+    }
   }
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
   PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
@@ -482,6 +555,21 @@ pwf_status pwf_forward(const pwf_problem* problems, int32_t n, const void* const
   PWF_TRY(K.col(pwf::COL_BLUR));
   PWF_TRY(K.row(pwf::ROW_FORWARD_OUT));
   return PWF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+pwf_status pwf_forward(const pwf_problem* problems, int32_t n, const void* const* psi, float* const* f_out,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  return forward_impl(problems, n, psi, f_out, nullptr, nullptr, workspace, workspace_bytes, stream);
+}
+
+pwf_status pwf_rmse_image(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
+                          const double* ref_mean, float* const* out, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+  if (!y || !ref_mean) return PWF_ERR_ARG;
+  return forward_impl(problems, n, psi, out, y, ref_mean, workspace, workspace_bytes, stream);
 }
 
 pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
@@ -705,9 +793,28 @@ namespace {
 
 // The solve sequence after the descriptor upload: setup, iters x 12 sweeps,
 // final inverse pass into psi_out.
-pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, std::vector<Inst>& desc, int iters) {
-  (void)probs;
-  (void)n;
+// Joint diffuser refinement (Results, "Diffuser transmission function"):
+// after every iteration, t <- t - eta_t sum_j conj(u1_j) a2_j / sum_j max|u1_j|^2
+// over all instances (which share t), then max|t|^2 for the next gradient.
+struct JointCfg {
+  bool on = false;
+  double eta_t = 0.0;
+};
+
+pwf_status joint_step(const Launcher& K, const pwf_problem* probs, int n, const JointCfg& jc) {
+  const pwf_problem& p = probs[0];
+  const size_t m = (size_t)p.geom.nx * p.geom.ny;
+  const int count = p.geom.ny / pwf::row_rows_per_block(p.geom.nx, row_alt(p.geom.nx, pwf::ROW_MUL_T));
+  float2* t = (float2*)p.diffuser;
+  PWF_HIP(pwf::launch_joint_update((const float*)(K.ws + K.L.u1max), n, count, (size_t)p.geom.ny,
+                                   (const float2*)(K.ws + K.L.u1[0]), field_bytes(p) / sizeof(float2), m, t,
+                                   jc.eta_t, (double*)(K.ws + K.L.dsum), K.st));
+  PWF_HIP(pwf::launch_maxabs2(t, m, (float*)(K.ws + K.L.maxt2_part), (float*)(K.ws + K.L.maxt2), K.st));
+  return PWF_OK;
+}
+
+pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, std::vector<Inst>& desc, int iters,
+                          const JointCfg& jc) {
   (void)desc;
   // spectrum of y (uses W as scratch), then clear the status word and W,
   // psi_hat, z_hat of every instance (contiguous regions): psi = z = 0
@@ -728,6 +835,7 @@ pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, st
     PWF_TRY(K.col(pwf::COL_CHIRP1_CONJ, k));
     PWF_TRY(K.row(pwf::ROW_GRAD, k));
     PWF_TRY(K.col(pwf::COL_NESTEROV, k));
+    if (jc.on) PWF_TRY(joint_step(K, probs, n, jc));
   }
   PWF_TRY(K.row(pwf::ROW_IFFT_OUT, iters));
   return PWF_OK;
@@ -737,16 +845,20 @@ pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, st
 
 extern "C" {
 
-pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const* y, void* const* psi_out,
-                     int32_t iters, double corr_tol, double* loss_hist, int32_t* iters_done, void* workspace,
-                     size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+pwf_status solve_impl(const pwf_problem* problems, int32_t n, const float* const* y, void* const* psi_out,
+                      int32_t iters, double corr_tol, double* loss_hist, int32_t* iters_done, void* workspace,
+                      size_t workspace_bytes, void* stream, const JointCfg& jc) {
   PWF_TRY(validate_batch(problems, n));
   if (!y || !psi_out || iters < 0 || iters > kBetaCap || std::isnan(corr_tol) || corr_tol >= 1.0) return PWF_ERR_ARG;
   const bool corr_mode = corr_tol > 0.0;
   for (int i = 0; i < n; ++i)
     if (!y[i] || !psi_out[i]) return PWF_ERR_ARG;
   Layout L;
-  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
+  PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L, jc.on));
   std::lock_guard<std::mutex> lk(g_mu);
   Context* ctx;
   PWF_TRY(context_for_current(&ctx));
@@ -769,9 +881,14 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
     I.out = (float2*)psi_out[i];
     I.loss_partial = (double*)(ws + L.part[i]);
     I.loss_dst = loss_hist ? loss_hist + (size_t)i * iters : nullptr;
+    if (jc.on) {
+      I.u1 = (float2*)(ws + L.u1[i]);
+      I.u1max = (float*)(ws + L.u1max) + (size_t)i * problems[i].geom.ny;
+    }
     if (corr_mode) {
       I.corr_partial = (double*)(ws + L.corr[i]);
-      I.n_corr_partials = problems[i].geom.ny / pwf::row_rows_per_block(problems[i].geom.nx, pwf::ROW_PSI_UPDATE);
+      I.n_corr_partials = problems[i].geom.ny /
+                          pwf::row_rows_per_block(problems[i].geom.nx, row_alt(problems[i].geom.nx, pwf::ROW_PSI_UPDATE));
       I.stop_iter = (int32_t*)(ws + L.stop) + i;
     }
   }
@@ -801,7 +918,7 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
     if (corr_mode) PWF_HIP(pwf::launch_fill_zero(ws + L.stop, align_up(sizeof(int32_t) * n), s));
     std::vector<Inst> tmp = desc;
     PWF_TRY(launch_maxt2(problems, n, B, tmp, ws, L, s));
-    return solve_sequence(K, problems, n, desc, iters);
+    return solve_sequence(K, problems, n, desc, iters, jc);
   };
 
   auto report = [&]() -> pwf_status {
@@ -820,9 +937,11 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
 
   GraphKey key{workspace, n, iters, {}};
   key.dims.push_back(corr_mode ? 1 : 0);
-  {
+  key.dims.push_back(g_tune_gen);
+  key.dims.push_back(jc.on ? 1 : 0);
+  for (double d : {corr_tol, jc.eta_t}) {
     int64_t bits;
-    std::memcpy(&bits, &corr_tol, sizeof(bits));
+    std::memcpy(&bits, &d, sizeof(bits));
     key.dims.push_back((int)(bits & 0x7fffffff));
     key.dims.push_back((int)((bits >> 31) & 0x7fffffff));
     key.dims.push_back((int)(bits >> 62));
@@ -863,6 +982,35 @@ pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const*
   PWF_HIP(hipEventRecord(ctx->ev_out, ctx->side));
   PWF_HIP(hipStreamWaitEvent(st, ctx->ev_out, 0));
   return report();
+}
+
+}  // namespace
+
+extern "C" {
+
+pwf_status pwf_solve(const pwf_problem* problems, int32_t n, const float* const* y, void* const* psi_out,
+                     int32_t iters, double corr_tol, double* loss_hist, int32_t* iters_done, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+  return solve_impl(problems, n, y, psi_out, iters, corr_tol, loss_hist, iters_done, workspace, workspace_bytes,
+                    stream, JointCfg{});
+}
+
+size_t pwf_joint_workspace_size(const pwf_problem* problems, int32_t n) {
+  if (validate_batch(problems, n) != PWF_OK) return 0;
+  return make_layout(problems, n, true).total;
+}
+
+pwf_status pwf_solve_joint(const pwf_problem* problems, int32_t n, const float* const* y, void* const* psi_out,
+                           int32_t iters, double eta_t, double* loss_hist, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!std::isfinite(eta_t) || eta_t < 0.0) return PWF_ERR_ARG;
+  for (int i = 1; i < n; ++i)
+    if (problems[i].diffuser != problems[0].diffuser || problems[i].geom.nx != problems[0].geom.nx ||
+        problems[i].geom.ny != problems[0].geom.ny)
+      return PWF_ERR_ARG;
+  return solve_impl(problems, n, y, psi_out, iters, 0.0, loss_hist, nullptr, workspace, workspace_bytes, stream,
+                    JointCfg{true, eta_t});
 }
 
 pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep, int32_t reps, void* workspace,
@@ -917,18 +1065,45 @@ pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep
   return PWF_OK;
 }
 
-pwf_status pwf_set_column_tile(int32_t n, int32_t width) {
+pwf_status pwf_set_column_tile(int32_t n, int32_t sweep, int32_t width) {
   const int i = size_index(n);
   if (i < 0) return PWF_ERR_SIZE;
   if (width != 0 && !pwf::col_width_supported(n, width)) return PWF_ERR_ARG;
+  const int op = sweep < 0 ? -1 : col_op_of_sweep(sweep);
+  if (sweep >= 0 && op < 0) return PWF_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_col_width[i] = width;
+  if (op < 0) {
+    for (int& w : g_col_width[i]) w = width;
+  } else {
+    g_col_width[i][op] = width;
+  }
+  ++g_tune_gen;
   return PWF_OK;
 }
 
-int32_t pwf_column_tile(int32_t n) {
+int32_t pwf_column_tile(int32_t n, int32_t sweep) {
+  const int op = col_op_of_sweep(sweep);
+  if (op < 0) return 0;
   std::lock_guard<std::mutex> lk(g_mu);
-  return col_width(n);
+  return col_width(n, op);
+}
+
+pwf_status pwf_set_row_plan(int32_t n, int32_t sweep, int32_t plan) {
+  const int i = size_index(n);
+  if (i < 0) return PWF_ERR_SIZE;
+  const int op = row_op_of_sweep(sweep);
+  if (op < 0 || plan < -1 || plan > 1) return PWF_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_row_plan[i][op] = plan;
+  ++g_tune_gen;
+  return PWF_OK;
+}
+
+int32_t pwf_row_plan(int32_t n, int32_t sweep) {
+  const int op = row_op_of_sweep(sweep);
+  if (size_index(n) < 0 || op < 0) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return row_alt(n, op) ? 1 : 0;
 }
 
 pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, void* workspace,
@@ -971,37 +1146,54 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
     one.order = B.order;
     one.classes = {c};
     const Launcher K{*ctx, ws, L, one, st};
-    const int idx = size_index(c.ny);
-    const int cands[2] = {pwf::col_default_width(c.ny), pwf::col_alt_width(c.ny)};
-    float best_ms = 0.f;
-    int best_w = cands[0];
-    for (int w : cands) {
-      if (c.nx % w) continue;
-      g_col_width[idx] = w;
-      auto run = [&]() -> pwf_status {
-        PWF_TRY(K.col(pwf::COL_CHIRP1));
-        PWF_TRY(K.col(pwf::COL_NESTEROV));
-        return PWF_OK;
-      };
-      result = run();  // warm-up
-      if (result != PWF_OK) break;
-      if (hipEventRecord(e0, st) != hipSuccess) { result = PWF_ERR_HIP; break; }
-      for (int r = 0; r < reps && result == PWF_OK; ++r) result = run();
-      if (result != PWF_OK) break;
-      float ms = 0.f;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        result = PWF_ERR_HIP;
-        break;
-      }
-      if (best_ms == 0.f || ms < best_ms) {
-        best_ms = ms;
-        best_w = w;
+    const int cidx = size_index(c.ny), ridx = size_index(c.nx);
+    // time `reps` launches of one sweep (after a warm-up launch)
+    auto timed = [&](auto launch, float* ms) -> pwf_status {
+      PWF_TRY(launch());
+      PWF_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < reps; ++r) PWF_TRY(launch());
+      PWF_HIP(hipEventRecord(e1, st));
+      PWF_HIP(hipEventSynchronize(e1));
+      PWF_HIP(hipEventElapsedTime(ms, e0, e1));
+      return PWF_OK;
+    };
+    // every sweep of the iteration, one at a time: tile width of the column
+    // sweeps, radix plan of the row sweeps
+    for (int sweep = 0; sweep < 12 && result == PWF_OK; ++sweep) {
+      float best = 0.f, ms = 0.f;
+      if (sweep & 1) {
+        const int op = col_op_of_sweep(sweep);
+        const int cands[2] = {pwf::col_default_width(c.ny), pwf::col_alt_width(c.ny)};
+        int best_w = col_width(c.ny, op);
+        for (int w : cands) {
+          if (c.nx % w) continue;
+          g_col_width[cidx][op] = w;
+          result = timed([&]() { return K.col(op); }, &ms);
+          if (result != PWF_OK) break;
+          if (best == 0.f || ms < best) {
+            best = ms;
+            best_w = w;
+          }
+        }
+        g_col_width[cidx][op] = best_w;
+      } else {
+        const int op = row_op_of_sweep(sweep);
+        int best_plan = row_alt(c.nx, op) ? 1 : 0;
+        for (int plan = 0; plan <= 1; ++plan) {
+          g_row_plan[ridx][op] = plan;
+          result = timed([&]() { return K.row(op); }, &ms);
+          if (result != PWF_OK) break;
+          if (best == 0.f || ms < best) {
+            best = ms;
+            best_plan = plan;
+          }
+        }
+        g_row_plan[ridx][op] = best_plan;
       }
     }
-    g_col_width[idx] = best_w;
     if (result != PWF_OK) break;
   }
+  ++g_tune_gen;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   return result;
@@ -1079,6 +1271,192 @@ pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi
     PWF_TRY(ew(pwf::PLAIN_DIRECTION, G, Bf, Cc, A, k));               // d
     PWF_TRY(ew(pwf::PLAIN_NESTEROV, psi, A, Z, psi, k));              // z, tau, psi
   }
+  return PWF_OK;
+}
+
+// ------------------------------------------------------------ calibration front end
+
+size_t pwf_speckle_workspace_size(void) {
+  const int nv = 1 + 2 * (pwf::kMaxShift + 1);
+  return align_up(sizeof(double) * ((size_t)pwf::speckle_sum_blocks() + 1) * nv);
+}
+
+pwf_status pwf_speckle_g2(const float* ref, int32_t nx, int32_t ny, int32_t max_shift, double* g2x, double* g2y,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+  if (!ref || !g2x || !g2y || nx < 1 || ny < 1 || max_shift < 0 || max_shift > pwf::kMaxShift ||
+      max_shift >= nx || max_shift >= ny)
+    return PWF_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < pwf_speckle_workspace_size())
+    return PWF_ERR_WORKSPACE;
+  const int K = pwf::kMaxShift + 1, nv = 1 + 2 * K;
+  double* partial = (double*)workspace;
+  double* out = partial + (size_t)pwf::speckle_sum_blocks() * nv;
+  hipStream_t st = (hipStream_t)stream;
+  PWF_HIP(pwf::launch_speckle_sums(ref, nx, ny, max_shift, partial, out, st));
+  std::vector<double> h(nv);
+  PWF_HIP(hipMemcpyAsync(h.data(), out, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
+  PWF_HIP(hipStreamSynchronize(st));
+  // g2(d) = <I(r) I(r + d)> / <I>^2 (Methods, Eq. 3)
+  const double m = (double)nx * ny;
+  const double mean = h[0] / m;
+  if (!(mean > 0.0)) return PWF_ERR_ARG;
+  for (int d = 0; d <= max_shift; ++d) {
+    g2x[d] = h[1 + d] / m / (mean * mean);
+    g2y[d] = h[1 + K + d] / m / (mean * mean);
+  }
+  return PWF_OK;
+}
+
+pwf_status pwf_fit_coherence(const double* g2, int32_t count, double pixel_m, double* coh_m, double* contrast) {
+  if (!g2 || !coh_m || count < 3 || !(pixel_m > 0.0)) return PWF_ERR_ARG;
+  // ln(g2 - 1) = ln c - pi (d p)^2 / coh^2 over d = 1..K; K: the last shift
+  // before g2 - 1 first drops below 2% of g2(1) - 1
+  const double floor = 0.02 * (g2[1] - 1.0);
+  if (!(g2[1] - 1.0 > 0.0)) return PWF_ERR_ARG;
+  int k = 1;
+  while (k + 1 < count && g2[k + 1] - 1.0 >= floor) ++k;
+  if (k < 2) return PWF_ERR_ARG;
+  double sx = 0, sy = 0, sxx = 0, sxy = 0;
+  for (int d = 1; d <= k; ++d) {
+    const double xv = (d * pixel_m) * (d * pixel_m), yv = std::log(g2[d] - 1.0);
+    sx += xv;
+    sy += yv;
+    sxx += xv * xv;
+    sxy += xv * yv;
+  }
+  const double nk = k, den = nk * sxx - sx * sx;
+  const double slope = (nk * sxy - sx * sy) / den, icpt = (sy - slope * sx) / nk;
+  if (!(slope < 0.0)) return PWF_ERR_ARG;
+  *coh_m = std::sqrt(-M_PI / slope);
+  if (contrast) *contrast = std::exp(icpt);
+  return PWF_OK;
+}
+
+pwf_status pwf_diffuser_from_reference(const pwf_problem* problem, const float* ref, double eps, void* t_out,
+                                       void* workspace, size_t workspace_bytes, void* stream) {
+  PWF_TRY(validate_batch(problem, 1));
+  if (!ref || !t_out || !std::isfinite(eps) || eps < 0.0) return PWF_ERR_ARG;
+  Layout L;
+  PWF_TRY(check_ws(problem, 1, workspace, workspace_bytes, &L));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const pwf_problem& p = *problem;
+  const int nx = p.geom.nx, ny = p.geom.ny;
+  const size_t m = (size_t)nx * ny;
+  Inst I = base_inst(p);
+  I.y = ref;
+  I.wiener_eps = (float)eps;
+  Inst* dI = (Inst*)(ws + L.desc);
+  PWF_TRY(upload(*ctx, &I, sizeof(Inst), dI, st));
+  float2* X = (float2*)(ws + L.W[0]);
+  float2* t = (float2*)t_out;
+  double* part = (double*)(ws + L.part[0]);
+  const float2* twx = ctx->tw[size_index(nx)];
+  const float2* twy = ctx->twc[size_index(ny)];
+  auto filter = [&](const float2* src, float2* dst, int window) -> pwf_status {
+    PWF_HIP(pwf::launch_plain_rows(nx, -1, src, dst, ny, twx, st));
+    PWF_HIP(pwf::launch_plain_cols(ny, -1, dst, nx, twy, st));
+    PWF_HIP(pwf::launch_plain_window(dst, dI, window, m, st));
+    PWF_HIP(pwf::launch_plain_cols(ny, 1, dst, nx, twy, st));
+    PWF_HIP(pwf::launch_plain_rows(nx, 1, dst, dst, ny, twx, st));
+    return PWF_OK;
+  };
+  auto ew = [&](int op, const float2* a, float2* out) -> pwf_status {
+    PWF_HIP(pwf::launch_plain_elementwise(op, m, a, nullptr, nullptr, out, dI, ctx->beta, 0, part, st));
+    return PWF_OK;
+  };
+  // Results, "Diffuser transmission function": Wiener deconvolution by the
+  // IOTF, zero-phase square root, back-propagation over L2
+  PWF_TRY(ew(pwf::PLAIN_FROM_REAL, nullptr, X));
+  PWF_TRY(filter(X, X, pwf::PLAIN_W_WIENER));
+  PWF_TRY(ew(pwf::PLAIN_SQRT_POS, X, X));
+  PWF_TRY(filter(X, t, pwf::PLAIN_W_Q2C));
+  return PWF_OK;
+}
+
+// ------------------------------------------------------------ tomography
+
+namespace {
+constexpr int kMaxFbpAngles = 4096;
+
+int fbp_pad_length(int nx) {
+  int p = 64;
+  while (p < 2 * nx) p <<= 1;
+  return p;
+}
+
+struct FbpLayout {
+  size_t q = 0, ramp = 0, cs = 0, ptrs = 0, total = 0;
+};
+
+bool fbp_layout(int n_proj, int nx, int ny, FbpLayout* L) {
+  if (n_proj < 1 || n_proj > kMaxFbpAngles || nx < 64 || ny < 32 || ny % 32) return false;
+  const int n_pad = fbp_pad_length(nx);
+  if (size_index(n_pad) < 0) return false;
+  size_t off = 0;
+  L->q = off;
+  off += align_up(sizeof(float2) * (size_t)n_proj * ny * n_pad);
+  L->ramp = off;
+  off += align_up(sizeof(float) * n_pad);
+  L->cs = off;
+  off += align_up(sizeof(float2) * n_proj);
+  L->ptrs = off;
+  off += align_up(sizeof(void*) * n_proj);
+  L->total = off;
+  return true;
+}
+}  // namespace
+
+size_t pwf_fbp_workspace_size(int32_t n_proj, int32_t nx, int32_t ny) {
+  FbpLayout L;
+  return fbp_layout(n_proj, nx, ny, &L) ? L.total : 0;
+}
+
+pwf_status pwf_fbp(const void* const* psi, int32_t n_proj, int32_t nx, int32_t ny, const double* angles_rad,
+                   int32_t n_out, double scale, void* vol_out, void* workspace, size_t workspace_bytes,
+                   void* stream) {
+  FbpLayout L;
+  if (!fbp_layout(n_proj, nx, ny, &L)) return PWF_ERR_SIZE;
+  if (!psi || !angles_rad || !vol_out || n_out < 16 || n_out % 16 || !std::isfinite(scale)) return PWF_ERR_ARG;
+  for (int j = 0; j < n_proj; ++j)
+    if (!psi[j] || !std::isfinite(angles_rad[j])) return PWF_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total) return PWF_ERR_WORKSPACE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const int n_pad = fbp_pad_length(nx);
+  // ramp response: DFT of the band-limited ramp h(0) = 1/4, h(odd n) =
+  // -1/(pi^2 n^2) on the circular grid of n_pad samples, over n_pad for the
+  // unnormalised inverse transform
+  std::vector<float> H(n_pad);
+  for (int k = 0; k < n_pad; ++k) {
+    double acc = 0.25;
+    for (int n = 1; n <= n_pad / 2; n += 2) {
+      const double hn = -1.0 / (M_PI * M_PI * (double)n * n);
+      const double w = (n == n_pad / 2 ? 1.0 : 2.0) * std::cos(2.0 * M_PI * (double)k * n / n_pad);
+      acc += hn * w;
+    }
+    H[k] = (float)(acc / n_pad);
+  }
+  std::vector<float2> cs(n_proj);
+  for (int j = 0; j < n_proj; ++j) cs[j] = make_float2((float)std::cos(angles_rad[j]), (float)std::sin(angles_rad[j]));
+  PWF_TRY(upload(*ctx, H.data(), sizeof(float) * n_pad, ws + L.ramp, st));
+  PWF_TRY(upload(*ctx, cs.data(), sizeof(float2) * n_proj, ws + L.cs, st));
+  PWF_TRY(upload(*ctx, psi, sizeof(void*) * n_proj, ws + L.ptrs, st));
+  float2* q = (float2*)(ws + L.q);
+  const size_t rows = (size_t)n_proj * ny;
+  const float2* tw = ctx->tw[size_index(n_pad)];
+  PWF_HIP(pwf::launch_fbp_pad((const float2* const*)(ws + L.ptrs), n_proj, nx, ny, n_pad, q, st));
+  PWF_HIP(pwf::launch_plain_rows(n_pad, -1, q, q, (int)rows, tw, st));
+  PWF_HIP(pwf::launch_fbp_ramp(q, (const float*)(ws + L.ramp), n_pad, rows, st));
+  PWF_HIP(pwf::launch_plain_rows(n_pad, 1, q, q, (int)rows, tw, st));
+  PWF_HIP(pwf::launch_fbp_backproject(q, n_proj, nx, ny, n_pad, (const float2*)(ws + L.cs), n_out,
+                                      (float)(scale * M_PI / n_proj), (float2*)vol_out, st));
   return PWF_OK;
 }
 

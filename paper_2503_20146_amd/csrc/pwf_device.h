@@ -20,6 +20,9 @@ struct Inst {
   int32_t n_partials;   // number of loss partials (column tiles)
   float2* W;            // work field between sweeps
   float2* v;            // detector field v, saved by the forward for the gradient
+  float2* u1;           // joint diffuser mode: field incident on the diffuser (S2), then
+                        // conj(u1) a2 (S8); null otherwise
+  float* u1max;         // joint diffuser mode: per-workgroup max |u1|^2 of S2
   float2* x;            // sample transmission x = exp(psi), saved for the gradient
   const float2* psi_src;// real-space psi that a forward pass starts from
   float2* psi;          // real-space psi written by a state initialisation
@@ -58,6 +61,8 @@ struct Inst {
   float eta;
   float inv_m;             // 1/(nx ny)
   double inv_m_d;
+  float wiener_eps;     // calibration: Wiener regulariser of the IOTF deconvolution
+  float rmse_scale;     // > 0: the forward output is the RMSE image |y - f| rmse_scale
 };
 
 // Loads and stores through the global address space, element i of a field

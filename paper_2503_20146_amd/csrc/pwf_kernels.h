@@ -24,10 +24,16 @@ enum RowOp {
   ROW_IFFT_OUT,        // out = IFFT_x(W)
 };
 
-// Row sweeps that run with the alternative plan of their side (RowCfgAlt):
-// the update sweep on every side, the gradient sweep from 1024 up and the
-// intensity sweep at 2048.
-template <int N> constexpr bool row_uses_alt(int op) {
+// Row sweeps of the iteration (S0, S2, S4, S6, S8, S10) are compiled with both
+// plans of their side and the plan is chosen at run time (pwf_set_row_plan,
+// pwf_autotune).  Default: the alternative plan (RowCfgAlt) for the update
+// sweep on every side, the gradient sweep from 1024 up and the intensity sweep
+// at 2048.  Other row sweeps always use RowCfg.
+constexpr bool row_plan_tunable(int op) {
+  return op == ROW_PSI_UPDATE || op == ROW_MUL_T || op == ROW_INTENSITY || op == ROW_BACKBLUR ||
+         op == ROW_MUL_CONJ_T || op == ROW_GRAD;
+}
+template <int N> constexpr bool row_alt_default(int op) {
   return op == ROW_PSI_UPDATE || (N >= 1024 && op == ROW_GRAD) || (N == 2048 && op == ROW_INTENSITY);
 }
 
@@ -44,18 +50,24 @@ enum ColOp {
   COL_SPEC_PSIHAT,     // psi_hat = FFT_y(W); z_hat = 0
 };
 
-enum PlainWindow { PLAIN_W_Q1 = 0, PLAIN_W_Q2, PLAIN_W_Q2C, PLAIN_W_Q1C, PLAIN_W_IOTF, PLAIN_W_PINV, PLAIN_W_GAMMA2 };
+enum PlainWindow {
+  PLAIN_W_Q1 = 0, PLAIN_W_Q2, PLAIN_W_Q2C, PLAIN_W_Q1C, PLAIN_W_IOTF, PLAIN_W_PINV, PLAIN_W_GAMMA2,
+  PLAIN_W_WIENER  // IOTF / (IOTF^2 + wiener_eps)
+};
 
 enum PlainOp {
   PLAIN_EXP = 0, PLAIN_MUL_T, PLAIN_MUL_CONJ_T, PLAIN_ABS2, PLAIN_REAL, PLAIN_NEG_ERR, PLAIN_MUL,
-  PLAIN_GRAD, PLAIN_IMAG, PLAIN_DIRECTION, PLAIN_NESTEROV
+  PLAIN_GRAD, PLAIN_IMAG, PLAIN_DIRECTION, PLAIN_NESTEROV,
+  PLAIN_FROM_REAL,  // out = (y, 0) from the descriptor's real image
+  PLAIN_SQRT_POS    // out = (sqrt(max(Re a, 0)), 0)
 };
 
-int row_rows_per_block(int n, int op);
+bool row_alt_default_n(int n, int op);
+int row_rows_per_block(int n, bool alt);
 int col_default_width(int n);
 int col_alt_width(int n);
 bool col_width_supported(int n, int w);
-hipError_t launch_row(int nx, int op, int nblocks, const Sweep& S, hipStream_t st);
+hipError_t launch_row(int nx, int op, bool alt, int nblocks, const Sweep& S, hipStream_t st);
 hipError_t launch_col(int ny, int width, int op, int nblocks, const Sweep& S, hipStream_t st);
 hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st);
 
@@ -71,6 +83,25 @@ hipError_t launch_plain_loss_final(const double* partial, int np, double* dst, i
                                    hipStream_t st);
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// Filtered back-projection (pwf_tomo.hip)
+hipError_t launch_fbp_pad(const float2* const* psi, int n_proj, int nx, int ny, int n_pad, float2* dst,
+                          hipStream_t st);
+hipError_t launch_fbp_ramp(float2* a, const float* h, int n_pad, size_t rows, hipStream_t st);
+hipError_t launch_fbp_backproject(const float2* q, int n_proj, int nx, int ny, int n_pad, const float2* cs, int n_out,
+                                  float scale, float2* vol, hipStream_t st);
+// Calibration: FP64 partial sums, per workgroup, of sum I, sum I(x,y) I(x+d,y)
+// and sum I(x,y) I(x,y+d) for d = 0..max_shift (circular shifts), then their
+// ordered total -> out[0] = sum I, out[1 + d] = x-shift sum, out[2 + kMaxShift + d]
+// = y-shift sum (entries past max_shift are 0).  max_shift <= kMaxShift.
+constexpr int kMaxShift = 32;
+int speckle_sum_blocks();
+hipError_t launch_speckle_sums(const float* img, int nx, int ny, int max_shift, double* partial, double* out,
+                               hipStream_t st);
+// Joint diffuser step (see joint_update_kernel): normalisation from the S2
+// maxima, then t <- t - eta_t sum_j G_j / sum_j max|u1_j|^2.
+hipError_t launch_joint_update(const float* u1max, int n, int count, size_t max_stride, const float2* g,
+                               size_t field_stride, size_t m, float2* t, double eta_t, double* dsum,
+                               hipStream_t st);
 int maxabs2_blocks();
 hipError_t launch_maxabs2(const float2* t, size_t m, float* partial, float* out, hipStream_t st);
 

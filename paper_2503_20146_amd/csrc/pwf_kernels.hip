@@ -2,6 +2,7 @@
 // dispatch of the per-side sweep instantiations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -34,6 +35,11 @@ __global__ void plain_window(float2* __restrict__ a, const Inst* __restrict__ ip
       case PLAIN_W_IOTF: val = cscale(val, iotf_of(I, fx, fy)); break;
       case PLAIN_W_PINV: val = cscale(val, pinv_of(I, fx, fy)); break;
       case PLAIN_W_GAMMA2: val = cscale(val, gamma2_of(I, fx, fy)); break;
+      case PLAIN_W_WIENER: {
+        const float h = iotf_of(I, fx, fy);
+        val = cscale(val, h / (h * h + I.wiener_eps));
+        break;
+      }
       default: break;
     }
     a[i] = cscale(val, I.inv_m);
@@ -68,6 +74,8 @@ __global__ void plain_elementwise(int op, size_t m, const float2* __restrict__ a
                              b[i].x + (I.alpha_c1 - I.alpha_c2) * c[i].y);
         break;
       }
+      case PLAIN_FROM_REAL: out[i] = make_float2(I.y[i], 0.f); break;
+      case PLAIN_SQRT_POS: out[i] = make_float2(sqrtf(fmaxf(a[i].x, 0.f)), 0.f); break;
       case PLAIN_NESTEROV: {  // a = psi (in/out via out), b = d, c = z (updated in place)
         const float bf = (float)beta[iter];
         const float2 zp = c[i];
@@ -177,13 +185,13 @@ hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st) {
 // ------------------------------------------------------------------ host dispatch
 
 #define PWF_DECLARE_SIDE(N)                                                                              \
-  template <int M> hipError_t launch_row_n(int op, int nblocks, const Sweep& S, hipStream_t st);        \
+  template <int M> hipError_t launch_row_n(int op, bool alt, int nblocks, const Sweep& S, hipStream_t st); \
   template <int M> hipError_t launch_col_n(int w, int op, int nblocks, const Sweep& S, hipStream_t st); \
   template <int M> hipError_t plain_rows_n(int dir, const float2* src, float2* dst, int ny,             \
                                            const float2* tw, hipStream_t st);                          \
   template <int M> hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, hipStream_t st); \
   template <int M> int plan_twiddles_n(int which, float2* out);                                       \
-  extern template hipError_t launch_row_n<N>(int, int, const Sweep&, hipStream_t);                     \
+  extern template hipError_t launch_row_n<N>(int, bool, int, const Sweep&, hipStream_t);               \
   extern template hipError_t launch_col_n<N>(int, int, int, const Sweep&, hipStream_t);                \
   extern template hipError_t plain_rows_n<N>(int, const float2*, float2*, int, const float2*, hipStream_t); \
   extern template hipError_t plain_cols_n<N>(int, float2*, int, const float2*, hipStream_t);           \
@@ -195,13 +203,24 @@ PWF_DECLARE_SIDE(1024)
 PWF_DECLARE_SIDE(2048)
 #undef PWF_DECLARE_SIDE
 
-int row_rows_per_block(int n, int op) {
+bool row_alt_default_n(int n, int op) {
   switch (n) {
-    case 128: return row_uses_alt<128>(op) ? RowCfgAlt<128>::RW : RowCfg<128>::RW;
-    case 256: return row_uses_alt<256>(op) ? RowCfgAlt<256>::RW : RowCfg<256>::RW;
-    case 512: return row_uses_alt<512>(op) ? RowCfgAlt<512>::RW : RowCfg<512>::RW;
-    case 1024: return row_uses_alt<1024>(op) ? RowCfgAlt<1024>::RW : RowCfg<1024>::RW;
-    case 2048: return row_uses_alt<2048>(op) ? RowCfgAlt<2048>::RW : RowCfg<2048>::RW;
+    case 128: return row_alt_default<128>(op);
+    case 256: return row_alt_default<256>(op);
+    case 512: return row_alt_default<512>(op);
+    case 1024: return row_alt_default<1024>(op);
+    case 2048: return row_alt_default<2048>(op);
+    default: return false;
+  }
+}
+
+int row_rows_per_block(int n, bool alt) {
+  switch (n) {
+    case 128: return alt ? RowCfgAlt<128>::RW : RowCfg<128>::RW;
+    case 256: return alt ? RowCfgAlt<256>::RW : RowCfg<256>::RW;
+    case 512: return alt ? RowCfgAlt<512>::RW : RowCfg<512>::RW;
+    case 1024: return alt ? RowCfgAlt<1024>::RW : RowCfg<1024>::RW;
+    case 2048: return alt ? RowCfgAlt<2048>::RW : RowCfg<2048>::RW;
     default: return 0;
   }
 }
@@ -239,13 +258,13 @@ int col_alt_width(int n) {
   }
 }
 
-hipError_t launch_row(int nx, int op, int nblocks, const Sweep& S, hipStream_t st) {
+hipError_t launch_row(int nx, int op, bool alt, int nblocks, const Sweep& S, hipStream_t st) {
   switch (nx) {
-    case 128: return launch_row_n<128>(op, nblocks, S, st);
-    case 256: return launch_row_n<256>(op, nblocks, S, st);
-    case 512: return launch_row_n<512>(op, nblocks, S, st);
-    case 1024: return launch_row_n<1024>(op, nblocks, S, st);
-    case 2048: return launch_row_n<2048>(op, nblocks, S, st);
+    case 128: return launch_row_n<128>(op, alt, nblocks, S, st);
+    case 256: return launch_row_n<256>(op, alt, nblocks, S, st);
+    case 512: return launch_row_n<512>(op, alt, nblocks, S, st);
+    case 1024: return launch_row_n<1024>(op, alt, nblocks, S, st);
+    case 2048: return launch_row_n<2048>(op, alt, nblocks, S, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -316,6 +335,113 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
 }
 
 int maxabs2_blocks() { return 256; }
+
+// Joint diffuser refinement: normalisation sum_j max|u1_j|^2 from the S2
+// workgroup maxima (n instances, `count` maxima each, `stride` floats apart),
+// summed in instance order in FP64.
+__global__ void joint_norm_kernel(const float* __restrict__ u1max, int n, int count, size_t stride,
+                                  double* __restrict__ dsum) {
+  __shared__ float red[4];
+  double acc = 0.0;
+  for (int j = 0; j < n; ++j) {
+    float mx = 0.f;
+    for (int b = threadIdx.x; b < count; b += blockDim.x) mx = fmaxf(mx, u1max[(size_t)j * stride + b]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) acc += (double)fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dsum = acc;
+}
+
+// t <- t - eta_t sum_j G_j / dsum, G_j = conj(u1_j) a2_j of instance j (fields
+// `stride` elements apart); the sum over instances runs in order, in FP64.
+__global__ void joint_update_kernel(const float2* __restrict__ g, int n, size_t stride, size_t m,
+                                    float2* __restrict__ t, double eta_t, const double* __restrict__ dsum) {
+  const double scale = eta_t / *dsum;
+  for (size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < m; r += (size_t)gridDim.x * blockDim.x) {
+    double gx = 0.0, gy = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const float2 a = g[(size_t)j * stride + r];
+      gx += a.x;
+      gy += a.y;
+    }
+    const float2 tv = t[r];
+    t[r] = make_float2((float)((double)tv.x - scale * gx), (float)((double)tv.y - scale * gy));
+  }
+}
+
+hipError_t launch_joint_update(const float* u1max, int n, int count, size_t max_stride, const float2* g,
+                               size_t field_stride, size_t m, float2* t, double eta_t, double* dsum,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(joint_norm_kernel, dim3(1), dim3(256), 0, st, u1max, n, count, max_stride, dsum);
+  const int blocks = (int)std::min<size_t>((m + 255) / 256, 4096);
+  hipLaunchKernelGGL(joint_update_kernel, dim3(blocks), dim3(256), 0, st, g, n, field_stride, m, t, eta_t, dsum);
+  return hipGetLastError();
+}
+
+// Speckle autocorrelation sums (Siegert calibration).  Each thread takes
+// pixels in a grid-stride loop and accumulates, for every shift d, the
+// products with the pixels d to the right and d below (circular), in FP64.
+__global__ void __launch_bounds__(256) speckle_sums_kernel(const float* __restrict__ img, int nx, int ny, int max_shift,
+                                    double* __restrict__ partial) {
+  constexpr int K = kMaxShift + 1;
+  constexpr int NV = 1 + 2 * K;
+  double acc[NV];  // [0]: sum I; [1 + d]: x shift d; [1 + K + d]: y shift d
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  const size_t m = (size_t)nx * ny;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / nx), x = (int)(i - (size_t)y * nx);
+    const float v = img[i];
+    acc[0] += v;
+#pragma unroll
+    for (int d = 0; d < K; ++d) {
+      if (d <= max_shift) {
+        const int xd = x + d < nx ? x + d : x + d - nx;
+        const int yd = y + d < ny ? y + d : y + d - ny;
+        acc[1 + d] += (double)(v * img[(size_t)y * nx + xd]);
+        acc[1 + K + d] += (double)(v * img[(size_t)yd * nx + x]);
+      }
+    }
+  }
+  // block reduction, one value at a time (wave butterflies, then waves in order)
+  __shared__ double red[16];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    double a = acc[j];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+      partial[(size_t)blockIdx.x * NV + j] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void speckle_sums_final(const double* __restrict__ partial, int blocks, int nv, double* __restrict__ out) {
+  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < blocks; ++b) t += partial[(size_t)b * nv + j];
+    out[j] = t;
+  }
+}
+
+int speckle_sum_blocks() { return 512; }
+
+hipError_t launch_speckle_sums(const float* img, int nx, int ny, int max_shift, double* partial, double* out,
+                               hipStream_t st) {
+  if (max_shift < 0 || max_shift > kMaxShift) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(speckle_sums_kernel, dim3(speckle_sum_blocks()), dim3(256), 0, st, img, nx, ny, max_shift,
+                     partial);
+  hipLaunchKernelGGL(speckle_sums_final, dim3(1), dim3(128), 0, st, partial, speckle_sum_blocks(),
+                     1 + 2 * (kMaxShift + 1), out);
+  return hipGetLastError();
+}
 
 hipError_t launch_maxabs2(const float2* t, size_t m, float* partial, float* out, hipStream_t st) {
   hipLaunchKernelGGL(maxabs2_partial, dim3(maxabs2_blocks()), dim3(256), 0, st, t, m, partial);

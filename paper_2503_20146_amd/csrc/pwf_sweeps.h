@@ -62,14 +62,14 @@ template <int NX, int OP> constexpr int row_min_waves() {
   return OP == ROW_PSI_UPDATE ? 3 : OP == ROW_GRAD ? (NX >= 2048 ? 2 : 3) : 4;
 }
 
-template <int NX, int OP>
-using RowCfgOf = typename std::conditional<row_uses_alt<NX>(OP), RowCfgAlt<NX>, RowCfg<NX>>::type;
+template <int NX, bool ALT>
+using RowCfgSel = typename std::conditional<ALT, RowCfgAlt<NX>, RowCfg<NX>>::type;
 
-template <int NX, int OP> constexpr int row_threads() { return RowCfgOf<NX, OP>::T * RowCfgOf<NX, OP>::RW; }
+template <int NX, bool ALT> constexpr int row_threads() { return RowCfgSel<NX, ALT>::T * RowCfgSel<NX, ALT>::RW; }
 
-template <int NX, int OP>
-__global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP>())) row_sweep(Sweep S) {
-  using C = RowCfgOf<NX, OP>;
+template <int NX, int OP, bool ALT>
+__global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, OP>())) row_sweep(Sweep S) {
+  using C = RowCfgSel<NX, ALT>;
   using Plan = typename C::Plan;
   constexpr int T = C::T, RW = C::RW, E = NX / T;
   constexpr int R1 = Plan::radix[0], RL = Plan::radix[Plan::NPASS - 1];
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
   const LdsView lv{lds + rw * lds_len(NX), 1};
   using TS = TwSel<Plan>;
   __shared__ float2 twl[TS::kLds];
-  const float2* twg = row_uses_alt<NX>(OP) ? S.tw_alt : S.tw_row;
+  const float2* twg = ALT ? S.tw_alt : S.tw_row;
   const auto tw = TS::forward(twl, twg);
   const auto twr = TS::inverse(twl, twg);
   const uint32_t rbase = (uint32_t)row * NX;
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
   auto load_twiddles = [&]() {
     if constexpr (TS::kMode != 0) {
       const float2* src = TS::staged_from(twg, S.twn_row);
-      for (int i = threadIdx.x; i < TS::kLds; i += row_threads<NX, OP>()) twl[i] = gld(src, i);
+      for (int i = threadIdx.x; i < TS::kLds; i += row_threads<NX, ALT>()) twl[i] = gld(src, i);
     }
   };
 
@@ -147,6 +147,7 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
 
   // real-space step; element e = c*R1 + q sits at x = t + T c + q M1
   float inv_maxt2 = 0.f;
+  float u1max = 0.f;  // joint diffuser mode (S2): max |u1|^2 over this lane's elements
   if constexpr (OP == ROW_GRAD) inv_maxt2 = I.grad_mul > 0.f ? I.grad_mul : 1.0f / *I.maxt2;
   // stopping correlation of exp(psi) with the previous iterate (FP64 sums)
   const bool corr = (OP == ROW_PSI_UPDATE) && I.corr_partial != nullptr;
@@ -173,8 +174,16 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
         v[e] = cexp_f(v[e]);
         if (I.x) gst(I.x, idx, v[e]);
       } else if constexpr (OP == ROW_MUL_T) {
+        if (I.u1) {  // joint diffuser mode: keep u1 for the diffuser gradient of S8
+          gst(I.u1, idx, v[e]);
+          u1max = fmaxf(u1max, v[e].x * v[e].x + v[e].y * v[e].y);
+        }
         v[e] = cmul(v[e], side[e]);
       } else if constexpr (OP == ROW_MUL_CONJ_T) {
+        if (I.u1) {  // joint diffuser mode: dL/dt* = conj(u1) a2, a2 = this back-propagated field
+          const float2 u = gld(I.u1, idx);
+          gst(I.u1, idx, cmulc(v[e], u));
+        }
         v[e] = cmulc(v[e], side[e]);
       } else if constexpr (OP == ROW_INTENSITY) {
         if (I.v) gst(I.v, idx, v[e]);
@@ -187,7 +196,8 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
         v[e] = cscale(cmulc(v[e], xs), inv_maxt2);
         if (I.g_out) gst(I.g_out, idx, v[e]);
       } else if constexpr (OP == ROW_FORWARD_OUT) {
-        gstf(I.f_out, idx, v[e].x);
+        const float f = v[e].x;   // RMSE image (Methods): |y - f| scaled by 100 / <reference>
+        gstf(I.f_out, idx, I.rmse_scale > 0.f ? fabsf(gldf(I.y, idx) - f) * I.rmse_scale : f);
       } else if constexpr (OP == ROW_CPLX_FFT) {
         if (I.psi) gst(I.psi, idx, v[e]);
       } else if constexpr (OP == ROW_IFFT_OUT) {
@@ -204,6 +214,20 @@ __global__ void __launch_bounds__((row_threads<NX, OP>()), (row_min_waves<NX, OP
         gst(I.W, rbase + col_of_kx(t + T * c + r * ML, NX), v[c * RL + r]);
       });
     });
+  }
+
+  if constexpr (OP == ROW_MUL_T) {
+    if (I.u1) {  // block max of |u1|^2 -> u1max[blk] (order-free, so deterministic)
+      __shared__ float mred[RW * T / 64 + 1];
+      for (int off = 32; off > 0; off >>= 1) u1max = fmaxf(u1max, __shfl_xor(u1max, off, 64));
+      if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = u1max;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float m = mred[0];
+        for (int i = 1; i < RW * T / 64; ++i) m = fmaxf(m, mred[i]);
+        gstf(I.u1max, blk, m);
+      }
+    }
   }
 
   if constexpr (OP == ROW_PSI_UPDATE) {
@@ -552,21 +576,28 @@ plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw) {
   }
 }
 
+template <int N, int OP, bool ALT>
+hipError_t launch_row_one(int nblocks, const Sweep& S, hipStream_t st) {
+  hipLaunchKernelGGL((row_sweep<N, OP, ALT>), dim3(nblocks), dim3(row_threads<N, ALT>()), 0, st, S);
+  return hipGetLastError();
+}
+
+// Row sweep `op` with the alternative plan when `alt` (tunable sweeps only;
+// the others always run with their default plan).
 template <int N>
-hipError_t launch_row_n(int op, int nblocks, const Sweep& S, hipStream_t st) {
-  const dim3 grid(nblocks);
+hipError_t launch_row_n(int op, bool alt, int nblocks, const Sweep& S, hipStream_t st) {
   switch (op) {
-#define PWF_CASE(o)                                                                        \
-  case o:                                                                                  \
-    hipLaunchKernelGGL((row_sweep<N, o>), grid, dim3(row_threads<N, o>()), 0, st, S);     \
-    break;
-    PWF_CASE(ROW_PSI_UPDATE) PWF_CASE(ROW_START) PWF_CASE(ROW_MUL_T) PWF_CASE(ROW_MUL_CONJ_T)
-    PWF_CASE(ROW_INTENSITY) PWF_CASE(ROW_BACKBLUR) PWF_CASE(ROW_GRAD) PWF_CASE(ROW_FORWARD_OUT)
-    PWF_CASE(ROW_REAL_FFT) PWF_CASE(ROW_CPLX_FFT) PWF_CASE(ROW_IFFT_OUT)
-#undef PWF_CASE
+#define PWF_TUNABLE(o) \
+  case o: return alt ? launch_row_one<N, o, true>(nblocks, S, st) : launch_row_one<N, o, false>(nblocks, S, st);
+#define PWF_FIXED(o) case o: return launch_row_one<N, o, row_alt_default<N>(o)>(nblocks, S, st);
+    PWF_TUNABLE(ROW_PSI_UPDATE) PWF_TUNABLE(ROW_MUL_T) PWF_TUNABLE(ROW_MUL_CONJ_T) PWF_TUNABLE(ROW_INTENSITY)
+    PWF_TUNABLE(ROW_BACKBLUR) PWF_TUNABLE(ROW_GRAD)
+    PWF_FIXED(ROW_START) PWF_FIXED(ROW_FORWARD_OUT) PWF_FIXED(ROW_REAL_FFT) PWF_FIXED(ROW_CPLX_FFT)
+    PWF_FIXED(ROW_IFFT_OUT)
+#undef PWF_TUNABLE
+#undef PWF_FIXED
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <int N, int W>

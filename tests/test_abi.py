@@ -22,7 +22,7 @@ def lib():
 def header_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pwf_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(pwf_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_entry_points():
@@ -50,6 +50,39 @@ def test_status_strings(lib):
     assert lib.pwf_status_string(42).decode() == "unknown status"
     assert lib.pwf_version() >= 10000
     assert _lib.status_string(-3).startswith("geometry has evanescent")
+
+
+def test_tuning_settings(lib):
+    """Tile widths and row plans: defaults, settable values, errors (host-only calls)."""
+    assert lib.pwf_column_tile(1024, 1) == 8 and lib.pwf_column_tile(2048, 11) == 4
+    assert lib.pwf_column_tile(100, 1) == 0 and lib.pwf_column_tile(1024, 2) == 0
+    assert lib.pwf_set_column_tile(1024, -1, 3) == -1
+    assert lib.pwf_set_column_tile(1024, 4, 4) == -1     # S4 is a row sweep
+    assert lib.pwf_set_column_tile(100, -1, 4) == -2
+    try:
+        assert lib.pwf_set_column_tile(1024, 11, 4) == 0
+        assert lib.pwf_column_tile(1024, 11) == 4 and lib.pwf_column_tile(1024, 1) == 8
+        assert lib.pwf_set_column_tile(1024, -1, 4) == 0
+        assert all(lib.pwf_column_tile(1024, s) == 4 for s in range(1, 12, 2))
+    finally:
+        lib.pwf_set_column_tile(1024, -1, 0)
+    assert lib.pwf_column_tile(1024, 11) == 8
+    # built-in plans at 1024: the update and gradient sweeps on the alternative plan
+    assert [lib.pwf_row_plan(1024, s) for s in range(0, 12, 2)] == [1, 0, 0, 0, 0, 1]
+    assert [lib.pwf_row_plan(2048, s) for s in range(0, 12, 2)] == [1, 0, 1, 0, 0, 1]
+    assert lib.pwf_row_plan(1024, 1) == -1 and lib.pwf_row_plan(100, 0) == -1
+    assert lib.pwf_set_row_plan(1024, 3, 0) == -1      # S3 is a column sweep
+    assert lib.pwf_set_row_plan(1024, 2, 2) == -1
+    assert lib.pwf_set_row_plan(96, 2, 1) == -2
+    try:
+        assert lib.pwf_set_row_plan(1024, 2, 1) == 0
+        assert lib.pwf_row_plan(1024, 2) == 1
+        assert lib.pwf_set_row_plan(1024, 0, 0) == 0
+        assert lib.pwf_row_plan(1024, 0) == 0
+    finally:
+        lib.pwf_set_row_plan(1024, 2, -1)
+        lib.pwf_set_row_plan(1024, 0, -1)
+    assert lib.pwf_row_plan(1024, 2) == 0 and lib.pwf_row_plan(1024, 0) == 1
 
 
 def _problem(nx=128, ny=128, **kw):
@@ -122,3 +155,59 @@ def test_product_code_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "synthetic" not in text, f
+
+
+def test_fit_coherence_host(lib):
+    """pwf_fit_coherence is host arithmetic: exact on a model curve, errors on degenerate input."""
+    import math
+    d = [float(i) for i in range(40)]
+    g2 = [1.0 + 0.37 * math.exp(-math.pi * (x * 0.65e-6) ** 2 / (4.1e-6) ** 2) for x in d]
+    g2[0] += 0.8
+    arr = (ctypes.c_double * 40)(*g2)
+    coh, c = ctypes.c_double(), ctypes.c_double()
+    assert lib.pwf_fit_coherence(arr, 40, 0.65e-6, ctypes.byref(coh), ctypes.byref(c)) == 0
+    assert abs(coh.value / 4.1e-6 - 1) < 1e-12 and abs(c.value - 0.37) < 1e-12
+    flat = (ctypes.c_double * 5)(*([1.0] * 5))
+    assert lib.pwf_fit_coherence(flat, 5, 1e-6, ctypes.byref(coh), None) == -1
+    assert lib.pwf_fit_coherence(arr, 2, 1e-6, ctypes.byref(coh), None) == -1
+    assert lib.pwf_fit_coherence(arr, 40, 0.0, ctypes.byref(coh), None) == -1
+
+
+def test_calibration_and_joint_argument_errors(lib):
+    from paper_2503_20146_amd import _lib
+    g = (ctypes.c_double * 40)()
+    ws = ctypes.c_void_p(0x100000)
+    big = lib.pwf_speckle_workspace_size()
+    assert big > 0
+    img = ctypes.c_void_p(0x2000)
+    assert lib.pwf_speckle_g2(img, 128, 128, 33, g, g, ws, big, None) == -1     # shift above 32
+    assert lib.pwf_speckle_g2(img, 16, 16, 16, g, g, ws, big, None) == -1      # shift >= side
+    assert lib.pwf_speckle_g2(img, 128, 128, 8, g, g, ws, big - 1, None) == -4
+    assert lib.pwf_speckle_g2(None, 128, 128, 8, g, g, ws, big, None) == -1
+    arr = (_lib.pwf_problem * 1)(_problem())
+    size = lib.pwf_workspace_size(arr, 1)
+    assert lib.pwf_diffuser_from_reference(arr, img, -1.0, img, ws, size, None) == -1
+    assert lib.pwf_diffuser_from_reference(arr, img, 1e-3, None, ws, size, None) == -1
+    two = (_lib.pwf_problem * 2)(_problem(diffuser=0x1000), _problem(diffuser=0x3000))
+    ptrs = (ctypes.c_void_p * 2)(0x2000, 0x2000)
+    jsize = lib.pwf_joint_workspace_size(two, 2)
+    assert jsize > lib.pwf_workspace_size(two, 2)
+    assert lib.pwf_solve_joint(two, 2, ptrs, ptrs, 5, 0.5, None, ws, jsize, None) == -1   # distinct diffusers
+    one = (_lib.pwf_problem * 1)(_problem())
+    assert lib.pwf_solve_joint(one, 1, ptrs, ptrs, 5, float("nan"), None, ws, 1 << 40, None) == -1
+    assert lib.pwf_solve_joint(one, 1, ptrs, ptrs, 5, 0.5, None, ws, lib.pwf_workspace_size(one, 1), None) == -4
+
+
+def test_fbp_argument_errors(lib):
+    assert lib.pwf_fbp_workspace_size(180, 1024, 1024) > 180 * 1024 * 2048 * 8
+    assert lib.pwf_fbp_workspace_size(0, 1024, 1024) == 0
+    assert lib.pwf_fbp_workspace_size(180, 2048, 1024) == 0      # padded rows beyond 2048
+    assert lib.pwf_fbp_workspace_size(180, 1024, 1000) == 0      # ny not a multiple of 32
+    ang = (ctypes.c_double * 2)(0.0, 1.0)
+    ptrs = (ctypes.c_void_p * 2)(0x2000, 0x3000)
+    size = lib.pwf_fbp_workspace_size(2, 128, 64)
+    ws = ctypes.c_void_p(0x100000)
+    assert lib.pwf_fbp(ptrs, 2, 128, 64, ang, 120, 1.0, ctypes.c_void_p(0x4000), ws, size, None) == -1   # n_out % 16
+    assert lib.pwf_fbp(ptrs, 2, 128, 64, ang, 128, 1.0, None, ws, size, None) == -1
+    assert lib.pwf_fbp(ptrs, 2, 128, 64, ang, 128, 1.0, ctypes.c_void_p(0x4000), ws, size - 1, None) == -4
+    assert lib.pwf_fbp(ptrs, 2, 100, 60, ang, 128, 1.0, ctypes.c_void_p(0x4000), ws, size, None) == -2

@@ -167,6 +167,41 @@ def test_solve_parity_workload1_100_iterations():
     assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
+@pytest.mark.parametrize("plan", [0, 1])
+def test_row_plans_match_oracle(plan):
+    """Every tunable row sweep forced onto one radix plan (32x32 or 16x16x4 at
+    1024; the autotuner may pick either per sweep): forward, gradient and 30
+    iterations against the oracle, and the graph vs eager solve agree."""
+    from paper_2503_20146_amd import set_graph_mode, set_row_plan
+    dev = device()
+    inp, geo, prob, y = instance(1)
+    say(f"row plan {plan} at 1024^2")
+    for s in range(0, 12, 2):
+        set_row_plan(1024, s, plan)
+    try:
+        batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+        psi0 = (0.5 * inp["psi_true"]).astype(np.complex64)
+        f = batch.forward([to_dev(psi0, dev)])[0].cpu().numpy()
+        f_ref, _, _ = O.physical_model(psi0.astype(np.complex128), prob)
+        assert rel(f, f_ref) <= FWD_TOL
+        yd = to_dev(y, dev)
+        out, hist = batch.solve([yd], 30)
+        set_graph_mode(False)
+        try:
+            out_e, _ = batch.solve([yd], 30)
+        finally:
+            set_graph_mode(True)
+    finally:
+        for s in range(0, 12, 2):
+            set_row_plan(1024, s, -1)
+    import torch
+    assert torch.equal(out[0], out_e[0])
+    psi = out[0].cpu().numpy()
+    psi_ref, hist_ref, _ = O.pwf(y, prob, 30)
+    assert np.sqrt(np.mean(np.abs(psi - psi_ref) ** 2)) <= PHASE_TOL
+    assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
+
+
 def test_plain_path_parity():
     dev = device()
     inp, geo, prob, y = instance(0)
