@@ -159,6 +159,69 @@ def build_workload(n_proj: int, dev):
     return batch, ys, geo, probs, d
 
 
+# Algorithmic FP32 flops of one voxel-angle step of the back-projection: the
+# detector coordinate (mul, fma, add), the interpolation weight (sub) and, per
+# real/imaginary part, the difference, the interpolating fma and the sum.
+FBP_FLOPS_PER_VOXEL_ANGLE = 13
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
+    """Joint diffuser refinement, calibration front end and tomography on the same workload."""
+    import math
+
+    import torch
+
+    from paper_2503_20146_amd import PWF, calibrate_source, diffuser_from_reference, fbp, problem_from_geometry
+
+    res = {}
+    n = len(probs)
+    # joint diffuser refinement: the same 100-iteration solve, t stepped every iteration
+    t_joint = probs[0].diffuser.clone()
+    jb = PWF([problem_from_geometry(geo, t_joint) for _ in range(n)])
+    jb.solve_joint(ys, 2, loss_hist=False)
+    torch.cuda.synchronize()
+    iters = 100
+    t_joint.copy_(probs[0].diffuser)
+    sec = time_events(lambda: jb.solve_joint(ys, iters, loss_hist=False))
+    res["joint_diffuser"] = {"value": round(n * iters / sec, 1), "unit": "proj-iter/s",
+                             "config": f"{n} projections x 1024^2, {iters} iterations, diffuser step every iteration"}
+    del jb, t_joint
+    torch.cuda.empty_cache()
+    print(f"[bench] joint {res['joint_diffuser']['value']} proj-iter/s", file=sys.stderr, flush=True)
+    # calibration on the reference speckle of the workload's diffuser (GPU forward at psi = 0)
+    zero = torch.zeros((geo.ny, geo.nx), dtype=torch.complex64, device=dev)
+    ref = PWF([probs[0]]).forward([zero])[0]
+    calibrate_source(ref, geo.pixel_m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cal = calibrate_source(ref, geo.pixel_m)
+    t_cal = time.perf_counter() - t0
+    sec_t = time_events(lambda: diffuser_from_reference(probs[0], ref, 1e-3))
+    res["calibration"] = {"coherence_ms": round(t_cal * 1e3, 3), "diffuser_ms": round(sec_t * 1e3, 3),
+                          "sigma_px_fitted": [round(cal["sigma_x_px"], 3), round(cal["sigma_y_px"], 3)],
+                          "config": "one 1024^2 reference speckle, shifts 0..32"}
+    print(f"[bench] calibration {res['calibration']}", file=sys.stderr, flush=True)
+    # tomography of the retrieved projections
+    angles = [math.pi * j / n for j in range(n)]
+    scale = geo.wavelength_m / (2.0 * math.pi * geo.pixel_m)
+    vol = fbp(out, angles, geo.nx, scale)
+    torch.cuda.synchronize()
+    sec_f = time_events(lambda: fbp(out, angles, geo.nx, scale, out=vol))
+    va = float(geo.ny) * geo.nx * geo.nx * n
+    achieved = va * FBP_FLOPS_PER_VOXEL_ANGLE / sec_f / 1e12
+    res["tomography"] = {"ms": round(sec_f * 1e3, 2), "voxel_angles_per_s": round(va / sec_f, 1),
+                         "roofline": {"bound": "alu", "achieved": round(achieved, 2),
+                                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                      "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                                      "flops_per_voxel_angle": FBP_FLOPS_PER_VOXEL_ANGLE},
+                         "config": f"FBP of {n} retrieved 1024^2 projections -> {geo.ny} x {geo.nx}^2 volume"}
+    del vol
+    torch.cuda.empty_cache()
+    print(f"[bench] tomography {res['tomography']}", file=sys.stderr, flush=True)
+    return res
+
+
 def time_events(fn, reps_note=None):
     import torch
     s = torch.cuda.current_stream()
@@ -205,6 +268,8 @@ def main() -> int:
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the joint-diffuser, calibration and tomography measurements")
     ap.add_argument("--sweep-only", default=None,
                     help="after setup, only launch sweep K (0..11) or 'all' plus a 1 GiB copy (counter runs)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -220,14 +285,14 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
-              "projections are independent, see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); the "
+              "projections are independent problems that shard across GPUs with no exchange", file=sys.stderr)
         return 2
 
     import torch
     dev = torch.device("cuda:0")
     print(f"[bench] building workload: {args.projections} x 1024^2", file=sys.stderr, flush=True)
-    batch, ys, geo, probs, _ = build_workload(args.projections, dev)
+    batch, ys, geo, probs, d_inputs = build_workload(args.projections, dev)
     pixels = args.projections * geo.nx * geo.ny
 
     tiles = {}
@@ -235,7 +300,7 @@ def main() -> int:
         from paper_2503_20146_amd import _lib
         _lib.check(_lib.load().pwf_set_column_tile(1024, -1, args.col_tile), "pwf_set_column_tile")
         tiles = {1024: [args.col_tile] * 6}
-    elif not args.no_autotune:
+    elif not args.no_autotune and args.sweep_only is None:
         tiles = autotune(batch)
         print(f"[bench] column tiles {tiles}", file=sys.stderr, flush=True)
     from paper_2503_20146_amd import _lib as _l
@@ -252,9 +317,12 @@ def main() -> int:
             dst.copy_(src)
             torch.cuda.synchronize()
             del src, dst
-        for sw in sweeps:
-            batch.bench_sweep(sw, args.sweep_reps)
-        torch.cuda.synchronize()
+        # every compiled column-tile width in turn unless one is fixed
+        for w in ([args.col_tile] if args.col_tile else [8, 4]):
+            _l.load().pwf_set_column_tile(1024, -1, w)
+            for sw in sweeps:
+                batch.bench_sweep(sw, args.sweep_reps)
+            torch.cuda.synchronize()
         print(f"[bench] sweeps {list(sweeps)} x {args.sweep_reps} done", file=sys.stderr, flush=True)
         return 0
 
@@ -308,6 +376,8 @@ def main() -> int:
                          "no batching, no graph", "speedup_of_batched": round(value / pv, 2)}
         print(f"[bench] plain {pv:.1f} proj-iter/s", file=sys.stderr, flush=True)
 
+    extras = None if args.no_extras else secondary_measurements(batch, ys, out, probs, geo, d_inputs, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_iters)
@@ -324,7 +394,7 @@ def main() -> int:
                    "projections": args.projections, "grid": [geo.ny, geo.nx], "iterations_per_step": args.iters,
                    "column_tiles_S1_S3_S5_S7_S9_S11": tiles, "row_plans_S0_S2_S4_S6_S8_S10": row_plans,
                    "parallelism": "single GPU"},
-        "roofline": roofline, "cpu_baseline": cpu, "plain_baseline": plain,
+        "roofline": roofline, "cpu_baseline": cpu, "plain_baseline": plain, "extras": extras,
     }
     print(json.dumps(rec), flush=True)
     return 0
