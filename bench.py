@@ -172,7 +172,10 @@ def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
 
     import torch
 
-    from paper_2503_20146_amd import PWF, calibrate_source, diffuser_from_reference, fbp, problem_from_geometry
+    import numpy as np
+
+    from paper_2503_20146_amd import (PWF, calibrate_source, diffuser_from_reference, fbp, problem_from_geometry,
+                                      shell_correlation)
 
     res = {}
     n = len(probs)
@@ -216,9 +219,26 @@ def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
                                       "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                                       "flops_per_voxel_angle": FBP_FLOPS_PER_VOXEL_ANGLE},
                          "config": f"FBP of {n} retrieved 1024^2 projections -> {geo.ny} x {geo.nx}^2 volume"}
+    print(f"[bench] tomography {res['tomography']}", file=sys.stderr, flush=True)
+    # Fourier shell correlation of the delta tomogram with that of the true projections
+    if geo.ny == geo.nx:
+        true_psis = [torch.from_numpy(p.astype(np.complex64)).to(dev) for p in d["psi_true"]]
+        vol_true = fbp(true_psis, angles, geo.nx, scale)
+        del true_psis
+        shell_correlation(vol, vol_true, part=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fsc = shell_correlation(vol, vol_true, part=1)
+        t_fsc = time.perf_counter() - t0
+        kappa = next((k for k in range(1, len(fsc)) if fsc[k] < 0.5), len(fsc) - 1)
+        res["fsc_vs_truth"] = {"ms": round(t_fsc * 1e3, 2),
+                               "resolution_um_at_half": round(geo.nx * geo.pixel_m / kappa * 1e6, 3),
+                               "fsc_at_shells_64_128_256_512": [round(fsc[k], 4) for k in (64, 128, 256, 512)],
+                               "config": f"delta tomograms {geo.nx}^3 from retrieved vs true projections"}
+        print(f"[bench] fsc {res['fsc_vs_truth']}", file=sys.stderr, flush=True)
+        del vol_true
     del vol
     torch.cuda.empty_cache()
-    print(f"[bench] tomography {res['tomography']}", file=sys.stderr, flush=True)
     return res
 
 

@@ -325,6 +325,22 @@ pwf_status pwf_fbp(const void* const* psi, int32_t n_proj, int32_t nx, int32_t n
                    int32_t n_out, double scale, void* vol_out, void* workspace, size_t workspace_bytes,
                    void* stream);
 
+/* Workspace bytes for pwf_shell_correlation; 0 when unsupported (n = 128,
+ * 256, 512, 1024 or 2048; dims 2 or 3). */
+size_t pwf_shell_correlation_workspace_size(int32_t n, int32_t dims);
+
+/* Fourier shell (dims = 3) or ring (dims = 2) correlation of Eq. 16 between
+ * the real (part = 0) or imaginary (part = 1) parts of two device complex64
+ * arrays g1, g2 of n^dims elements (e.g. two pwf_fbp volumes of n slices):
+ *   fsc[kappa] = Re sum G1* G2 / sqrt(sum |G1|^2 sum |G2|^2) over the shell
+ *   kappa = round(|k|) of signed index frequencies, kappa = 0 .. n/2.
+ * The resolution criterion of the paper is fsc = 1/4 (Eqs. 17-18).  Shell
+ * sums in FP64 (LDS atomics within a workgroup: not bit-reproducible across
+ * runs, agreement ~1e-12).  fsc_out: HOST float64 [n/2 + 1]; the call
+ * synchronises on `stream`. */
+pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int32_t dims, int32_t part,
+                                 double* fsc_out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Release the library's twiddle tables and cached graphs. */
 void pwf_finalize(void);
 

@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     set_column_tile,
     set_graph_mode,
     set_row_plan,
+    shell_correlation,
 )
 from ._lib import PwfError, load  # noqa: F401
 from .autograd import PWFLoss, pwf_loss  # noqa: F401

@@ -325,3 +325,25 @@ def fbp(psis: Sequence[torch.Tensor], angles_rad: Sequence[float], n_out: int | 
                       ctypes.c_void_p(vol.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                       _stream(dev)), "pwf_fbp")
     return vol
+
+
+def shell_correlation(g1: torch.Tensor, g2: torch.Tensor, part: int = 1):
+    """Fourier shell (3-D) or ring (2-D) correlation of Eq. 16 (pwf_shell_correlation):
+    a list over shells 0..n/2 of the real (part 0) or imaginary (part 1) parts' FSC."""
+    if g1.shape != g2.shape or g1.dtype != torch.complex64 or g2.dtype != torch.complex64:
+        raise ValueError("two complex64 arrays of one shape")
+    if not (g1.is_cuda and g2.is_cuda and g1.is_contiguous() and g2.is_contiguous()):
+        raise ValueError("contiguous GPU arrays")
+    n, dims = g1.shape[0], g1.dim()
+    if any(s != n for s in g1.shape):
+        raise ValueError("a square image or a cubic volume")
+    lib = _lib.load()
+    size = lib.pwf_shell_correlation_workspace_size(n, dims)
+    if size == 0:
+        raise ValueError("unsupported size for the shell correlation")
+    ws = torch.empty(size, dtype=torch.uint8, device=g1.device)
+    out = (ctypes.c_double * (n // 2 + 1))()
+    check(lib.pwf_shell_correlation(ctypes.c_void_p(g1.data_ptr()), ctypes.c_void_p(g2.data_ptr()), n, dims, part,
+                                    out, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(g1.device)),
+          "pwf_shell_correlation")
+    return list(out)

@@ -1460,6 +1460,66 @@ pwf_status pwf_fbp(const void* const* psi, int32_t n_proj, int32_t nx, int32_t n
   return PWF_OK;
 }
 
+// ------------------------------------------------------------ shell correlation
+
+namespace {
+bool fsc_layout(int n, int dims, size_t* g2_off, size_t* part_off, size_t* out_off, size_t* total) {
+  if ((dims != 2 && dims != 3) || size_index(n) < 0) return false;
+  const size_t m = dims == 3 ? (size_t)n * n * n : (size_t)n * n;
+  const size_t nsh = (size_t)n / 2 + 1;
+  size_t off = align_up(sizeof(float2) * m);
+  *g2_off = off;
+  off += align_up(sizeof(float2) * m);
+  *part_off = off;
+  off += align_up(sizeof(double) * 3 * nsh * pwf::fsc_blocks());
+  *out_off = off;
+  off += align_up(sizeof(double) * 3 * nsh);
+  *total = off;
+  return true;
+}
+}  // namespace
+
+size_t pwf_shell_correlation_workspace_size(int32_t n, int32_t dims) {
+  size_t a, b, c, total;
+  return fsc_layout(n, dims, &a, &b, &c, &total) ? total : 0;
+}
+
+pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int32_t dims, int32_t part,
+                                 double* fsc_out, void* workspace, size_t workspace_bytes, void* stream) {
+  size_t g2_off, part_off, out_off, total;
+  if (!fsc_layout(n, dims, &g2_off, &part_off, &out_off, &total)) return PWF_ERR_SIZE;
+  if (!g1 || !g2 || !fsc_out || (part != 0 && part != 1)) return PWF_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < total) return PWF_ERR_WORKSPACE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const size_t m = dims == 3 ? (size_t)n * n * n : (size_t)n * n;
+  float2* A = (float2*)ws;
+  float2* B = (float2*)(ws + g2_off);
+  const float2* twr = ctx->tw[size_index(n)];
+  const float2* twc = ctx->twc[size_index(n)];
+  // the n^dims DFT as 1-D transforms along x, y (per z plane) and z
+  for (int v = 0; v < 2; ++v) {
+    float2* X = v == 0 ? A : B;
+    PWF_HIP(pwf::launch_fsc_part((const float2*)(v == 0 ? g1 : g2), part, X, m, st));
+    PWF_HIP(pwf::launch_plain_rows(n, -1, X, X, (int)(m / n), twr, st));
+    const int planes = dims == 3 ? n : 1;
+    for (int z = 0; z < planes; ++z) PWF_HIP(pwf::launch_plain_cols(n, -1, X + (size_t)z * n * n, n, twc, st));
+    if (dims == 3) PWF_HIP(pwf::launch_plain_cols(n, -1, X, n * n, twc, st));
+  }
+  double* out = (double*)(ws + out_off);
+  PWF_HIP(pwf::launch_fsc_shells(A, B, n, dims, (double*)(ws + part_off), out, st));
+  const int nsh = n / 2 + 1;
+  std::vector<double> h(3 * (size_t)nsh);
+  PWF_HIP(hipMemcpyAsync(h.data(), out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  PWF_HIP(hipStreamSynchronize(st));
+  // Eq. 16: shell cross-correlation over the geometric mean of the shell powers
+  for (int s = 0; s < nsh; ++s) fsc_out[s] = h[s] / std::sqrt(h[nsh + s] * h[2 * nsh + s]);
+  return PWF_OK;
+}
+
 pwf_status pwf_sync_status(void* workspace, void* stream) {
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return PWF_ERR_WORKSPACE;
   PWF_HIP(hipStreamSynchronize((hipStream_t)stream));

@@ -26,15 +26,17 @@ enum RowOp {
 
 // Row sweeps of the iteration (S0, S2, S4, S6, S8, S10) are compiled with both
 // plans of their side and the plan is chosen at run time (pwf_set_row_plan,
-// pwf_autotune).  Default: the alternative plan (RowCfgAlt) for the update
-// sweep on every side, the gradient sweep from 1024 up and the intensity sweep
-// at 2048.  Other row sweeps always use RowCfg.
+// pwf_autotune).  Default (what the autotuner picks on the 180 x 1024^2
+// workload): the alternative plan (RowCfgAlt) for every tunable sweep at 1024,
+// for the update, intensity and gradient sweeps at 2048, for the update sweep
+// elsewhere.  Other row sweeps always use RowCfg.
 constexpr bool row_plan_tunable(int op) {
   return op == ROW_PSI_UPDATE || op == ROW_MUL_T || op == ROW_INTENSITY || op == ROW_BACKBLUR ||
          op == ROW_MUL_CONJ_T || op == ROW_GRAD;
 }
 template <int N> constexpr bool row_alt_default(int op) {
-  return op == ROW_PSI_UPDATE || (N >= 1024 && op == ROW_GRAD) || (N == 2048 && op == ROW_INTENSITY);
+  return op == ROW_PSI_UPDATE || (N == 1024 && row_plan_tunable(op)) ||
+         (N == 2048 && (op == ROW_GRAD || op == ROW_INTENSITY));
 }
 
 enum ColOp {
@@ -89,6 +91,12 @@ hipError_t launch_fbp_pad(const float2* const* psi, int n_proj, int nx, int ny, 
 hipError_t launch_fbp_ramp(float2* a, const float* h, int n_pad, size_t rows, hipStream_t st);
 hipError_t launch_fbp_backproject(const float2* q, int n_proj, int nx, int ny, int n_pad, const float2* cs, int n_out,
                                   float scale, float2* vol, hipStream_t st);
+// Fourier shell correlation (pwf_tomo.hip): out[s], out[nsh + s], out[2 nsh + s]
+// = shell sums of Re(G1* G2), |G1|^2, |G2|^2, nsh = n/2 + 1.
+int fsc_blocks();
+hipError_t launch_fsc_part(const float2* src, int part, float2* dst, size_t m, hipStream_t st);
+hipError_t launch_fsc_shells(const float2* g1, const float2* g2, int n, int dims, double* partial, double* out,
+                             hipStream_t st);
 // Calibration: FP64 partial sums, per workgroup, of sum I, sum I(x,y) I(x+d,y)
 // and sum I(x,y) I(x,y+d) for d = 0..max_shift (circular shifts), then their
 // ordered total -> out[0] = sum I, out[1 + d] = x-shift sum, out[2 + kMaxShift + d]

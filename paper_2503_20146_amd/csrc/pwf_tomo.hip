@@ -89,3 +89,68 @@ hipError_t launch_fbp_backproject(const float2* q, int n_proj, int nx, int ny, i
 }
 
 }  // namespace pwf
+
+namespace pwf {
+
+// Fourier shell correlation (Methods, Eq. 16): the chosen part (0 real, 1
+// imaginary) of a complex volume, as a complex field for the transforms.
+__global__ void fsc_part_kernel(const float2* __restrict__ src, int part, float2* __restrict__ dst, size_t m) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = make_float2(part ? src[i].y : src[i].x, 0.f);
+}
+
+// Shell sums of Re(G1* G2), |G1|^2, |G2|^2 over kappa = round(|k|) (signed
+// index frequencies of an n^dims grid), kappa <= n/2.  Each workgroup sums its
+// grid-stride share into LDS (FP64 atomics: summation order within a
+// workgroup is not fixed) and writes one row of partials.
+__global__ void __launch_bounds__(256) fsc_shell_kernel(const float2* __restrict__ g1, const float2* __restrict__ g2,
+                                                        int n, int dims, double* __restrict__ partial) {
+  extern __shared__ double sh[];
+  const int nsh = n / 2 + 1;
+  for (int i = threadIdx.x; i < 3 * nsh; i += blockDim.x) sh[i] = 0.0;
+  __syncthreads();
+  const size_t m = dims == 3 ? (size_t)n * n * n : (size_t)n * n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    const int kx = (int)(i % n);
+    const int ky = (int)((i / n) % n);
+    const int kz = dims == 3 ? (int)(i / ((size_t)n * n)) : 0;
+    const float fx = (float)(kx < n / 2 ? kx : kx - n);
+    const float fy = (float)(ky < n / 2 ? ky : ky - n);
+    const float fz = (float)(kz < n / 2 ? kz : kz - n);
+    const int s = (int)rintf(sqrtf(fx * fx + fy * fy + fz * fz));
+    if (s >= nsh) continue;
+    const float2 a = g1[i], b = g2[i];
+    atomicAdd(&sh[s], (double)a.x * b.x + (double)a.y * b.y);
+    atomicAdd(&sh[nsh + s], (double)a.x * a.x + (double)a.y * a.y);
+    atomicAdd(&sh[2 * nsh + s], (double)b.x * b.x + (double)b.y * b.y);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * nsh; i += blockDim.x) partial[(size_t)blockIdx.x * 3 * nsh + i] = sh[i];
+}
+
+__global__ void fsc_final_kernel(const double* __restrict__ partial, int blocks, int len, double* __restrict__ out) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < len; j += gridDim.x * blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < blocks; ++b) t += partial[(size_t)b * len + j];
+    out[j] = t;
+  }
+}
+
+int fsc_blocks() { return 1024; }
+
+hipError_t launch_fsc_part(const float2* src, int part, float2* dst, size_t m, hipStream_t st) {
+  hipLaunchKernelGGL(fsc_part_kernel, dim3(4096), dim3(256), 0, st, src, part, dst, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_fsc_shells(const float2* g1, const float2* g2, int n, int dims, double* partial, double* out,
+                             hipStream_t st) {
+  const int nsh = n / 2 + 1;
+  hipLaunchKernelGGL(fsc_shell_kernel, dim3(fsc_blocks()), dim3(256), sizeof(double) * 3 * nsh, st, g1, g2, n, dims,
+                     partial);
+  hipLaunchKernelGGL(fsc_final_kernel, dim3((3 * nsh + 255) / 256), dim3(256), 0, st, partial, fsc_blocks(),
+                     3 * nsh, out);
+  return hipGetLastError();
+}
+
+}  // namespace pwf

@@ -67,22 +67,22 @@ def test_tuning_settings(lib):
     finally:
         lib.pwf_set_column_tile(1024, -1, 0)
     assert lib.pwf_column_tile(1024, 11) == 8
-    # built-in plans at 1024: the update and gradient sweeps on the alternative plan
-    assert [lib.pwf_row_plan(1024, s) for s in range(0, 12, 2)] == [1, 0, 0, 0, 0, 1]
+    # built-in plans at 1024: every tunable row sweep on the alternative plan
+    assert [lib.pwf_row_plan(1024, s) for s in range(0, 12, 2)] == [1, 1, 1, 1, 1, 1]
     assert [lib.pwf_row_plan(2048, s) for s in range(0, 12, 2)] == [1, 0, 1, 0, 0, 1]
     assert lib.pwf_row_plan(1024, 1) == -1 and lib.pwf_row_plan(100, 0) == -1
     assert lib.pwf_set_row_plan(1024, 3, 0) == -1      # S3 is a column sweep
     assert lib.pwf_set_row_plan(1024, 2, 2) == -1
     assert lib.pwf_set_row_plan(96, 2, 1) == -2
     try:
-        assert lib.pwf_set_row_plan(1024, 2, 1) == 0
-        assert lib.pwf_row_plan(1024, 2) == 1
-        assert lib.pwf_set_row_plan(1024, 0, 0) == 0
-        assert lib.pwf_row_plan(1024, 0) == 0
+        assert lib.pwf_set_row_plan(1024, 2, 0) == 0
+        assert lib.pwf_row_plan(1024, 2) == 0
+        assert lib.pwf_set_row_plan(2048, 2, 1) == 0
+        assert lib.pwf_row_plan(2048, 2) == 1
     finally:
         lib.pwf_set_row_plan(1024, 2, -1)
-        lib.pwf_set_row_plan(1024, 0, -1)
-    assert lib.pwf_row_plan(1024, 2) == 0 and lib.pwf_row_plan(1024, 0) == 1
+        lib.pwf_set_row_plan(2048, 2, -1)
+    assert lib.pwf_row_plan(1024, 2) == 1 and lib.pwf_row_plan(2048, 2) == 0
 
 
 def _problem(nx=128, ny=128, **kw):
@@ -211,3 +211,17 @@ def test_fbp_argument_errors(lib):
     assert lib.pwf_fbp(ptrs, 2, 128, 64, ang, 128, 1.0, None, ws, size, None) == -1
     assert lib.pwf_fbp(ptrs, 2, 128, 64, ang, 128, 1.0, ctypes.c_void_p(0x4000), ws, size - 1, None) == -4
     assert lib.pwf_fbp(ptrs, 2, 100, 60, ang, 128, 1.0, ctypes.c_void_p(0x4000), ws, size, None) == -2
+
+
+def test_shell_correlation_argument_errors(lib):
+    assert lib.pwf_shell_correlation_workspace_size(128, 3) > 2 * 128 ** 3 * 8
+    assert lib.pwf_shell_correlation_workspace_size(100, 3) == 0
+    assert lib.pwf_shell_correlation_workspace_size(128, 4) == 0
+    out = (ctypes.c_double * 65)()
+    size = lib.pwf_shell_correlation_workspace_size(128, 2)
+    ws = ctypes.c_void_p(0x100000)
+    p = ctypes.c_void_p(0x2000)
+    assert lib.pwf_shell_correlation(p, p, 128, 2, 2, out, ws, size, None) == -1
+    assert lib.pwf_shell_correlation(None, p, 128, 2, 0, out, ws, size, None) == -1
+    assert lib.pwf_shell_correlation(p, p, 128, 2, 0, out, ws, size - 1, None) == -4
+    assert lib.pwf_shell_correlation(p, p, 96, 2, 0, out, ws, size, None) == -2

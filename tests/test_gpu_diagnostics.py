@@ -25,3 +25,23 @@ def test_rmse_image_matches_oracle(workload, frac):
     # |d|y - f|| <= |df| pointwise, so ||img - ref|| <= 100 / ref_mean * 1e-5 ||f||
     assert np.linalg.norm(img[0].cpu().numpy() - ref) <= 100.0 / ref_mean * 1e-5 * np.linalg.norm(f)
     assert rel(img[0].cpu().numpy(), ref) <= 1e-5 * np.linalg.norm(f) / np.linalg.norm(y - f)
+
+
+@pytest.mark.parametrize("n,dims", [(128, 3), (256, 2)])
+def test_shell_correlation_matches_oracle(n, dims):
+    """FP32 transforms against FP64: the shell correlations agree to 1e-5."""
+    import torch
+    from paper_2503_20146_amd import shell_correlation
+    dev = device()
+    rng = np.random.default_rng(n + dims)
+    shape = (n,) * dims
+    s = rng.standard_normal(shape)
+    a = (s + 0.7 * rng.standard_normal(shape)) + 1j * rng.standard_normal(shape)
+    b = (s + 0.7 * rng.standard_normal(shape)) + 1j * rng.standard_normal(shape)
+    say(f"shell correlation {n}^{dims}")
+    ta, tb = to_dev(a.astype(np.complex64), dev), to_dev(b.astype(np.complex64), dev)
+    got = np.array(shell_correlation(ta, tb, part=0))
+    ref = O.shell_correlation(a.real.astype(np.float32), b.real.astype(np.float32))
+    assert np.max(np.abs(got - ref)) <= 1e-5
+    same = np.array(shell_correlation(ta, ta, part=1))
+    assert np.max(np.abs(same[1:] - 1.0)) <= 1e-6
