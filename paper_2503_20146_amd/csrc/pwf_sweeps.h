@@ -57,6 +57,39 @@ __device__ __forceinline__ float2 cexp_f(float2 p) {
   return make_float2(a * c, a * s);
 }
 
+// Twiddles staged in LDS.  Every load of the table is issued ahead of the
+// sweep's own loads and held in registers, and the LDS writes come after those
+// loads are issued: the table's latency then hides under the data's instead of
+// costing one dependent round trip per strided chunk of the table.
+// A copy of v that the compiler cannot see through.  Stores at the end of a
+// sweep take their offsets from such a copy: otherwise the compiler reuses the
+// 64-bit addresses of the matching loads and keeps one register pair per
+// element alive across the whole FFT.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+template <int COUNT, int NTHR>
+struct TwStage {
+  static constexpr int K = (COUNT + NTHR - 1) / NTHR;
+  float2 r[K];
+  __device__ __forceinline__ void load(const float2* src) {
+    static_for<0, K>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      const int i = (int)threadIdx.x + j * NTHR;
+      if (COUNT % NTHR == 0 || i < COUNT) r[j] = gld(src, (uint32_t)i);
+    });
+  }
+  __device__ __forceinline__ void store(float2* lds) const {
+    static_for<0, K>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      const int i = (int)threadIdx.x + j * NTHR;
+      if (COUNT % NTHR == 0 || i < COUNT) lds[i] = r[j];
+    });
+  }
+};
+
 // Waves per SIMD the compiler must leave room for (launch bound).
 template <int NX, int OP> constexpr int row_min_waves() {
   return OP == ROW_PSI_UPDATE ? 3 : OP == ROW_GRAD ? (NX >= 2048 ? 2 : 3) : 4;
@@ -92,11 +125,10 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   const uint32_t rbase = (uint32_t)row * NX;
   // Twiddles to LDS; the first pass needs none, and the barrier after its
   // LDS exchange orders these writes before the first use.
+  TwStage<TS::kLds, row_threads<NX, ALT>()> tws;
+  if constexpr (TS::kMode != 0) tws.load(TS::staged_from(twg, S.twn_row));
   auto load_twiddles = [&]() {
-    if constexpr (TS::kMode != 0) {
-      const float2* src = TS::staged_from(twg, S.twn_row);
-      for (int i = threadIdx.x; i < TS::kLds; i += row_threads<NX, ALT>()) twl[i] = gld(src, i);
-    }
+    if constexpr (TS::kMode != 0) tws.store(twl);
   };
 
   // Side input of the real-space step (t, v or x at this row), loaded after
@@ -153,11 +185,12 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   const bool corr = (OP == ROW_PSI_UPDATE) && I.corr_partial != nullptr;
   const bool corr_sum = corr && S.iter > 0;
   double c_re = 0.0, c_im = 0.0, n_new = 0.0, n_old = 0.0;
+  const uint32_t rb_rs = opaque(rbase);
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
       constexpr int e = c * R1 + q;
-      const uint32_t idx = rbase + t + T * c + q * M1;
+      const uint32_t idx = rb_rs + t + T * c + q * M1;
       if constexpr (OP == ROW_PSI_UPDATE) {
         if (corr) gst(I.out, idx, v[e]);  // psi of this iterate, kept in case the stop fires
         const float2 xn = cexp_f(v[e]);
@@ -208,10 +241,11 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
 
   if constexpr (OUT_FREQ) {
     fft_forward<Plan, T>(v, t, tw, lv);
+    const uint32_t rb_st = opaque(rbase);
     static_for<0, E / RL>([&](auto cc) {
       static_for<0, RL>([&](auto rr) {
         constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
-        gst(I.W, rbase + col_of_kx(t + T * c + r * ML, NX), v[c * RL + r]);
+        gst(I.W, rb_st + col_of_kx(t + T * c + r * ML, NX), v[c * RL + r]);
       });
     });
   }
@@ -339,25 +373,25 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, col_min_waves<OP>()) col_sw
   }
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int s = tile * W + w;
+  const uint32_t o_ld = (uint32_t)(t * nx + s);  // element (t, s); row r adds r nx
   const LdsView lv{lds + w, W};
   using TS = TwSel<Plan>;
   __shared__ float2 twl[TS::kLds];
   const auto tw = TS::forward(twl, S.tw_col);
   const auto twr = TS::inverse(twl, S.tw_col);
 
+  TwStage<TS::kLds, NT> tws;
+  if constexpr (TS::kMode != 0) tws.load(TS::staged_from(S.tw_col, S.twn_col));
   float2 v[E];
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-      v[c * R1 + q] = gld(I.W, (uint32_t)((t + T * c + q * M1) * nx + s));
+      v[c * R1 + q] = gld(I.W, o_ld + (uint32_t)((T * c + q * M1) * nx));
     });
   });
   // Twiddles to LDS; the first pass needs none, and the barrier after its
   // LDS exchange orders these writes before the first use.
-  if constexpr (TS::kMode != 0) {
-    const float2* src = TS::staged_from(S.tw_col, S.twn_col);
-    for (int i = threadIdx.x; i < TS::kLds; i += NT) twl[i] = gld(src, i);
-  }
+  if constexpr (TS::kMode != 0) tws.store(twl);
   fft_forward<Plan, T>(v, t, tw, lv);
 
   // Fourier-domain step; element e = c*RL + r holds ky = t + T c + r ML.
@@ -370,6 +404,19 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, col_min_waves<OP>()) col_sw
     // neighbour position mirror_col(s), inside this tile.
     const int wm = mirror_col(s) - tile * W;
     const LdsView lm{lds + wm, W};
+    // Psi(k), z(k) and the 1 - STF factors of this lane's elements, issued
+    // before the exchange of G so that their latency overlaps it (behind the
+    // stores of the update, the compiler could not move them up).
+    float2 pk[E], zp[OP == COL_NESTEROV ? E : 1];
+    float gyv[E];
+    static_for<0, E>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      const int ky = t + T * (e / RL) + (e % RL) * ML;
+      const uint32_t gi = o_ld + (uint32_t)((ky - t) * nx);
+      pk[e] = gld(I.psi_hat, gi);
+      if constexpr (OP == COL_NESTEROV) zp[e] = gld(I.z_hat, gi);
+      gyv[e] = gldf(I.gy, ky);
+    });
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       lv.at(t + T * (e / RL) + (e % RL) * ML) = v[e];
@@ -388,25 +435,25 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, col_min_waves<OP>()) col_sw
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       const int ky = t + T * (e / RL) + (e % RL) * ML;
-      lv.at(ky) = gld(I.psi_hat, (uint32_t)(ky * nx + s));
+      lv.at(ky) = pk[e];
     });
     __syncthreads();
     const float bf = (OP == COL_NESTEROV) ? (float)S.beta[I.k0 + S.iter] : 0.f;
     const float gxv = gldf(I.gx, kx);
+    const uint32_t o_up = opaque(o_ld);
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       const int ky = t + T * (e / RL) + (e % RL) * ML;
-      const float2 pk = lv.at(ky);
       const float2 pm = lm.at((NY - ky) & (NY - 1));
-      const float g2 = gxv + (1.f - gxv) * gldf(I.gy, ky);   // 1 - STFx STFy without cancellation
+      const float g2 = gxv + (1.f - gxv) * gyv[e];   // 1 - STFx STFy without cancellation
       // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
-      const float2 reg = make_float2(I.alpha_c1 * pk.x + I.alpha_c2 * pm.x, I.alpha_c1 * pk.y - I.alpha_c2 * pm.y);
+      const float2 reg = make_float2(I.alpha_c1 * pk[e].x + I.alpha_c2 * pm.x, I.alpha_c1 * pk[e].y - I.alpha_c2 * pm.y);
       const float2 d = make_float2(v[e].x + g2 * reg.x, v[e].y + g2 * reg.y);
       if constexpr (OP == COL_NESTEROV) {
-        const uint32_t gi = (uint32_t)(ky * nx + s);
-        const float2 zp = gld(I.z_hat, gi);
-        const float2 z = make_float2(pk.x - I.eta * d.x, pk.y - I.eta * d.y);
-        const float2 pn = make_float2(z.x + bf * (z.x - zp.x), z.y + bf * (z.y - zp.y));
+        const uint32_t gi = o_up + (uint32_t)((ky - t) * nx);
+        const float2 zo = zp[OP == COL_NESTEROV ? e : 0];
+        const float2 z = make_float2(pk[e].x - I.eta * d.x, pk[e].y - I.eta * d.y);
+        const float2 pn = make_float2(z.x + bf * (z.x - zo.x), z.y + bf * (z.y - zo.y));
         gst(I.z_hat, gi, z);
         gst(I.psi_hat, gi, pn);
         v[e] = cscale(pn, I.inv_m);
@@ -478,10 +525,11 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, col_min_waves<OP>()) col_sw
 
   if constexpr (ColOpTraits<OP>::kInverse) {
     fft_inverse<Plan, T>(v, t, twr, lv);
+    const uint32_t o_st = opaque(o_ld);
     static_for<0, E / R1>([&](auto cc) {
       static_for<0, R1>([&](auto qq) {
         constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-        gst(I.W, (uint32_t)((t + T * c + q * M1) * nx + s), v[c * R1 + q]);
+        gst(I.W, o_st + (uint32_t)((T * c + q * M1) * nx), v[c * R1 + q]);
       });
     });
   }
