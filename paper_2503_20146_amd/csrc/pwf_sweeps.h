@@ -50,11 +50,36 @@ PWF_ROW_TRAIT(ROW_CPLX_FFT, false, true)
 PWF_ROW_TRAIT(ROW_IFFT_OUT, true, false)
 #undef PWF_ROW_TRAIT
 
+// exp(p) for complex p.  The phase is reduced to a quadrant index n and a
+// remainder f in [-pi/4, pi/4] in units of revolutions (r = p.y / 2 pi; r - n/4
+// is exact), and cos f, sin f come from their Taylor series, truncated where
+// the next term is below 2e-9 on that interval.  The only error beyond the
+// polynomials' rounding is that of r itself, |p.y| 2^-24 rad, the same as
+// one rounding of p.y.
 __device__ __forceinline__ float2 cexp_f(float2 p) {
-  float s, c;
-  sincosf(p.y, &s, &c);
+  const float r = p.y * 0.159154943091895336f;
+  const float n = rintf(4.f * r);
+  const float f = fmaf(-0.25f, n, r) * 6.28318530717958648f;
+  const float f2 = f * f;
+  // sin f = f (1 - f^2/3! + f^4/5! - f^6/7! + f^8/9!)
+  float sp = fmaf(f2, 2.75573192e-6f, -1.98412698e-4f);
+  sp = fmaf(f2, sp, 8.33333333e-3f);
+  sp = fmaf(f2, sp, -1.66666667e-1f);
+  const float sn = fmaf(f * f2, sp, f);
+  // cos f = 1 - f^2/2! + f^4/4! - f^6/6! + f^8/8! - f^10/10!
+  float cp = fmaf(f2, -2.75573192e-7f, 2.48015873e-5f);
+  cp = fmaf(f2, cp, -1.38888889e-3f);
+  cp = fmaf(f2, cp, 4.16666667e-2f);
+  cp = fmaf(f2, cp, -0.5f);
+  const float cs = fmaf(f2, cp, 1.f);
+  // rotate by n quarter turns: n = 1 -> (-sin, cos), 2 -> (-cos, -sin), 3 -> (sin, -cos)
+  const int q = (int)n;
+  const bool swap = q & 1;
+  const float c1 = swap ? sn : cs, s1 = swap ? cs : sn;
+  const uint32_t flip_c = (uint32_t)((q + 1) & 2) << 30, flip_s = (uint32_t)(q & 2) << 30;
   const float a = expf(p.x);
-  return make_float2(a * c, a * s);
+  return make_float2(a * __uint_as_float(__float_as_uint(c1) ^ flip_c),
+                     a * __uint_as_float(__float_as_uint(s1) ^ flip_s));
 }
 
 // Twiddles staged in LDS.  Every load of the table is issued ahead of the
