@@ -362,11 +362,16 @@ __device__ __noinline__ float2 transfer_direct(double chirp_rev, double s_coef, 
   return transfer(chirp_rev, s_coef, 0, fx, fy, false);
 }
 
-// Column sweeps keep the 2-wave bound: with 128 registers the FFT spills.
-template <int OP> constexpr int col_min_waves() { return 2; }
+// Waves per SIMD the column sweeps must leave room for: 3 for the update
+// sweeps (168 registers; at 256 points the 16-column tile would spill), 2 for
+// the others, which need fewer registers than that anyway (a 4-wave bound,
+// 128 registers, makes the chirp sweeps spill).
+template <int NY, int W, int OP> constexpr int col_min_waves() {
+  return (OP == COL_NESTEROV || OP == COL_DIRECTION) && !(NY == 256 && W == 16) ? 3 : 2;
+}
 
 template <int NY, int W, int OP>
-__global__ void __launch_bounds__(ColCfg<NY>::T * W, col_min_waves<OP>()) col_sweep(Sweep S) {
+__global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>())) col_sweep(Sweep S) {
   using C = ColCfg<NY>;
   using Plan = typename C::Plan;
   constexpr int T = C::T, E = NY / T;
