@@ -115,6 +115,19 @@ struct TwStage {
   }
 };
 
+// Logical block of hardware block b in a grid of g blocks.  Workgroups are
+// dispatched round-robin over the 8 XCDs: XCD b % 8 gets the contiguous range
+// [(b % 8) g/8, (b % 8 + 1) g/8), walked forwards, or backwards with REV.
+// Row sweeps walk forwards and column sweeps backwards, so that each sweep
+// starts on the data its predecessor wrote last, which the memory-side cache
+// may still hold.  (Plain reversal when 8 does not divide g.)
+template <bool REV>
+__device__ __forceinline__ int xcd_contiguous(int b, int g) {
+  if (g & 7) return REV ? g - 1 - b : b;
+  const int per = g >> 3, j = b >> 3;
+  return (b & 7) * per + (REV ? per - 1 - j : j);
+}
+
 // Waves per SIMD the compiler must leave room for (launch bound).
 template <int NX, int OP> constexpr int row_min_waves() {
   return OP == ROW_PSI_UPDATE ? 3 : OP == ROW_GRAD ? (NX >= 2048 ? 2 : 3) : 4;
@@ -135,8 +148,9 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   constexpr bool IN_FREQ = RowOpTraits<OP>::kInFreq, OUT_FREQ = RowOpTraits<OP>::kOutFreq;
   __shared__ float2 lds[RW * lds_len(NX)];
 
-  const int inst = blockIdx.x / S.blocks_per_inst;
-  const int blk = blockIdx.x - inst * S.blocks_per_inst;
+  const int b = xcd_contiguous<false>(blockIdx.x, gridDim.x);
+  const int inst = b / S.blocks_per_inst;
+  const int blk = b - inst * S.blocks_per_inst;
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
   if (instance_stopped(I)) return;  // uniform over the workgroup
   const int t = threadIdx.x % T, rw = threadIdx.x / T;
@@ -322,13 +336,6 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
 
 // ------------------------------------------------------------------ column sweeps
 
-// Logical block of hardware block b in a grid of g blocks: XCD b % 8 gets the
-// contiguous range [(b % 8) g/8, (b % 8 + 1) g/8).  Identity when 8 does not divide g.
-__device__ __forceinline__ int xcd_contiguous(int b, int g) {
-  if (g & 7) return b;
-  return (b & 7) * (g >> 3) + (b >> 3);
-}
-
 template <int OP> struct ColOpTraits;
 #define PWF_COL_TRAIT(op, inv) \
   template <> struct ColOpTraits<op> { static constexpr bool kInverse = inv; };
@@ -384,7 +391,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous range of tiles so that tiles sharing 128-byte lines meet in
   // the same L2.
-  const int b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int b = xcd_contiguous<true>(blockIdx.x, gridDim.x);
   const int inst = b / S.blocks_per_inst;
   const int tile = b - inst * S.blocks_per_inst;
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
