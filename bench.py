@@ -38,10 +38,15 @@ SWEEP_NAMES = ["S0 row psi-update", "S1 col Q_L1", "S2 row x t", "S3 col Q_L2", 
 ITER_BYTES_PER_PX = sum(SWEEP_BYTES_PER_PX)   # 280
 
 
+# sources that define the 1024^2 sweep kernels: counters taken before a change to any
+# of them no longer describe the kernels that run
+SWEEP_SOURCES = ["pwf_device.h", "pwf_fft.h", "pwf_kernels.h", "pwf_sweeps.h", "pwf_sweeps_1024.hip"]
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2503_20146_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in SWEEP_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
