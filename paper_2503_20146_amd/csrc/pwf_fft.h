@@ -252,12 +252,22 @@ struct TwPass {
 
 // TwTable: one table of w_N^m (m = 0..N-1) for every pass of both
 // directions: w_{LR}^{qk} = w_N^{qk N/(LR)}, and qk N/(LR) < N.
-template <int N>
+// HALF keeps only m < N/2 and uses w_N^(m + N/2) = -w_N^m (a sign flip of both
+// parts), which halves the staged table at the cost of a few integer ops per
+// twiddle.
+template <int N, bool HALF = false>
 struct TwTable {
   const float2* tab;
   template <class Plan, int P, int q>
   __device__ __forceinline__ float2 get(int k) const {
-    return tab[q * (N / (Plan::stride_before(P) * Plan::radix[P])) * k];
+    const int i = q * (N / (Plan::stride_before(P) * Plan::radix[P])) * k;
+    if constexpr (!HALF) {
+      return tab[i];
+    } else {
+      const float2 w = tab[i & (N / 2 - 1)];
+      const uint32_t sg = (uint32_t)(i & (N / 2)) << (31 - ilog2(N / 2));
+      return make_float2(__uint_as_float(__float_as_uint(w.x) ^ sg), __uint_as_float(__float_as_uint(w.y) ^ sg));
+    }
   }
 };
 
@@ -387,12 +397,13 @@ struct TwLayout {
 // them).  Mode 2: the single table w_N^m staged in LDS (N entries, fewer than
 // the per-pass tables of both directions).  Mode 0: per-pass tables in global
 // memory, where no staged table fits beside the exchange buffer (N > 1024).
-template <class Plan>
+// HALF: stage the half table in mode 2 (see TwTable).
+template <class Plan, bool HALF = false>
 struct TwSel {
   static constexpr int N = Plan::kN;
   static constexpr int kMode = N > 1024 ? 0 : (TwLayout<Plan>::kSelfReverse ? 1 : 2);
-  static constexpr int kLds = kMode == 1 ? TwLayout<Plan>::kUsed : kMode == 2 ? N : 1;
-  using View = typename std::conditional<kMode == 2, TwTable<N>, TwPass>::type;
+  static constexpr int kLds = kMode == 1 ? TwLayout<Plan>::kUsed : kMode == 2 ? (HALF ? N / 2 : N) : 1;
+  using View = typename std::conditional<kMode == 2, TwTable<N, HALF>, TwPass>::type;
   // pass: per-pass tables in global memory (forward, then reversed plan);
   // full: w_N^m in global memory; lds: the staged copy.
   __device__ static const float2* staged_from(const float2* pass, const float2* full) {
