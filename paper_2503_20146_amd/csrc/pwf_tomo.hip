@@ -31,39 +31,69 @@ __global__ void fbp_ramp_kernel(float2* __restrict__ a, const float* __restrict_
   }
 }
 
-// One 16 x 16 tile of voxels of one slice per workgroup; each thread sums the
-// linearly interpolated filtered rows over all angles.  Voxel centres X, Z =
-// k + 1/2 - n_out/2; detector index u + nx/2 - 1/2 with u = X cos - Z sin.
-__global__ void __launch_bounds__(256) fbp_backproject_kernel(const float2* __restrict__ q, int n_proj, int nx,
-                                                              int ny, int n_pad, const float2* __restrict__ cs,
-                                                              int n_out, float scale, float2* __restrict__ vol) {
-  extern __shared__ float2 cs_lds[];
-  for (int j = threadIdx.x; j < n_proj; j += blockDim.x) cs_lds[j] = cs[j];
-  __syncthreads();
+// One 16 x 16 tile of voxels of one slice per workgroup.  Voxel centres X, Z =
+// k + 1/2 - n_out/2; detector index u + nx/2 - 1/2 with u = X cos - Z sin,
+// linear interpolation, 0 outside the detector.  For a chunk of angles the
+// detector samples the tile can reach are staged in LDS first: over the tile u
+// spans 15 (|cos| + |sin|) < 22 pixels, so kFbpSeg samples from one below the
+// smallest corner value cover every voxel's pair (zeros stand for samples
+// outside the detector).  Every voxel then reads its pair from LDS instead of
+// gathering it through the vector-memory path once per angle.
+constexpr int kFbpSeg = 32;     // staged samples per angle
+constexpr int kFbpChunk = 64;   // angles per staged chunk
+constexpr int kFbpThreads = 256;
+
+__global__ void __launch_bounds__(kFbpThreads) fbp_backproject_kernel(const float2* __restrict__ q, int n_proj, int nx,
+                                                                      int ny, int n_pad, const float2* __restrict__ cs,
+                                                                      int n_out, float scale, float2* __restrict__ vol) {
+  __shared__ float2 seg[kFbpChunk * kFbpSeg];
+  __shared__ float2 csl[kFbpChunk];
+  __shared__ int base[kFbpChunk];
   const int tiles = n_out / 16;
   const int y = blockIdx.x / (tiles * tiles);
   const int tile = blockIdx.x - y * tiles * tiles;
-  const int ix = (tile % tiles) * 16 + (threadIdx.x & 15);
-  const int iz = (tile / tiles) * 16 + (threadIdx.x >> 4);
-  const float X = (float)ix + 0.5f - 0.5f * (float)n_out;
-  const float Z = (float)iz + 0.5f - 0.5f * (float)n_out;
+  const int tx = tile % tiles, tz = tile / tiles;
+  const float h = 0.5f * (float)n_out;
+  const float X = (float)(tx * 16 + (threadIdx.x & 15)) + 0.5f - h;
+  const float Z = (float)(tz * 16 + (threadIdx.x >> 4)) + 0.5f - h;
+  const float X0 = (float)(tx * 16) + 0.5f - h, Z0 = (float)(tz * 16) + 0.5f - h;
   const float off = 0.5f * (float)nx - 0.5f;
   float2 acc = make_float2(0.f, 0.f);
-  const float2* row = q + (size_t)y * n_pad;
-  const size_t proj_stride = (size_t)ny * n_pad;
-  for (int j = 0; j < n_proj; ++j, row += proj_stride) {
-    const float2 c = cs_lds[j];
-    const float t = X * c.x - Z * c.y + off;
-    const float f = floorf(t);
-    const int i0 = (int)f;
-    const float w = t - f;
-    if (i0 >= -1 && i0 < nx) {
-      const float2 lo = i0 >= 0 ? row[i0] : make_float2(0.f, 0.f);
-      const float2 hi = i0 + 1 < nx ? row[i0 + 1] : make_float2(0.f, 0.f);
+  for (int j0 = 0; j0 < n_proj; j0 += kFbpChunk) {
+    const int na = min(kFbpChunk, n_proj - j0);
+    __syncthreads();  // the previous chunk's reads are done
+    if ((int)threadIdx.x < na) {
+      const float2 c = cs[j0 + threadIdx.x];
+      const float ta = X0 * c.x - Z0 * c.y, tb = (X0 + 15.f) * c.x - Z0 * c.y;
+      const float tc = X0 * c.x - (Z0 + 15.f) * c.y, td = (X0 + 15.f) * c.x - (Z0 + 15.f) * c.y;
+      base[threadIdx.x] = (int)floorf(fminf(fminf(ta, tb), fminf(tc, td)) + off) - 1;
+      csl[threadIdx.x] = c;
+    }
+    __syncthreads();
+    // every load of the chunk is issued before the first LDS write
+    constexpr int kPer = kFbpChunk * kFbpSeg / kFbpThreads;
+    float2 r[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = (int)threadIdx.x + u * kFbpThreads;
+      const int a = e / kFbpSeg, i = base[a] + e % kFbpSeg;
+      r[u] = (a < na && i >= 0 && i < nx) ? q[((size_t)(j0 + a) * ny + y) * n_pad + i] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) seg[threadIdx.x + u * kFbpThreads] = r[u];
+    __syncthreads();
+    for (int a = 0; a < na; ++a) {
+      const float2 c = csl[a];
+      const float t = X * c.x - Z * c.y + off;
+      const float f = floorf(t);
+      const float w = t - f;
+      const int k = min(max((int)f - base[a], 0), kFbpSeg - 2);
+      const float2 lo = seg[a * kFbpSeg + k], hi = seg[a * kFbpSeg + k + 1];
       acc.x += lo.x + w * (hi.x - lo.x);
       acc.y += lo.y + w * (hi.y - lo.y);
     }
   }
+  const int ix = tx * 16 + (threadIdx.x & 15), iz = tz * 16 + (threadIdx.x >> 4);
   vol[((size_t)y * n_out + iz) * n_out + ix] = make_float2(acc.x * scale, acc.y * scale);
 }
 
@@ -83,8 +113,8 @@ hipError_t launch_fbp_backproject(const float2* q, int n_proj, int nx, int ny, i
                                   float scale, float2* vol, hipStream_t st) {
   const int tiles = n_out / 16;
   const size_t blocks = (size_t)ny * tiles * tiles;
-  hipLaunchKernelGGL(fbp_backproject_kernel, dim3((unsigned)blocks), dim3(256), sizeof(float2) * n_proj, st, q,
-                     n_proj, nx, ny, n_pad, cs, n_out, scale, vol);
+  hipLaunchKernelGGL(fbp_backproject_kernel, dim3((unsigned)blocks), dim3(kFbpThreads), 0, st, q, n_proj, nx, ny, n_pad,
+                     cs, n_out, scale, vol);
   return hipGetLastError();
 }
 
