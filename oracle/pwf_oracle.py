@@ -470,7 +470,7 @@ def diffuser_from_reference(I_ref, prob: Problem, eps: float):
 # * f(X, Z) = (pi / P) sum_j q_j(u_j(X, Z)) for P equally spaced angles;
 # * psi = -mu + i phi is reconstructed as one complex sinogram (the filter is
 #   real): delta = Im(f) lambda / (2 pi p), beta = -Re(f) lambda / (2 pi p);
-# * the quadratic background fit of the paper is not part of this step.
+# * the quadratic background fit is a separate step (background_quadratic).
 
 
 def fbp_pad_length(nx: int) -> int:
@@ -533,6 +533,53 @@ def refractive_index(vol, wavelength_m: float, pixel_m: float):
     """``(delta, beta)`` of a tomogram of psi = -mu + i phi."""
     c = wavelength_m / (2.0 * math.pi * pixel_m)
     return np.imag(vol) * c, -np.real(vol) * c
+
+
+# --------------------------------------------------------------------------- background removal
+#
+# Methods ("Reconstruction procedure"): the low-frequency background curvature
+# of the tomograms (phase-gradient sensing is weak on slow phase variations) is
+# removed by fitting the background area with a two-dimensional quadratic
+# function after the reconstruction.  Readings: the fit is per slice; the
+# background area of a slice is every voxel whose centre lies at a distance
+# >= r_bg (voxels) from the rotation axis, the sample being inside that
+# cylinder; the model is b = c0 + c1 x + c2 z + c3 x^2 + c4 x z + c5 z^2 with
+# x, z the voxel-centre coordinates divided by N/2; the real and imaginary
+# parts are fitted separately by least squares, and the fitted surface is
+# subtracted from the whole slice.
+
+
+def background_basis(n: int) -> np.ndarray:
+    """The six quadratic monomials on the n x n voxel-centre grid, [6, Z, X]."""
+    c = (np.arange(n) + 0.5 - n / 2.0) / (n / 2.0)
+    x = np.broadcast_to(c[None, :], (n, n))
+    z = np.broadcast_to(c[:, None], (n, n))
+    return np.stack([np.ones((n, n)), x, z, x * x, x * z, z * z])
+
+
+def background_mask(n: int, r_bg: float) -> np.ndarray:
+    c = np.arange(n) + 0.5 - n / 2.0
+    return np.hypot(c[None, :], c[:, None]) >= r_bg
+
+
+def background_quadratic(vol, r_bg: float):
+    """Slices of ``vol`` [slice, Z, X] minus their fitted quadratic backgrounds,
+    and the coefficients [slice, part (re, im), 6]."""
+    vol = np.asarray(vol)
+    n = vol.shape[-1]
+    basis = background_basis(n)
+    mask = background_mask(n, r_bg)
+    a = basis[:, mask].T
+    if a.shape[0] < 6 or np.linalg.matrix_rank(a) < 6:
+        raise ValueError("too few background voxels for a quadratic fit")
+    out = np.empty(vol.shape, np.complex128)
+    coef = np.empty((vol.shape[0], 2, 6))
+    for s, sl in enumerate(vol):
+        coef[s, 0] = np.linalg.lstsq(a, sl.real[mask], rcond=None)[0]
+        coef[s, 1] = np.linalg.lstsq(a, sl.imag[mask], rcond=None)[0]
+        bg = np.tensordot(coef[s, 0], basis, 1) + 1j * np.tensordot(coef[s, 1], basis, 1)
+        out[s] = sl - bg
+    return out, coef
 
 
 # --------------------------------------------------------------------------- diagnostics
