@@ -169,6 +169,8 @@ def build_workload(n_proj: int, dev):
 # real/imaginary part, the difference, the interpolating fma and the sum.
 FBP_FLOPS_PER_VOXEL_ANGLE = 13
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# background removal: one read for the moments, one read and one write for the subtraction
+BACKGROUND_BYTES_PER_VOXEL = 24
 
 
 def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
@@ -179,8 +181,8 @@ def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
 
     import numpy as np
 
-    from paper_2503_20146_amd import (PWF, calibrate_source, diffuser_from_reference, fbp, problem_from_geometry,
-                                      shell_correlation)
+    from paper_2503_20146_amd import (PWF, background_quadratic, calibrate_source, diffuser_from_reference, fbp,
+                                      problem_from_geometry, shell_correlation)
 
     res = {}
     n = len(probs)
@@ -242,6 +244,20 @@ def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
                                "config": f"delta tomograms {geo.nx}^3 from retrieved vs true projections"}
         print(f"[bench] fsc {res['fsc_vs_truth']}", file=sys.stderr, flush=True)
         del vol_true
+    # quadratic background removal of the tomogram (outside the 0.46 n cylinder)
+    r_bg = 0.46 * geo.nx
+    background_quadratic(vol, r_bg)
+    torch.cuda.synchronize()
+    sec_b = time_events(lambda: background_quadratic(vol, r_bg))
+    vox = float(vol.numel())
+    bg_gbs = vox * BACKGROUND_BYTES_PER_VOXEL / sec_b / 1e9
+    res["background"] = {"ms": round(sec_b * 1e3, 2),
+                         "roofline": {"bound": "hbm", "achieved": round(bg_gbs, 1), "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": round(bg_gbs / HBM_PEAK_GBS, 4),
+                                      "bytes_per_voxel": BACKGROUND_BYTES_PER_VOXEL},
+                         "config": f"quadratic background fit per slice of the {geo.ny} x {geo.nx}^2 tomogram, "
+                                   f"background at radius >= {r_bg:g} voxels"}
+    print(f"[bench] background {res['background']}", file=sys.stderr, flush=True)
     del vol
     torch.cuda.empty_cache()
     return res

@@ -325,6 +325,28 @@ pwf_status pwf_fbp(const void* const* psi, int32_t n_proj, int32_t nx, int32_t n
                    int32_t n_out, double scale, void* vol_out, void* workspace, size_t workspace_bytes,
                    void* stream);
 
+/* Workspace bytes for pwf_background_quadratic; 0 when unsupported (n a
+ * multiple of 16 in [16, 8192], n_slices >= 1). */
+size_t pwf_background_workspace_size(int32_t n_slices, int32_t n);
+
+/* Quadratic background removal after tomography (Methods, "Reconstruction
+ * procedure": the background area of the tomogram is fitted with a
+ * two-dimensional quadratic function, which removes the low-frequency
+ * curvature of phase-gradient sensing).  vol: device complex64
+ * [n_slices][n][n] (e.g. a pwf_fbp volume, slice-major [y][Z][X]), modified in
+ * place.  For every slice, the background area is the set of voxels whose
+ * centre lies at distance >= r_bg (voxels) from the rotation axis (the slice
+ * centre); the real and imaginary parts are fitted separately by least
+ * squares with b = c0 + c1 x + c2 z + c3 x^2 + c4 x z + c5 z^2, where x, z are
+ * the voxel-centre coordinates divided by n/2, and b is subtracted from the
+ * whole slice.  Sums and coefficients in FP64, in a fixed order (the result is
+ * reproducible).  coef_out: optional HOST float64 [n_slices][2][6] (real part,
+ * then imaginary part); when given the call synchronises on `stream`.
+ * PWF_ERR_ARG when r_bg is negative or not finite or leaves too few background
+ * voxels to determine the six coefficients. */
+pwf_status pwf_background_quadratic(void* vol, int32_t n_slices, int32_t n, double r_bg, double* coef_out,
+                                    void* workspace, size_t workspace_bytes, void* stream);
+
 /* Workspace bytes for pwf_shell_correlation; 0 when unsupported (n = 128,
  * 256, 512, 1024 or 2048; dims 2 or 3). */
 size_t pwf_shell_correlation_workspace_size(int32_t n, int32_t dims);

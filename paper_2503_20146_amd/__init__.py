@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     DEFAULT_PRECOND_SCALE,
     PWF,
     Problem,
+    background_quadratic,
     calibrate_source,
     diffuser_from_reference,
     fbp,

@@ -79,6 +79,9 @@ SIGNATURES = {
                               ctypes.c_size_t, _vp]),
     "pwf_shell_correlation_workspace_size": (ctypes.c_size_t, [_i32, _i32]),
     "pwf_shell_correlation": (_i32, [_vp, _vp, _i32, _i32, _i32, _P(ctypes.c_double), _vp, ctypes.c_size_t, _vp]),
+    "pwf_background_workspace_size": (ctypes.c_size_t, [_i32, _i32]),
+    "pwf_background_quadratic": (_i32, [_vp, _i32, _i32, ctypes.c_double, _P(ctypes.c_double), _vp, ctypes.c_size_t,
+                                        _vp]),
     "pwf_fbp_workspace_size": (ctypes.c_size_t, [_i32, _i32, _i32]),
     "pwf_fbp": (_i32, [_P(_vp), _i32, _i32, _i32, _P(ctypes.c_double), _i32, ctypes.c_double, _vp, _vp,
                        ctypes.c_size_t, _vp]),

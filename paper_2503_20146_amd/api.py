@@ -327,6 +327,30 @@ def fbp(psis: Sequence[torch.Tensor], angles_rad: Sequence[float], n_out: int | 
     return vol
 
 
+def background_quadratic(vol: torch.Tensor, r_bg: float, coefficients: bool = False):
+    """Quadratic background removal of a tomogram [slices, n, n] complex64, in place
+    (pwf_background_quadratic): per slice, the least-squares quadratic fitted to the
+    voxels at radius >= r_bg (voxels) from the rotation axis is subtracted.  With
+    ``coefficients`` also returns the fitted coefficients [slices][2][6] (FP64)."""
+    if vol.dtype != torch.complex64 or vol.dim() != 3 or vol.shape[1] != vol.shape[2]:
+        raise ValueError("a complex64 volume [slices, n, n]")
+    if not (vol.is_cuda and vol.is_contiguous()):
+        raise ValueError("a contiguous GPU array")
+    lib = _lib.load()
+    n_slices, n = vol.shape[0], vol.shape[1]
+    size = lib.pwf_background_workspace_size(n_slices, n)
+    if size == 0:
+        raise ValueError("unsupported size for the background fit")
+    ws = torch.empty(size, dtype=torch.uint8, device=vol.device)
+    coef = (ctypes.c_double * (12 * n_slices))() if coefficients else None
+    check(lib.pwf_background_quadratic(ctypes.c_void_p(vol.data_ptr()), n_slices, n, float(r_bg), coef,
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(vol.device)),
+          "pwf_background_quadratic")
+    if coefficients:
+        return vol, [[list(coef[(12 * s + 6 * p):(12 * s + 6 * p + 6)]) for p in range(2)] for s in range(n_slices)]
+    return vol
+
+
 def shell_correlation(g1: torch.Tensor, g2: torch.Tensor, part: int = 1):
     """Fourier shell (3-D) or ring (2-D) correlation of Eq. 16 (pwf_shell_correlation):
     a list over shells 0..n/2 of the real (part 0) or imaginary (part 1) parts' FSC."""

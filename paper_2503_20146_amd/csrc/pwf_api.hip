@@ -1460,6 +1460,104 @@ pwf_status pwf_fbp(const void* const* psi, int32_t n_proj, int32_t nx, int32_t n
   return PWF_OK;
 }
 
+// ------------------------------------------------------------ background removal
+
+namespace {
+constexpr int kBgMaxN = 8192;
+
+bool bg_layout(int n_slices, int n, size_t* part_off, size_t* coef_off, size_t* total) {
+  if (n_slices < 1 || n < 16 || n % 16 || n > kBgMaxN) return false;
+  const size_t bands = (size_t)(n / pwf::bg_rows_per_band(n));
+  *part_off = align_up(sizeof(double) * 36);
+  *coef_off = *part_off + align_up(sizeof(double) * 12 * bands * n_slices);
+  *total = *coef_off + align_up(sizeof(double) * 12 * (size_t)n_slices);
+  return true;
+}
+
+// Inverse of the 6 x 6 normal matrix of the quadratic monomials over the
+// background voxels (radius >= r_bg), FP64 Gauss-Jordan with partial pivoting.
+// False when fewer than 6 voxels or a pivot below 1e-12 of the largest
+// diagonal entry leave the fit undetermined.
+bool bg_normal_inverse(int n, double r_bg, double (&inv)[36]) {
+  double M[36] = {0.0};
+  const double h = 0.5 * n, inv_h = 1.0 / h, r2 = r_bg * r_bg;
+  size_t count = 0;
+  for (int iz = 0; iz < n; ++iz) {
+    const double Z = iz + 0.5 - h;
+    for (int ix = 0; ix < n; ++ix) {
+      const double X = ix + 0.5 - h;
+      if (X * X + Z * Z < r2) continue;
+      const double x = X * inv_h, z = Z * inv_h;
+      const double m[6] = {1.0, x, z, x * x, x * z, z * z};
+      for (int a = 0; a < 6; ++a)
+        for (int b = a; b < 6; ++b) M[a * 6 + b] += m[a] * m[b];
+      ++count;
+    }
+  }
+  if (count < 6) return false;
+  double scale = 0.0;
+  for (int a = 0; a < 6; ++a) {
+    for (int b = 0; b < a; ++b) M[a * 6 + b] = M[b * 6 + a];
+    scale = std::max(scale, M[a * 6 + a]);
+  }
+  for (int i = 0; i < 36; ++i) inv[i] = (i % 7 == 0) ? 1.0 : 0.0;
+  for (int c = 0; c < 6; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 6; ++r)
+      if (std::fabs(M[r * 6 + c]) > std::fabs(M[piv * 6 + c])) piv = r;
+    if (!(std::fabs(M[piv * 6 + c]) > 1e-12 * scale)) return false;
+    for (int k = 0; k < 6; ++k) {
+      std::swap(M[c * 6 + k], M[piv * 6 + k]);
+      std::swap(inv[c * 6 + k], inv[piv * 6 + k]);
+    }
+    const double d = 1.0 / M[c * 6 + c];
+    for (int k = 0; k < 6; ++k) {
+      M[c * 6 + k] *= d;
+      inv[c * 6 + k] *= d;
+    }
+    for (int r = 0; r < 6; ++r) {
+      if (r == c) continue;
+      const double f = M[r * 6 + c];
+      for (int k = 0; k < 6; ++k) {
+        M[r * 6 + k] -= f * M[c * 6 + k];
+        inv[r * 6 + k] -= f * inv[c * 6 + k];
+      }
+    }
+  }
+  return true;
+}
+}  // namespace
+
+size_t pwf_background_workspace_size(int32_t n_slices, int32_t n) {
+  size_t part_off, coef_off, total;
+  return bg_layout(n_slices, n, &part_off, &coef_off, &total) ? total : 0;
+}
+
+pwf_status pwf_background_quadratic(void* vol, int32_t n_slices, int32_t n, double r_bg, double* coef_out,
+                                    void* workspace, size_t workspace_bytes, void* stream) {
+  size_t part_off, coef_off, total;
+  if (!bg_layout(n_slices, n, &part_off, &coef_off, &total)) return PWF_ERR_SIZE;
+  if (!vol || !std::isfinite(r_bg) || r_bg < 0.0) return PWF_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < total) return PWF_ERR_WORKSPACE;
+  double inv[36];
+  if (!bg_normal_inverse(n, r_bg, inv)) return PWF_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Context* ctx;
+  PWF_TRY(context_for_current(&ctx));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  PWF_TRY(upload(*ctx, inv, sizeof(inv), ws, st));
+  double* partial = (double*)(ws + part_off);
+  double* coef = (double*)(ws + coef_off);
+  PWF_HIP(pwf::launch_bg_moments((const float2*)vol, n_slices, n, r_bg, partial, st));
+  PWF_HIP(pwf::launch_bg_subtract((float2*)vol, n_slices, n, partial, (const double*)ws, coef, st));
+  if (coef_out) {
+    PWF_HIP(hipMemcpyAsync(coef_out, coef, sizeof(double) * 12 * (size_t)n_slices, hipMemcpyDeviceToHost, st));
+    PWF_HIP(hipStreamSynchronize(st));
+  }
+  return PWF_OK;
+}
+
 // ------------------------------------------------------------ shell correlation
 
 namespace {

@@ -97,6 +97,14 @@ int fsc_blocks();
 hipError_t launch_fsc_part(const float2* src, int part, float2* dst, size_t m, hipStream_t st);
 hipError_t launch_fsc_shells(const float2* g1, const float2* g2, int n, int dims, double* partial, double* out,
                              hipStream_t st);
+// Quadratic background removal (pwf_tomo.hip): n a multiple of 16; slices are
+// split into bands of bg_rows_per_band(n) rows (n a multiple of that).
+// partial: n_slices * (n / rows) * 12 doubles; minv: the inverse 6 x 6 normal
+// matrix (row-major); coef: n_slices * 12 doubles.
+int bg_rows_per_band(int n);
+hipError_t launch_bg_moments(const float2* vol, int n_slices, int n, double r_bg, double* partial, hipStream_t st);
+hipError_t launch_bg_subtract(float2* vol, int n_slices, int n, const double* partial, const double* minv,
+                              double* coef, hipStream_t st);
 // Calibration: FP64 partial sums, per workgroup, of sum I, sum I(x,y) I(x+d,y)
 // and sum I(x,y) I(x,y+d) for d = 0..max_shift (circular shifts), then their
 // ordered total -> out[0] = sum I, out[1 + d] = x-shift sum, out[2 + kMaxShift + d]

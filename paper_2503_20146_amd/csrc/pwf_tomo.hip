@@ -37,25 +37,26 @@ __global__ void fbp_ramp_kernel(float2* __restrict__ a, const float* __restrict_
 // detector samples the tile can reach are staged in LDS first: over the tile u
 // spans 15 (|cos| + |sin|) < 22 pixels, so kFbpSeg samples from one below the
 // smallest corner value cover every voxel's pair (zeros stand for samples
-// outside the detector).  Every voxel then reads its pair from LDS instead of
-// gathering it through the vector-memory path once per angle.
+// outside the detector).  Each staged entry holds a sample and the step to the
+// next one, so that a voxel's interpolation is one LDS read and two FMAs per
+// part, instead of a gather through the vector-memory path once per angle.
 constexpr int kFbpSeg = 32;     // staged samples per angle
-constexpr int kFbpChunk = 64;   // angles per staged chunk
+constexpr int kFbpChunk = 32;   // angles per staged chunk
 constexpr int kFbpThreads = 256;
 
 __global__ void __launch_bounds__(kFbpThreads) fbp_backproject_kernel(const float2* __restrict__ q, int n_proj, int nx,
                                                                       int ny, int n_pad, const float2* __restrict__ cs,
                                                                       int n_out, float scale, float2* __restrict__ vol) {
-  __shared__ float2 seg[kFbpChunk * kFbpSeg];
-  __shared__ float2 csl[kFbpChunk];
+  __shared__ float4 seg[kFbpChunk * kFbpSeg];  // sample k, then sample k + 1 minus sample k
+  __shared__ float2 csl[kFbpChunk];  // cos, sin
+  __shared__ float t0l[kFbpChunk];   // detector index of the tile's first voxel minus base
   __shared__ int base[kFbpChunk];
   const int tiles = n_out / 16;
   const int y = blockIdx.x / (tiles * tiles);
   const int tile = blockIdx.x - y * tiles * tiles;
   const int tx = tile % tiles, tz = tile / tiles;
   const float h = 0.5f * (float)n_out;
-  const float X = (float)(tx * 16 + (threadIdx.x & 15)) + 0.5f - h;
-  const float Z = (float)(tz * 16 + (threadIdx.x >> 4)) + 0.5f - h;
+  const float dx = (float)(threadIdx.x & 15), dz = (float)(threadIdx.x >> 4);  // voxel within the tile
   const float X0 = (float)(tx * 16) + 0.5f - h, Z0 = (float)(tz * 16) + 0.5f - h;
   const float off = 0.5f * (float)nx - 0.5f;
   float2 acc = make_float2(0.f, 0.f);
@@ -66,31 +67,38 @@ __global__ void __launch_bounds__(kFbpThreads) fbp_backproject_kernel(const floa
       const float2 c = cs[j0 + threadIdx.x];
       const float ta = X0 * c.x - Z0 * c.y, tb = (X0 + 15.f) * c.x - Z0 * c.y;
       const float tc = X0 * c.x - (Z0 + 15.f) * c.y, td = (X0 + 15.f) * c.x - (Z0 + 15.f) * c.y;
-      base[threadIdx.x] = (int)floorf(fminf(fminf(ta, tb), fminf(tc, td)) + off) - 1;
+      const int b0 = (int)floorf(fminf(fminf(ta, tb), fminf(tc, td)) + off) - 1;
+      base[threadIdx.x] = b0;
+      // u + nx/2 - 1/2 - base = (ta + off - base) + dx cos - dz sin: small numbers,
+      // so the index and the weight keep more bits than from u itself
       csl[threadIdx.x] = c;
+      t0l[threadIdx.x] = (ta + off) - (float)b0;
     }
     __syncthreads();
     // every load of the chunk is issued before the first LDS write
     constexpr int kPer = kFbpChunk * kFbpSeg / kFbpThreads;
-    float2 r[kPer];
+    float2 r0[kPer], r1[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = (int)threadIdx.x + u * kFbpThreads;
       const int a = e / kFbpSeg, i = base[a] + e % kFbpSeg;
-      r[u] = (a < na && i >= 0 && i < nx) ? q[((size_t)(j0 + a) * ny + y) * n_pad + i] : make_float2(0.f, 0.f);
+      const float2* row = q + ((size_t)(j0 + a) * ny + y) * n_pad;
+      r0[u] = (a < na && i >= 0 && i < nx) ? row[i] : make_float2(0.f, 0.f);
+      r1[u] = (a < na && i + 1 >= 0 && i + 1 < nx) ? row[i + 1] : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) seg[threadIdx.x + u * kFbpThreads] = r[u];
+    for (int u = 0; u < kPer; ++u)
+      seg[threadIdx.x + u * kFbpThreads] = make_float4(r0[u].x, r0[u].y, r1[u].x - r0[u].x, r1[u].y - r0[u].y);
     __syncthreads();
     for (int a = 0; a < na; ++a) {
       const float2 c = csl[a];
-      const float t = X * c.x - Z * c.y + off;
+      const float t = fmaf(dx, c.x, fmaf(-dz, c.y, t0l[a]));
       const float f = floorf(t);
       const float w = t - f;
-      const int k = min(max((int)f - base[a], 0), kFbpSeg - 2);
-      const float2 lo = seg[a * kFbpSeg + k], hi = seg[a * kFbpSeg + k + 1];
-      acc.x += lo.x + w * (hi.x - lo.x);
-      acc.y += lo.y + w * (hi.y - lo.y);
+      const int k = min(max((int)f, 0), kFbpSeg - 1);
+      const float4 p = seg[a * kFbpSeg + k];
+      acc.x = fmaf(w, p.z, acc.x + p.x);
+      acc.y = fmaf(w, p.w, acc.y + p.y);
     }
   }
   const int ix = tx * 16 + (threadIdx.x & 15), iz = tz * 16 + (threadIdx.x >> 4);
@@ -180,6 +188,133 @@ hipError_t launch_fsc_shells(const float2* g1, const float2* g2, int n, int dims
                      partial);
   hipLaunchKernelGGL(fsc_final_kernel, dim3((3 * nsh + 255) / 256), dim3(256), 0, st, partial, fsc_blocks(),
                      3 * nsh, out);
+  return hipGetLastError();
+}
+
+}  // namespace pwf
+
+namespace pwf {
+
+// Quadratic background removal after tomography (Methods, "Reconstruction
+// procedure"): per slice, the least-squares quadratic in x, z (voxel-centre
+// coordinates over n/2) fitted separately to the real and imaginary parts of
+// the voxels at radius >= r_bg, subtracted from the whole slice.  The normal
+// matrix depends only on the grid and the radius; the host inverts it once.
+// Each slice is split into kBgRows-row bands, one workgroup per band.
+constexpr int kBgThreads = 256;
+
+__device__ __forceinline__ void bg_monomials(double x, double z, double (&m)[6]) {
+  m[0] = 1.0;
+  m[1] = x;
+  m[2] = z;
+  m[3] = x * x;
+  m[4] = x * z;
+  m[5] = z * z;
+}
+
+// partial[(slice * bands + band) * 12 + p * 6 + k] = sum over the band's
+// background voxels of monomial k times part p (0 real, 1 imaginary).
+__global__ void __launch_bounds__(kBgThreads) bg_moments_kernel(const float2* __restrict__ vol, int n, int rows,
+                                                               double r2_bg, double* __restrict__ partial) {
+  const int bands = n / rows;
+  const int slice = blockIdx.x / bands, band = blockIdx.x - slice * bands;
+  const double h = 0.5 * n, inv_h = 1.0 / h;
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  for (int r = 0; r < rows; ++r) {
+    const int iz = band * rows + r;
+    const double Z = (double)iz + 0.5 - h;
+    const float2* row = vol + ((size_t)slice * n + iz) * n;
+    for (int ix = threadIdx.x; ix < n; ix += kBgThreads) {
+      const double X = (double)ix + 0.5 - h;
+      if (X * X + Z * Z < r2_bg) continue;
+      const float2 v = row[ix];
+      double m[6];
+      bg_monomials(X * inv_h, Z * inv_h, m);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        acc[k] = fma(m[k], (double)v.x, acc[k]);
+        acc[6 + k] = fma(m[k], (double)v.y, acc[6 + k]);
+      }
+    }
+  }
+  // fixed-order reduction: wave butterflies, then the waves in order
+  __shared__ double red[kBgThreads / 64][12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    double a = acc[k];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    double a = 0.0;
+    for (int w = 0; w < kBgThreads / 64; ++w) a += red[w][threadIdx.x];
+    partial[(size_t)blockIdx.x * 12 + threadIdx.x] = a;
+  }
+}
+
+// Coefficients of every slice (band sums in order, times the inverse normal
+// matrix), then the surface subtracted over the band.  coef[slice * 12 + p * 6
+// + k]: coefficient k of part p, written by the slice's first band.
+__global__ void __launch_bounds__(kBgThreads) bg_subtract_kernel(float2* __restrict__ vol, int n, int rows,
+                                                                const double* __restrict__ partial,
+                                                                const double* __restrict__ minv,
+                                                                double* __restrict__ coef) {
+  const int bands = n / rows;
+  const int slice = blockIdx.x / bands, band = blockIdx.x - slice * bands;
+  __shared__ double mom[12], c[12];
+  if (threadIdx.x < 12) {
+    double a = 0.0;
+    for (int b = 0; b < bands; ++b) a += partial[((size_t)slice * bands + b) * 12 + threadIdx.x];
+    mom[threadIdx.x] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    const int p = threadIdx.x / 6, k = threadIdx.x % 6;
+    double a = 0.0;
+    for (int j = 0; j < 6; ++j) a = fma(minv[k * 6 + j], mom[p * 6 + j], a);
+    c[threadIdx.x] = a;
+    if (band == 0) coef[(size_t)slice * 12 + threadIdx.x] = a;
+  }
+  __syncthreads();
+  const double h = 0.5 * n, inv_h = 1.0 / h;
+  for (int r = 0; r < rows; ++r) {
+    const int iz = band * rows + r;
+    const double z = ((double)iz + 0.5 - h) * inv_h;
+    float2* row = vol + ((size_t)slice * n + iz) * n;
+    for (int ix = threadIdx.x; ix < n; ix += kBgThreads) {
+      double m[6];
+      bg_monomials(((double)ix + 0.5 - h) * inv_h, z, m);
+      double bre = 0.0, bim = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        bre = fma(c[k], m[k], bre);
+        bim = fma(c[6 + k], m[k], bim);
+      }
+      const float2 v = row[ix];
+      row[ix] = make_float2((float)((double)v.x - bre), (float)((double)v.y - bim));
+    }
+  }
+}
+
+int bg_rows_per_band(int n) { return n % 64 == 0 ? 64 : 16; }
+
+hipError_t launch_bg_moments(const float2* vol, int n_slices, int n, double r_bg, double* partial, hipStream_t st) {
+  const int rows = bg_rows_per_band(n);
+  const size_t blocks = (size_t)n_slices * (n / rows);
+  hipLaunchKernelGGL(bg_moments_kernel, dim3((unsigned)blocks), dim3(kBgThreads), 0, st, vol, n, rows, r_bg * r_bg,
+                     partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_bg_subtract(float2* vol, int n_slices, int n, const double* partial, const double* minv,
+                              double* coef, hipStream_t st) {
+  const int rows = bg_rows_per_band(n);
+  const size_t blocks = (size_t)n_slices * (n / rows);
+  hipLaunchKernelGGL(bg_subtract_kernel, dim3((unsigned)blocks), dim3(kBgThreads), 0, st, vol, n, rows, partial,
+                     minv, coef);
   return hipGetLastError();
 }
 

@@ -225,3 +225,20 @@ def test_shell_correlation_argument_errors(lib):
     assert lib.pwf_shell_correlation(None, p, 128, 2, 0, out, ws, size, None) == -1
     assert lib.pwf_shell_correlation(p, p, 128, 2, 0, out, ws, size - 1, None) == -4
     assert lib.pwf_shell_correlation(p, p, 96, 2, 0, out, ws, size, None) == -2
+
+
+def test_background_argument_errors(lib):
+    """Every refusal of pwf_background_quadratic happens on the host, before any GPU work."""
+    assert lib.pwf_background_workspace_size(4, 64) > 0
+    assert lib.pwf_background_workspace_size(0, 64) == 0
+    assert lib.pwf_background_workspace_size(4, 40) == 0
+    assert lib.pwf_background_workspace_size(4, 8) == 0
+    size = lib.pwf_background_workspace_size(4, 64)
+    ws = ctypes.c_void_p(0x100000)
+    v = ctypes.c_void_p(0x2000)
+    assert lib.pwf_background_quadratic(None, 4, 64, 20.0, None, ws, size, None) == -1
+    assert lib.pwf_background_quadratic(v, 4, 64, -1.0, None, ws, size, None) == -1
+    assert lib.pwf_background_quadratic(v, 4, 64, float("nan"), None, ws, size, None) == -1
+    assert lib.pwf_background_quadratic(v, 4, 64, 32.0 * 2 ** 0.5, None, ws, size, None) == -1  # no background
+    assert lib.pwf_background_quadratic(v, 4, 64, 20.0, None, ws, size - 1, None) == -4
+    assert lib.pwf_background_quadratic(v, 4, 48 + 2, 20.0, None, ws, size, None) == -2

@@ -1,0 +1,104 @@
+"""Quadratic background removal on the GPU (pwf_background_quadratic) against
+the oracle.
+
+Both fit the same FP32 volume; the GPU accumulates the normal equations in
+FP64 and the oracle solves the least-squares problem in FP64, so the
+coefficients agree to rounding (1e-9 absolute for O(1) data, a bound far above
+the ~1e-13 either side makes) and the corrected voxels to the FP32 rounding of
+the subtraction (2e-6 of the largest magnitude).  Cases: random slices at
+n = 64 (one band per slice) and n = 80 (five bands of 16 rows), a sample
+inside the cylinder on a quadratic background (the fit must return the sample
+alone), and the full 1024 slices x 1024^2 tomogram shape, checked on sampled
+slices, with run-to-run bitwise reproducibility.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_helpers import device, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+COEF_TOL = 1e-9
+VOX_TOL = 2e-6
+
+
+def _monomials(n):
+    c = (np.arange(n) + 0.5 - n / 2.0) / (n / 2.0)
+    x = np.broadcast_to(c[None, :], (n, n))
+    z = np.broadcast_to(c[:, None], (n, n))
+    return np.stack([np.ones((n, n)), x, z, x * x, x * z, z * z])
+
+
+@pytest.mark.parametrize("n", [64, 80])
+def test_background_matches_oracle(n):
+    import torch
+    from paper_2503_20146_amd import background_quadratic
+    dev = device()
+    rng = np.random.default_rng(100 + n)
+    vol = (rng.standard_normal((5, n, n)) + 1j * rng.standard_normal((5, n, n))).astype(np.complex64)
+    r_bg = 0.35 * n
+    say(f"background fit 5 x {n}^2, r_bg {r_bg}")
+    tv = to_dev(vol, dev)
+    _, coef = background_quadratic(tv, r_bg, coefficients=True)
+    torch.cuda.synchronize()
+    ref, ref_coef = O.background_quadratic(vol.astype(np.complex128), r_bg)
+    assert np.max(np.abs(np.array(coef) - ref_coef)) <= COEF_TOL
+    got = tv.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= VOX_TOL * np.max(np.abs(vol))
+
+
+def test_sample_inside_the_cylinder_is_recovered():
+    from paper_2503_20146_amd import background_quadratic
+    dev = device()
+    n, r_bg = 128, 50.0
+    rng = np.random.default_rng(7)
+    c = np.arange(n) + 0.5 - n / 2.0
+    sample = np.where(np.hypot(c[None, :] - 8, c[:, None] + 5) < 30, 0.2 + 0.5j, 0.0)
+    sample = sample + np.where(np.hypot(c[None, :] + 20, c[:, None] - 12) < 12, -0.1j, 0.0)
+    coefs = rng.standard_normal((3, 2, 6))
+    mono = _monomials(n)
+    vol = np.stack([sample + np.tensordot(k[0], mono, 1) + 1j * np.tensordot(k[1], mono, 1) for k in coefs])
+    say("background fit: sample inside the cylinder, 3 x 128^2")
+    tv = to_dev(vol.astype(np.complex64), dev)
+    _, coef = background_quadratic(tv, r_bg, coefficients=True)
+    assert np.max(np.abs(np.array(coef) - coefs)) <= 1e-5   # FP32 inputs: coefficients to their rounding
+    got = tv.cpu().numpy()
+    assert np.max(np.abs(got - sample[None])) <= 1e-5
+
+
+def test_full_size_sampled_slices():
+    """1024 slices x 1024^2 (the tomogram of the 180 x 1024^2 workload), bands of
+    64 rows: sampled slices against the oracle, and two runs bit for bit."""
+    import torch
+    from paper_2503_20146_amd import background_quadratic
+    dev = device()
+    n, slices, r_bg = 1024, 1024, 470.0
+    rng = np.random.default_rng(11)
+    base = (rng.standard_normal((4, n, n)) + 1j * rng.standard_normal((4, n, n))).astype(np.complex64)
+    coefs = rng.standard_normal((slices, 2, 6)).astype(np.float32)
+    mono = torch.from_numpy(_monomials(n).reshape(6, -1).astype(np.float32)).to(dev)
+    tb = to_dev(base, dev)
+    tc = torch.from_numpy(coefs).to(dev)
+    say("background fit 1024 x 1024^2: building the volume")
+    vol = torch.empty((slices, n, n), dtype=torch.complex64, device=dev)
+    for s0 in range(0, slices, 64):
+        re = (tc[s0:s0 + 64, 0] @ mono).view(-1, n, n)
+        im = (tc[s0:s0 + 64, 1] @ mono).view(-1, n, n)
+        idx = torch.arange(s0, s0 + 64, device=dev) % 4
+        vol[s0:s0 + 64] = tb[idx] + torch.complex(re, im)
+    sample_idx = [0, 333, 1023]
+    before = vol[sample_idx].cpu().numpy()
+    vol2 = vol.clone()
+    say("background fit 1024 x 1024^2: two runs")
+    _, coef = background_quadratic(vol, r_bg, coefficients=True)
+    background_quadratic(vol2, r_bg)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(vol[sample_idx]), torch.view_as_real(vol2[sample_idx]))
+    ref, ref_coef = O.background_quadratic(before.astype(np.complex128), r_bg)
+    got = vol[sample_idx].cpu().numpy()
+    assert np.max(np.abs(np.array(coef)[sample_idx] - ref_coef)) <= COEF_TOL
+    assert np.max(np.abs(got - ref)) <= VOX_TOL * np.max(np.abs(before))
+    del vol, vol2
+    torch.cuda.empty_cache()
