@@ -239,7 +239,9 @@ def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
         fsc = shell_correlation(vol, vol_true, part=1)
         t_fsc = time.perf_counter() - t0
         kappa = next((k for k in range(1, len(fsc)) if fsc[k] < 0.5), len(fsc) - 1)
+        kappa_q = next((k for k in range(1, len(fsc)) if fsc[k] < 0.25), len(fsc) - 1)   # Eqs. 17-18
         res["fsc_vs_truth"] = {"ms": round(t_fsc * 1e3, 2),
+                               "resolution_um_at_quarter": round(geo.nx * geo.pixel_m / kappa_q * 1e6, 3),
                                "resolution_um_at_half": round(geo.nx * geo.pixel_m / kappa * 1e6, 3),
                                "fsc_at_shells_64_128_256_512": [round(fsc[k], 4) for k in (64, 128, 256, 512)],
                                "config": f"delta tomograms {geo.nx}^3 from retrieved vs true projections"}
