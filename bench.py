@@ -298,9 +298,25 @@ def cpu_baseline(iters: int):
     for _ in range(iters):
         st, _ = O.pwf_step(st, y, prob)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, a shorter sample
+    O.FFT_WORKERS = 1
+    it1 = max(1, iters // 8)
+    t0 = time.perf_counter()
+    for _ in range(it1):
+        st, _ = O.pwf_step(st, y, prob)
+    dt1 = time.perf_counter() - t0
+    O.FFT_WORKERS = threads
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": iters / dt, "unit": "proj-iter/s", "cores": threads, "kind": "oracle",
             "sample": f"1 projection of 1024^2 (projection 0 of the workload), {iters} iterations of the "
-                      f"FP64 scipy.fft oracle after 1 warm-up iteration, {dt:.1f} s"}
+                      f"FP64 scipy.fft oracle after 1 warm-up iteration, {dt:.1f} s",
+            "single_thread": {"value": it1 / dt1, "sample": f"{it1} further iterations on 1 thread, {dt1:.1f} s"},
+            "cpu_model": model}
 
 
 def main() -> int:
