@@ -1539,8 +1539,23 @@ pwf_status pwf_background_quadratic(void* vol, int32_t n_slices, int32_t n, doub
   if (!bg_layout(n_slices, n, &part_off, &coef_off, &total)) return PWF_ERR_SIZE;
   if (!vol || !std::isfinite(r_bg) || r_bg < 0.0) return PWF_ERR_ARG;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < total) return PWF_ERR_WORKSPACE;
+  // the normal matrix depends only on (n, r_bg): keep the last inversion (an
+  // O(n^2) host loop) for repeated calls on tomograms of one shape
+  static std::mutex inv_mu;
+  static int inv_n = 0;
+  static double inv_r = -1.0, inv_cached[36];
+  static bool inv_ok = false;
   double inv[36];
-  if (!bg_normal_inverse(n, r_bg, inv)) return PWF_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> lk(inv_mu);
+    if (inv_n != n || inv_r != r_bg) {
+      inv_ok = bg_normal_inverse(n, r_bg, inv_cached);
+      inv_n = n;
+      inv_r = r_bg;
+    }
+    if (!inv_ok) return PWF_ERR_ARG;
+    std::memcpy(inv, inv_cached, sizeof(inv));
+  }
   std::lock_guard<std::mutex> lk(g_mu);
   Context* ctx;
   PWF_TRY(context_for_current(&ctx));

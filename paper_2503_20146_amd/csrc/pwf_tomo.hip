@@ -222,20 +222,32 @@ __global__ void __launch_bounds__(kBgThreads) bg_moments_kernel(const float2* __
   double acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  // kBgCols columns per lane at a time, their loads issued before the sums
+  constexpr int kBgCols = 4;
   for (int r = 0; r < rows; ++r) {
     const int iz = band * rows + r;
     const double Z = (double)iz + 0.5 - h;
     const float2* row = vol + ((size_t)slice * n + iz) * n;
-    for (int ix = threadIdx.x; ix < n; ix += kBgThreads) {
-      const double X = (double)ix + 0.5 - h;
-      if (X * X + Z * Z < r2_bg) continue;
-      const float2 v = row[ix];
-      double m[6];
-      bg_monomials(X * inv_h, Z * inv_h, m);
+    for (int ix0 = threadIdx.x; ix0 < n; ix0 += kBgCols * kBgThreads) {
+      float2 v[kBgCols];
+      bool bg[kBgCols];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        acc[k] = fma(m[k], (double)v.x, acc[k]);
-        acc[6 + k] = fma(m[k], (double)v.y, acc[6 + k]);
+      for (int u = 0; u < kBgCols; ++u) {
+        const int ix = ix0 + u * kBgThreads;
+        const double X = (double)ix + 0.5 - h;
+        bg[u] = ix < n && X * X + Z * Z >= r2_bg;
+        v[u] = bg[u] ? row[ix] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < kBgCols; ++u) {
+        if (!bg[u]) continue;
+        double m[6];
+        bg_monomials(((double)(ix0 + u * kBgThreads) + 0.5 - h) * inv_h, Z * inv_h, m);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          acc[k] = fma(m[k], (double)v[u].x, acc[k]);
+          acc[6 + k] = fma(m[k], (double)v[u].y, acc[6 + k]);
+        }
       }
     }
   }
