@@ -6,7 +6,8 @@ FP64 and the oracle solves the least-squares problem in FP64, so the
 coefficients agree to rounding (1e-9 absolute for O(1) data, a bound far above
 the ~1e-13 either side makes) and the corrected voxels to the FP32 rounding of
 the subtraction (2e-6 of the largest magnitude).  Cases: random slices at
-n = 64 (one band per slice) and n = 80 (five bands of 16 rows), a sample
+n = 64 (one band per slice) and n = 80 (five bands of 16 rows), the smallest
+side with the whole slice as background, the corners alone, a sample
 inside the cylinder on a quadratic background (the fit must return the sample
 alone), and the full 1024 slices x 1024^2 tomogram shape, checked on sampled
 slices, with run-to-run bitwise reproducibility.
@@ -31,14 +32,14 @@ def _monomials(n):
     return np.stack([np.ones((n, n)), x, z, x * x, x * z, z * z])
 
 
-@pytest.mark.parametrize("n", [64, 80])
-def test_background_matches_oracle(n):
+@pytest.mark.parametrize("n,frac", [(64, 0.35), (80, 0.35), (16, 0.0), (48, 0.6)])
+def test_background_matches_oracle(n, frac):
     import torch
     from paper_2503_20146_amd import background_quadratic
     dev = device()
     rng = np.random.default_rng(100 + n)
     vol = (rng.standard_normal((5, n, n)) + 1j * rng.standard_normal((5, n, n))).astype(np.complex64)
-    r_bg = 0.35 * n
+    r_bg = frac * n   # 0: the whole slice is background; 0.6 n: only the corners
     say(f"background fit 5 x {n}^2, r_bg {r_bg}")
     tv = to_dev(vol, dev)
     _, coef = background_quadratic(tv, r_bg, coefficients=True)
