@@ -395,15 +395,18 @@ struct TwLayout {
 // Where a sweep kernel reads its twiddles from.  Mode 1: the per-pass tables
 // of a palindromic plan staged in LDS (conflict-free reads; the inverse shares
 // them).  Mode 2: the single table w_N^m staged in LDS (N entries, fewer than
-// the per-pass tables of both directions).  Mode 0: per-pass tables in global
-// memory, where no staged table fits beside the exchange buffer (N > 1024).
-// HALF: stage the half table in mode 2 (see TwTable).
-template <class Plan, bool HALF = false>
+// the per-pass tables of both directions).  HALF: stage the half table in
+// mode 2 (see TwTable).  Mode 0: per-pass tables read from global memory.
+// Above 1024 points the full table (16 KB at 2048) would leave room for only
+// one workgroup per CU beside the exchange buffer: kernels that pass
+// STAGE_LARGE stage the half table there, the others use mode 0.
+template <class Plan, bool HALF = false, bool STAGE_LARGE = false>
 struct TwSel {
   static constexpr int N = Plan::kN;
-  static constexpr int kMode = N > 1024 ? 0 : (TwLayout<Plan>::kSelfReverse ? 1 : 2);
-  static constexpr int kLds = kMode == 1 ? TwLayout<Plan>::kUsed : kMode == 2 ? (HALF ? N / 2 : N) : 1;
-  using View = typename std::conditional<kMode == 2, TwTable<N, HALF>, TwPass>::type;
+  static constexpr bool kHalf = HALF || N > 1024;
+  static constexpr int kMode = N > 1024 ? (STAGE_LARGE ? 2 : 0) : (TwLayout<Plan>::kSelfReverse ? 1 : 2);
+  static constexpr int kLds = kMode == 1 ? TwLayout<Plan>::kUsed : kMode == 2 ? (kHalf ? N / 2 : N) : 1;
+  using View = typename std::conditional<kMode == 2, TwTable<N, kHalf>, TwPass>::type;
   // pass: per-pass tables in global memory (forward, then reversed plan);
   // full: w_N^m in global memory; lds: the staged copy.
   __device__ static const float2* staged_from(const float2* pass, const float2* full) {

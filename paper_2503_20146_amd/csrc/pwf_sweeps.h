@@ -338,15 +338,18 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
 
 // ------------------------------------------------------------------ column sweeps
 
-// Column tile of the j-th workgroup of an instance with B tiles.  Tiles 2m and
-// 2m + 1 share 128-byte lines and stay adjacent in time; the pairs are dealt
-// out over the four quarters of the row (pair m -> (m mod 4) B/8 + m/4), so that
-// the workgroups in flight touch more HBM channels (about 1% on the column
-// sweeps at 1024^2).  Identity when 4 does not divide B/2.
+// Column tile of the j-th workgroup of an instance with B tiles of W columns.
+// The G = 128 / (8 W) tiles that share a 128-byte line stay adjacent in time;
+// the groups are dealt out over the four quarters of the row (group m ->
+// (m mod 4) B/(4G) + m/4), so that the workgroups in flight touch more HBM
+// channels (about 1% on the column sweeps at 1024^2).  Identity when 4 does
+// not divide B/G.
+template <int W>
 __device__ __forceinline__ int col_tile_of(int j, int B) {
-  const int np = B >> 1, m = j >> 1;
-  if (np & 3) return j;
-  return ((((m & 3) * (np >> 2)) + (m >> 2)) << 1) | (j & 1);
+  constexpr int G = W >= 16 ? 1 : 16 / W;
+  const int ng = B / G, m = j / G;
+  if (ng & 3) return j;
+  return (((m & 3) * (ng >> 2)) + (m >> 2)) * G + j % G;
 }
 
 template <int OP> struct ColOpTraits;
@@ -406,7 +409,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
   // the same L2.
   const int b = xcd_contiguous<true>(blockIdx.x, gridDim.x);
   const int inst = b / S.blocks_per_inst;
-  const int tile = col_tile_of(b - inst * S.blocks_per_inst, S.blocks_per_inst);
+  const int tile = col_tile_of<W>(b - inst * S.blocks_per_inst, S.blocks_per_inst);
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
   if (instance_stopped(I)) return;  // uniform over the workgroup
   const int nx = I.nx;
@@ -425,7 +428,8 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
   const int s = tile * W + w;
   const uint32_t o_ld = (uint32_t)(t * nx + s);  // element (t, s); row r adds r nx
   const LdsView lv{lds + w, W};
-  using TS = TwSel<Plan>;
+  // at 2048 points the half table still leaves room for two 4-column tiles per CU
+  using TS = TwSel<Plan, false, true>;
   __shared__ float2 twl[TS::kLds];
   const auto tw = TS::forward(twl, S.tw_col);
   const auto twr = TS::inverse(twl, S.tw_col);
