@@ -269,6 +269,39 @@ def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
     return res
 
 
+def share_2048(dev) -> dict:
+    """One GPU's share of the 720 x 2048^2 workload over 16 GPUs: 45 projections (8
+    distinct projections of that workload's phantom, repeated, noise-free), autotuned,
+    one 20-iteration solve timed after a warm-up."""
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    from paper_2503_20146_amd import PWF, problem_from_geometry
+
+    d = S.tomo_projection_inputs(4, range(0, 720, 90))
+    geo = d["geometry"]
+    t = torch.from_numpy(d["t"]).to(dev)
+    n, iters = 45, 20
+    batch = PWF([problem_from_geometry(geo, t) for _ in range(n)])
+    distinct = [torch.from_numpy(p.astype(np.complex64)).to(dev) for p in d["psi_true"]]
+    f = batch.forward([distinct[j % len(distinct)] for j in range(n)])
+    ys = [f[j] for j in range(n)]
+    tiles = autotune(batch)
+    batch.solve(ys, 2, loss_hist=False)
+    torch.cuda.synchronize()
+    sec = time_events(lambda: batch.solve(ys, iters, loss_hist=False))
+    value = n * iters / sec
+    roof = HBM_PEAK_GBS * 1e9 / (ITER_BYTES_PER_PX * geo.nx * geo.ny)
+    res = {"value": round(value, 1), "unit": "proj-iter/s", "iteration_frac_of_hbm_roofline": round(value / roof, 4),
+           "column_tiles_S1_S3_S5_S7_S9_S11": tiles.get(2048),
+           "config": f"{n} x 2048^2 (8 distinct projections of the 720 x 2048^2 phantom), {iters} iterations"}
+    del batch, ys, f, distinct
+    torch.cuda.empty_cache()
+    print(f"[bench] 2048 share {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def time_events(fn, reps_note=None):
     import torch
     s = torch.cuda.current_stream()
@@ -440,6 +473,8 @@ def main() -> int:
         print(f"[bench] plain {pv:.1f} proj-iter/s", file=sys.stderr, flush=True)
 
     extras = None if args.no_extras else secondary_measurements(batch, ys, out, probs, geo, d_inputs, dev)
+    if extras is not None:
+        extras["share_45x2048"] = share_2048(dev)
 
     cpu = None
     if not args.no_cpu_baseline:
