@@ -31,18 +31,21 @@ __global__ void fbp_ramp_kernel(float2* __restrict__ a, const float* __restrict_
   }
 }
 
-// One 16 x 16 tile of voxels of one slice per workgroup.  Voxel centres X, Z =
-// k + 1/2 - n_out/2; detector index u + nx/2 - 1/2 with u = X cos - Z sin,
-// linear interpolation, 0 outside the detector.  For a chunk of angles the
-// detector samples the tile can reach are staged in LDS first: over the tile u
-// spans 15 (|cos| + |sin|) < 22 pixels, so kFbpSeg samples from one below the
-// smallest corner value cover every voxel's pair (zeros stand for samples
-// outside the detector).  Each staged entry holds a sample and the step to the
-// next one, so that a voxel's interpolation is one LDS read and two FMAs per
-// part, instead of a gather through the vector-memory path once per angle.
-constexpr int kFbpSeg = 32;     // staged samples per angle
+// One 16 (x) by 32 (z) tile of voxels of one slice per workgroup, two voxels
+// per lane (rows z and z + 16).  Voxel centres X, Z = k + 1/2 - n_out/2;
+// detector index u + nx/2 - 1/2 with u = X cos - Z sin, linear interpolation,
+// 0 outside the detector.  For a chunk of angles the detector samples the tile
+// can reach are staged in LDS first: over the tile u spans 15 |cos| + 31 |sin|
+// < 35 pixels, so kFbpSeg samples from one below the smallest corner value
+// cover every voxel's pair (zeros stand for samples outside the detector).
+// Each staged entry holds a sample and the step to the next one, so that a
+// voxel's interpolation is one LDS read and two FMAs per part, instead of a
+// gather through the vector-memory path once per angle; the lane's second
+// voxel shares the per-angle reads and sits 16 sin below the first.
+constexpr int kFbpSeg = 40;     // staged samples per angle
 constexpr int kFbpChunk = 32;   // angles per staged chunk
 constexpr int kFbpThreads = 256;
+constexpr int kFbpTileZ = 32;
 
 __global__ void __launch_bounds__(kFbpThreads) fbp_backproject_kernel(const float2* __restrict__ q, int n_proj, int nx,
                                                                       int ny, int n_pad, const float2* __restrict__ cs,
@@ -51,22 +54,23 @@ __global__ void __launch_bounds__(kFbpThreads) fbp_backproject_kernel(const floa
   __shared__ float2 csl[kFbpChunk];  // cos, sin
   __shared__ float t0l[kFbpChunk];   // detector index of the tile's first voxel minus base
   __shared__ int base[kFbpChunk];
-  const int tiles = n_out / 16;
-  const int y = blockIdx.x / (tiles * tiles);
-  const int tile = blockIdx.x - y * tiles * tiles;
-  const int tx = tile % tiles, tz = tile / tiles;
+  const int tiles_x = n_out / 16, tiles_z = (n_out + kFbpTileZ - 1) / kFbpTileZ;
+  const int y = blockIdx.x / (tiles_x * tiles_z);
+  const int tile = blockIdx.x - y * tiles_x * tiles_z;
+  const int tx = tile % tiles_x, tz = tile / tiles_x;
   const float h = 0.5f * (float)n_out;
-  const float dx = (float)(threadIdx.x & 15), dz = (float)(threadIdx.x >> 4);  // voxel within the tile
-  const float X0 = (float)(tx * 16) + 0.5f - h, Z0 = (float)(tz * 16) + 0.5f - h;
+  const float dx = (float)(threadIdx.x & 15), dz = (float)(threadIdx.x >> 4);  // first voxel within the tile
+  const float X0 = (float)(tx * 16) + 0.5f - h, Z0 = (float)(tz * kFbpTileZ) + 0.5f - h;
   const float off = 0.5f * (float)nx - 0.5f;
-  float2 acc = make_float2(0.f, 0.f);
+  float2 acc0 = make_float2(0.f, 0.f), acc1 = make_float2(0.f, 0.f);
   for (int j0 = 0; j0 < n_proj; j0 += kFbpChunk) {
     const int na = min(kFbpChunk, n_proj - j0);
     __syncthreads();  // the previous chunk's reads are done
     if ((int)threadIdx.x < na) {
       const float2 c = cs[j0 + threadIdx.x];
-      const float ta = X0 * c.x - Z0 * c.y, tb = (X0 + 15.f) * c.x - Z0 * c.y;
-      const float tc = X0 * c.x - (Z0 + 15.f) * c.y, td = (X0 + 15.f) * c.x - (Z0 + 15.f) * c.y;
+      const float xe = X0 + 15.f, ze = Z0 + (float)(kFbpTileZ - 1);
+      const float ta = X0 * c.x - Z0 * c.y, tb = xe * c.x - Z0 * c.y;
+      const float tc = X0 * c.x - ze * c.y, td = xe * c.x - ze * c.y;
       const int b0 = (int)floorf(fminf(fminf(ta, tb), fminf(tc, td)) + off) - 1;
       base[threadIdx.x] = b0;
       // u + nx/2 - 1/2 - base = (ta + off - base) + dx cos - dz sin: small numbers,
@@ -76,33 +80,42 @@ __global__ void __launch_bounds__(kFbpThreads) fbp_backproject_kernel(const floa
     }
     __syncthreads();
     // every load of the chunk is issued before the first LDS write
-    constexpr int kPer = kFbpChunk * kFbpSeg / kFbpThreads;
+    constexpr int kPer = (kFbpChunk * kFbpSeg + kFbpThreads - 1) / kFbpThreads;
     float2 r0[kPer], r1[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = (int)threadIdx.x + u * kFbpThreads;
-      const int a = e / kFbpSeg, i = base[a] + e % kFbpSeg;
+      const int a = e / kFbpSeg, i = base[a < kFbpChunk ? a : 0] + e % kFbpSeg;
       const float2* row = q + ((size_t)(j0 + a) * ny + y) * n_pad;
-      r0[u] = (a < na && i >= 0 && i < nx) ? row[i] : make_float2(0.f, 0.f);
-      r1[u] = (a < na && i + 1 >= 0 && i + 1 < nx) ? row[i + 1] : make_float2(0.f, 0.f);
+      const bool ok = e < kFbpChunk * kFbpSeg && a < na;
+      r0[u] = (ok && i >= 0 && i < nx) ? row[i] : make_float2(0.f, 0.f);
+      r1[u] = (ok && i + 1 >= 0 && i + 1 < nx) ? row[i + 1] : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int u = 0; u < kPer; ++u)
-      seg[threadIdx.x + u * kFbpThreads] = make_float4(r0[u].x, r0[u].y, r1[u].x - r0[u].x, r1[u].y - r0[u].y);
+    for (int u = 0; u < kPer; ++u) {
+      const int e = (int)threadIdx.x + u * kFbpThreads;
+      if (e < kFbpChunk * kFbpSeg)
+        seg[e] = make_float4(r0[u].x, r0[u].y, r1[u].x - r0[u].x, r1[u].y - r0[u].y);
+    }
     __syncthreads();
     for (int a = 0; a < na; ++a) {
       const float2 c = csl[a];
       const float t = fmaf(dx, c.x, fmaf(-dz, c.y, t0l[a]));
-      const float f = floorf(t);
-      const float w = t - f;
-      const int k = min(max((int)f, 0), kFbpSeg - 1);
-      const float4 p = seg[a * kFbpSeg + k];
-      acc.x = fmaf(w, p.z, acc.x + p.x);
-      acc.y = fmaf(w, p.w, acc.y + p.y);
+      const float t2 = fmaf(-16.f, c.y, t);
+      const float f = floorf(t), f2 = floorf(t2);
+      const float w = t - f, w2 = t2 - f2;
+      const int k = min(max((int)f, 0), kFbpSeg - 1), k2 = min(max((int)f2, 0), kFbpSeg - 1);
+      const float4 p = seg[a * kFbpSeg + k], p2 = seg[a * kFbpSeg + k2];
+      acc0.x = fmaf(w, p.z, acc0.x + p.x);
+      acc0.y = fmaf(w, p.w, acc0.y + p.y);
+      acc1.x = fmaf(w2, p2.z, acc1.x + p2.x);
+      acc1.y = fmaf(w2, p2.w, acc1.y + p2.y);
     }
   }
-  const int ix = tx * 16 + (threadIdx.x & 15), iz = tz * 16 + (threadIdx.x >> 4);
-  vol[((size_t)y * n_out + iz) * n_out + ix] = make_float2(acc.x * scale, acc.y * scale);
+  const int ix = tx * 16 + (threadIdx.x & 15), iz = tz * kFbpTileZ + (threadIdx.x >> 4);
+  if (iz < n_out) vol[((size_t)y * n_out + iz) * n_out + ix] = make_float2(acc0.x * scale, acc0.y * scale);
+  if (iz + 16 < n_out)
+    vol[((size_t)y * n_out + iz + 16) * n_out + ix] = make_float2(acc1.x * scale, acc1.y * scale);
 }
 
 hipError_t launch_fbp_pad(const float2* const* psi, int n_proj, int nx, int ny, int n_pad, float2* dst,
@@ -119,8 +132,7 @@ hipError_t launch_fbp_ramp(float2* a, const float* h, int n_pad, size_t rows, hi
 
 hipError_t launch_fbp_backproject(const float2* q, int n_proj, int nx, int ny, int n_pad, const float2* cs, int n_out,
                                   float scale, float2* vol, hipStream_t st) {
-  const int tiles = n_out / 16;
-  const size_t blocks = (size_t)ny * tiles * tiles;
+  const size_t blocks = (size_t)ny * (n_out / 16) * ((n_out + kFbpTileZ - 1) / kFbpTileZ);
   hipLaunchKernelGGL(fbp_backproject_kernel, dim3((unsigned)blocks), dim3(kFbpThreads), 0, st, q, n_proj, nx, ny, n_pad,
                      cs, n_out, scale, vol);
   return hipGetLastError();

@@ -37,19 +37,20 @@ def test_fbp_small_phantom_every_slice():
     assert np.allclose(vol.imag, delta, rtol=0, atol=TOL * np.abs(delta).max() * 10)
 
 
-def test_fbp_off_centre_disk():
+@pytest.mark.parametrize("nx,ny,P,n_out", [(128, 32, 90, 128), (64, 32, 37, 48)])
+def test_fbp_off_centre_disk(nx, ny, P, n_out):
+    """The second case: a partial chunk of angles and a side that is not a multiple of 32."""
     from paper_2503_20146_amd import fbp
     dev = device()
-    nx, ny, P = 128, 32, 90
     angles = np.pi * np.arange(P) / P
     u = np.arange(nx) + 0.5 - nx / 2.0
     sino = np.array([2.0 * np.sqrt(np.maximum(20.0 ** 2 - (u - (25 * math.cos(th) + 10 * math.sin(th))) ** 2, 0))
                      for th in angles])
     psis = [np.repeat(sino[j][None, :], ny, axis=0).astype(np.complex64) * (1 + 0.5j) for j in range(P)]
-    say("fbp off-centre disk")
-    vol = fbp([to_dev(p, dev) for p in psis], angles, 128).cpu().numpy()
-    ref = O.fbp_slice(np.stack([p[0] for p in psis]).astype(np.complex128), angles, 128)
-    for y in (0, 17, 31):
+    say(f"fbp off-centre disk {P} x {ny} x {nx} -> {n_out}^2")
+    vol = fbp([to_dev(p, dev) for p in psis], angles, n_out).cpu().numpy()
+    ref = O.fbp_slice(np.stack([p[0] for p in psis]).astype(np.complex128), angles, n_out)
+    for y in sorted({0, ny // 2 + 1, ny - 1}):
         assert rel(vol[y], ref) <= TOL
 
 
