@@ -1433,15 +1433,25 @@ pwf_status pwf_fbp(const void* const* psi, int32_t n_proj, int32_t nx, int32_t n
   // ramp response: DFT of the band-limited ramp h(0) = 1/4, h(odd n) =
   // -1/(pi^2 n^2) on the circular grid of n_pad samples, over n_pad for the
   // unnormalised inverse transform
-  std::vector<float> H(n_pad);
-  for (int k = 0; k < n_pad; ++k) {
-    double acc = 0.25;
-    for (int n = 1; n <= n_pad / 2; n += 2) {
-      const double hn = -1.0 / (M_PI * M_PI * (double)n * n);
-      const double w = (n == n_pad / 2 ? 1.0 : 2.0) * std::cos(2.0 * M_PI * (double)k * n / n_pad);
-      acc += hn * w;
+  // (an O(n_pad^2) host loop: kept per n_pad for repeated calls)
+  static std::mutex ramp_mu;
+  static std::vector<float> ramp_cached;
+  std::vector<float> H;
+  {
+    std::lock_guard<std::mutex> lk(ramp_mu);
+    if ((int)ramp_cached.size() != n_pad) {
+      ramp_cached.assign(n_pad, 0.f);
+      for (int k = 0; k < n_pad; ++k) {
+        double acc = 0.25;
+        for (int n = 1; n <= n_pad / 2; n += 2) {
+          const double hn = -1.0 / (M_PI * M_PI * (double)n * n);
+          const double w = (n == n_pad / 2 ? 1.0 : 2.0) * std::cos(2.0 * M_PI * (double)k * n / n_pad);
+          acc += hn * w;
+        }
+        ramp_cached[k] = (float)(acc / n_pad);
+      }
     }
-    H[k] = (float)(acc / n_pad);
+    H = ramp_cached;
   }
   std::vector<float2> cs(n_proj);
   for (int j = 0; j < n_proj; ++j) cs[j] = make_float2((float)std::cos(angles_rad[j]), (float)std::sin(angles_rad[j]));
@@ -1619,7 +1629,7 @@ pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int3
     PWF_HIP(pwf::launch_fsc_part((const float2*)(v == 0 ? g1 : g2), part, X, m, st));
     PWF_HIP(pwf::launch_plain_rows(n, -1, X, X, (int)(m / n), twr, st));
     const int planes = dims == 3 ? n : 1;
-    for (int z = 0; z < planes; ++z) PWF_HIP(pwf::launch_plain_cols(n, -1, X + (size_t)z * n * n, n, twc, st));
+    PWF_HIP(pwf::launch_plain_cols(n, -1, X, n, twc, st, planes, (size_t)n * n));
     if (dims == 3) PWF_HIP(pwf::launch_plain_cols(n, -1, X, n * n, twc, st));
   }
   double* out = (double*)(ws + out_off);

@@ -75,7 +75,9 @@ hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st);
 
 hipError_t launch_plain_rows(int nx, int dir, const float2* src, float2* dst, int ny, const float2* tw,
                              hipStream_t st);
-hipError_t launch_plain_cols(int ny, int dir, float2* a, int nx, const float2* tw, hipStream_t st);
+// In-place column FFTs of `planes` [ny][nx] planes plane_stride elements apart.
+hipError_t launch_plain_cols(int ny, int dir, float2* a, int nx, const float2* tw, hipStream_t st, int planes = 1,
+                             size_t plane_stride = 0);
 hipError_t launch_plain_window(float2* a, const Inst* inst, int which, size_t m, hipStream_t st);
 int plain_elementwise_blocks();
 hipError_t launch_plain_elementwise(int op, size_t m, const float2* a, const float2* b, float2* c, float2* out,

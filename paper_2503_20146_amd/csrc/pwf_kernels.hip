@@ -189,12 +189,13 @@ hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st) {
   template <int M> hipError_t launch_col_n(int w, int op, int nblocks, const Sweep& S, hipStream_t st); \
   template <int M> hipError_t plain_rows_n(int dir, const float2* src, float2* dst, int ny,             \
                                            const float2* tw, hipStream_t st);                          \
-  template <int M> hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, hipStream_t st); \
+  template <int M> hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, int planes,   \
+                                           size_t plane_stride, hipStream_t st);                       \
   template <int M> int plan_twiddles_n(int which, float2* out);                                       \
   extern template hipError_t launch_row_n<N>(int, bool, int, const Sweep&, hipStream_t);               \
   extern template hipError_t launch_col_n<N>(int, int, int, const Sweep&, hipStream_t);                \
   extern template hipError_t plain_rows_n<N>(int, const float2*, float2*, int, const float2*, hipStream_t); \
-  extern template hipError_t plain_cols_n<N>(int, float2*, int, const float2*, hipStream_t);           \
+  extern template hipError_t plain_cols_n<N>(int, float2*, int, const float2*, int, size_t, hipStream_t); \
   extern template int plan_twiddles_n<N>(int, float2*);
 PWF_DECLARE_SIDE(128)
 PWF_DECLARE_SIDE(256)
@@ -292,13 +293,15 @@ hipError_t launch_plain_rows(int nx, int dir, const float2* src, float2* dst, in
   }
 }
 
-hipError_t launch_plain_cols(int ny, int dir, float2* a, int nx, const float2* tw, hipStream_t st) {
+hipError_t launch_plain_cols(int ny, int dir, float2* a, int nx, const float2* tw, hipStream_t st, int planes,
+                             size_t plane_stride) {
+  if (planes < 1 || planes > 65535) return hipErrorInvalidValue;
   switch (ny) {
-    case 128: return plain_cols_n<128>(dir, a, nx, tw, st);
-    case 256: return plain_cols_n<256>(dir, a, nx, tw, st);
-    case 512: return plain_cols_n<512>(dir, a, nx, tw, st);
-    case 1024: return plain_cols_n<1024>(dir, a, nx, tw, st);
-    case 2048: return plain_cols_n<2048>(dir, a, nx, tw, st);
+    case 128: return plain_cols_n<128>(dir, a, nx, tw, planes, plane_stride, st);
+    case 256: return plain_cols_n<256>(dir, a, nx, tw, planes, plane_stride, st);
+    case 512: return plain_cols_n<512>(dir, a, nx, tw, planes, plane_stride, st);
+    case 1024: return plain_cols_n<1024>(dir, a, nx, tw, planes, plane_stride, st);
+    case 2048: return plain_cols_n<2048>(dir, a, nx, tw, planes, plane_stride, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -640,10 +640,12 @@ plain_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst, const f
   }
 }
 
-// In-place FFT of every column (natural order).
+// In-place FFT of every column (natural order) of gridDim.y planes
+// plane_stride elements apart.
 template <int NY, int DIR>
 __global__ void __launch_bounds__(ColCfg<NY>::T * ColCfg<NY>::WA, 2)
-plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw) {
+plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw, size_t plane_stride) {
+  a += blockIdx.y * plane_stride;
   using C = ColCfg<NY>;
   using Plan = typename C::Plan;
   constexpr int T = C::T, W = C::WA, E = NY / T;
@@ -734,11 +736,12 @@ hipError_t plain_rows_n(int dir, const float2* src, float2* dst, int ny, const f
 }
 
 template <int N>
-hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, hipStream_t st) {
+hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, int planes, size_t plane_stride,
+                        hipStream_t st) {
   using C = ColCfg<N>;
-  const dim3 grid(nx / C::WA), block(C::T * C::WA);
-  if (dir < 0) hipLaunchKernelGGL((plain_fft_cols<N, -1>), grid, block, 0, st, a, nx, tw);
-  else hipLaunchKernelGGL((plain_fft_cols<N, 1>), grid, block, 0, st, a, nx, tw);
+  const dim3 grid(nx / C::WA, planes), block(C::T * C::WA);
+  if (dir < 0) hipLaunchKernelGGL((plain_fft_cols<N, -1>), grid, block, 0, st, a, nx, tw, plane_stride);
+  else hipLaunchKernelGGL((plain_fft_cols<N, 1>), grid, block, 0, st, a, nx, tw, plane_stride);
   return hipGetLastError();
 }
 
