@@ -40,7 +40,7 @@ ITER_BYTES_PER_PX = sum(SWEEP_BYTES_PER_PX)   # 280
 
 # sources that define the 1024^2 sweep kernels: counters taken before a change to any
 # of them no longer describe the kernels that run
-SWEEP_SOURCES = ["pwf_device.h", "pwf_fft.h", "pwf_kernels.h", "pwf_sweeps.h", "pwf_sweeps_1024.hip"]
+SWEEP_SOURCES = ["pwf_device.h", "pwf_fft.h", "pwf_sweeps.h", "pwf_sweeps_1024.hip"]
 
 
 def kernel_source_hash() -> str:

@@ -806,7 +806,7 @@ pwf_status joint_step(const Launcher& K, const pwf_problem* probs, int n, const 
   const size_t m = (size_t)p.geom.nx * p.geom.ny;
   const int count = p.geom.ny / pwf::row_rows_per_block(p.geom.nx, row_alt(p.geom.nx, pwf::ROW_MUL_T));
   float2* t = (float2*)p.diffuser;
-  PWF_HIP(pwf::launch_joint_update((const float*)(K.ws + K.L.u1max), n, count, (size_t)p.geom.ny,
+  PWF_HIP(pwf::launch_joint_update((float*)(K.ws + K.L.u1max), n, count, (size_t)p.geom.ny,
                                    (const float2*)(K.ws + K.L.u1[0]), field_bytes(p) / sizeof(float2), m, t,
                                    jc.eta_t, (double*)(K.ws + K.L.dsum), K.st));
   PWF_HIP(pwf::launch_maxabs2(t, m, (float*)(K.ws + K.L.maxt2_part), (float*)(K.ws + K.L.maxt2), K.st));

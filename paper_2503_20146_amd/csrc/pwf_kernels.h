@@ -116,8 +116,8 @@ int speckle_sum_blocks();
 hipError_t launch_speckle_sums(const float* img, int nx, int ny, int max_shift, double* partial, double* out,
                                hipStream_t st);
 // Joint diffuser step (see joint_update_kernel): normalisation from the S2
-// maxima, then t <- t - eta_t sum_j G_j / sum_j max|u1_j|^2.
-hipError_t launch_joint_update(const float* u1max, int n, int count, size_t max_stride, const float2* g,
+// maxima (u1max is overwritten), then t <- t - eta_t sum_j G_j / sum_j max|u1_j|^2.
+hipError_t launch_joint_update(float* u1max, int n, int count, size_t max_stride, const float2* g,
                                size_t field_stride, size_t m, float2* t, double eta_t, double* dsum,
                                hipStream_t st);
 int maxabs2_blocks();

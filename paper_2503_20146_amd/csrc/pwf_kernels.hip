@@ -340,22 +340,26 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
 int maxabs2_blocks() { return 256; }
 
 // Joint diffuser refinement: normalisation sum_j max|u1_j|^2 from the S2
-// workgroup maxima (n instances, `count` maxima each, `stride` floats apart),
-// summed in instance order in FP64.
-__global__ void joint_norm_kernel(const float* __restrict__ u1max, int n, int count, size_t stride,
-                                  double* __restrict__ dsum) {
+// workgroup maxima (n instances, `count` maxima each, `stride` floats apart).
+// One workgroup per instance takes its maximum (order-free, so deterministic)
+// and leaves it in the instance's first entry, which the next S2 rewrites;
+// one thread then sums the n maxima in instance order in FP64.
+__global__ void __launch_bounds__(256) joint_max_kernel(float* __restrict__ u1max, int count, size_t stride) {
+  float* p = u1max + (size_t)blockIdx.x * stride;
   __shared__ float red[4];
+  float mx = 0.f;
+  for (int b = threadIdx.x; b < count; b += blockDim.x) mx = fmaxf(mx, p[b]);
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) p[0] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ void joint_norm_kernel(const float* __restrict__ u1max, int n, size_t stride, double* __restrict__ dsum) {
+  if (threadIdx.x != 0) return;
   double acc = 0.0;
-  for (int j = 0; j < n; ++j) {
-    float mx = 0.f;
-    for (int b = threadIdx.x; b < count; b += blockDim.x) mx = fmaxf(mx, u1max[(size_t)j * stride + b]);
-    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-    __syncthreads();
-    if (threadIdx.x == 0) acc += (double)fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *dsum = acc;
+  for (int j = 0; j < n; ++j) acc += (double)u1max[(size_t)j * stride];
+  *dsum = acc;
 }
 
 // t <- t - eta_t sum_j G_j / dsum, G_j = conj(u1_j) a2_j of instance j (fields
@@ -375,10 +379,11 @@ __global__ void joint_update_kernel(const float2* __restrict__ g, int n, size_t 
   }
 }
 
-hipError_t launch_joint_update(const float* u1max, int n, int count, size_t max_stride, const float2* g,
+hipError_t launch_joint_update(float* u1max, int n, int count, size_t max_stride, const float2* g,
                                size_t field_stride, size_t m, float2* t, double eta_t, double* dsum,
                                hipStream_t st) {
-  hipLaunchKernelGGL(joint_norm_kernel, dim3(1), dim3(256), 0, st, u1max, n, count, max_stride, dsum);
+  hipLaunchKernelGGL(joint_max_kernel, dim3(n), dim3(256), 0, st, u1max, count, max_stride);
+  hipLaunchKernelGGL(joint_norm_kernel, dim3(1), dim3(64), 0, st, u1max, n, max_stride, dsum);
   const int blocks = (int)std::min<size_t>((m + 255) / 256, 4096);
   hipLaunchKernelGGL(joint_update_kernel, dim3(blocks), dim3(256), 0, st, g, n, field_stride, m, t, eta_t, dsum);
   return hipGetLastError();
