@@ -102,9 +102,9 @@ __global__ void __launch_bounds__(kFbpThreads) fbp_backproject_kernel(const floa
       const float2 c = csl[a];
       const float t = fmaf(dx, c.x, fmaf(-dz, c.y, t0l[a]));
       const float t2 = fmaf(-16.f, c.y, t);
-      const float f = floorf(t), f2 = floorf(t2);
-      const float w = t - f, w2 = t2 - f2;
-      const int k = min(max((int)f, 0), kFbpSeg - 1), k2 = min(max((int)f2, 0), kFbpSeg - 1);
+      // t, t2 >= 1 by the choice of base (up to rounding), so truncation is the floor
+      const float w = __builtin_amdgcn_fractf(t), w2 = __builtin_amdgcn_fractf(t2);
+      const int k = min(max((int)t, 0), kFbpSeg - 1), k2 = min(max((int)t2, 0), kFbpSeg - 1);
       const float4 p = seg[a * kFbpSeg + k], p2 = seg[a * kFbpSeg + k2];
       acc0.x = fmaf(w, p.z, acc0.x + p.x);
       acc0.y = fmaf(w, p.w, acc0.y + p.y);
