@@ -355,11 +355,19 @@ __global__ void __launch_bounds__(256) joint_max_kernel(float* __restrict__ u1ma
   if (threadIdx.x == 0) p[0] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
-__global__ void joint_norm_kernel(const float* __restrict__ u1max, int n, size_t stride, double* __restrict__ dsum) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(256) joint_norm_kernel(const float* __restrict__ u1max, int n, size_t stride,
+                                                         double* __restrict__ dsum) {
+  __shared__ float v[256];
   double acc = 0.0;
-  for (int j = 0; j < n; ++j) acc += (double)u1max[(size_t)j * stride];
-  *dsum = acc;
+  for (int j0 = 0; j0 < n; j0 += 256) {  // maxima gathered in parallel, summed in order
+    const int m = min(256, n - j0);
+    if ((int)threadIdx.x < m) v[threadIdx.x] = u1max[(size_t)(j0 + threadIdx.x) * stride];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int j = 0; j < m; ++j) acc += (double)v[j];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dsum = acc;
 }
 
 // t <- t - eta_t sum_j G_j / dsum, G_j = conj(u1_j) a2_j of instance j (fields
@@ -383,7 +391,7 @@ hipError_t launch_joint_update(float* u1max, int n, int count, size_t max_stride
                                size_t field_stride, size_t m, float2* t, double eta_t, double* dsum,
                                hipStream_t st) {
   hipLaunchKernelGGL(joint_max_kernel, dim3(n), dim3(256), 0, st, u1max, count, max_stride);
-  hipLaunchKernelGGL(joint_norm_kernel, dim3(1), dim3(64), 0, st, u1max, n, max_stride, dsum);
+  hipLaunchKernelGGL(joint_norm_kernel, dim3(1), dim3(256), 0, st, u1max, n, max_stride, dsum);
   const int blocks = (int)std::min<size_t>((m + 255) / 256, 4096);
   hipLaunchKernelGGL(joint_update_kernel, dim3(blocks), dim3(256), 0, st, g, n, field_stride, m, t, eta_t, dsum);
   return hipGetLastError();
