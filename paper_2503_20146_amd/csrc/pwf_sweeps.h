@@ -458,19 +458,6 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
     // neighbour position mirror_col(s), inside this tile.
     const int wm = mirror_col(s) - tile * W;
     const LdsView lm{lds + wm, W};
-    // Psi(k), z(k) and the 1 - STF factors of this lane's elements, issued
-    // before the exchange of G so that their latency overlaps it (behind the
-    // stores of the update, the compiler could not move them up).
-    float2 pk[E], zp[OP == COL_NESTEROV ? E : 1];
-    float gyv[E];
-    static_for<0, E>([&](auto ee) {
-      constexpr int e = decltype(ee)::value;
-      const int ky = t + T * (e / RL) + (e % RL) * ML;
-      const uint32_t gi = o_ld + (uint32_t)((ky - t) * nx);
-      pk[e] = gld(I.psi_hat, gi);
-      if constexpr (OP == COL_NESTEROV) zp[e] = gld(I.z_hat, gi);
-      gyv[e] = gldf(I.gy, ky);
-    });
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       lv.at(t + T * (e / RL) + (e % RL) * ML) = v[e];
@@ -486,34 +473,58 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
       v[e] = make_float2(a * v[e].x + b * gm.x, a * v[e].y - b * gm.y);
     });
     __syncthreads();
-    static_for<0, E>([&](auto ee) {
+    static_for<0, E>([&](auto ee) {  // Psi to LDS: each lane needs Psi(k) and Psi(-k)
       constexpr int e = decltype(ee)::value;
       const int ky = t + T * (e / RL) + (e % RL) * ML;
-      lv.at(ky) = pk[e];
+      lv.at(ky) = gld(I.psi_hat, o_ld + (uint32_t)((ky - t) * nx));
     });
     __syncthreads();
     const float bf = (OP == COL_NESTEROV) ? (float)S.beta[I.k0 + S.iter] : 0.f;
     const float gxv = gldf(I.gx, kx);
     const uint32_t o_up = opaque(o_ld);
-    static_for<0, E>([&](auto ee) {
-      constexpr int e = decltype(ee)::value;
-      const int ky = t + T * (e / RL) + (e % RL) * ML;
-      const float2 pm = lm.at((NY - ky) & (NY - 1));
-      const float g2 = gxv + (1.f - gxv) * gyv[e];   // 1 - STFx STFy without cancellation
-      // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
-      const float2 reg = make_float2(I.alpha_c1 * pk[e].x + I.alpha_c2 * pm.x, I.alpha_c1 * pk[e].y - I.alpha_c2 * pm.y);
-      const float2 d = make_float2(v[e].x + g2 * reg.x, v[e].y + g2 * reg.y);
-      if constexpr (OP == COL_NESTEROV) {
-        const uint32_t gi = o_up + (uint32_t)((ky - t) * nx);
-        const float2 zo = zp[OP == COL_NESTEROV ? e : 0];
-        const float2 z = make_float2(pk[e].x - I.eta * d.x, pk[e].y - I.eta * d.y);
-        const float2 pn = make_float2(z.x + bf * (z.x - zo.x), z.y + bf * (z.y - zo.y));
-        gst(I.z_hat, gi, z);
-        gst(I.psi_hat, gi, pn);
-        v[e] = cscale(pn, I.inv_m);
-      } else {
-        v[e] = cscale(d, I.inv_m);
-      }
+    // The update runs in batches of NB elements; z and the STF factors of the
+    // next batch are loaded before this batch's stores (behind them the
+    // compiler could not move the loads up, and one memory round trip per
+    // element followed), two batches in registers at a time: the sweep then
+    // fits 128 registers and two 8-column workgroups per CU.
+    constexpr int NB = 4;
+    static_assert(E % NB == 0, "update batches");
+    float2 zb[2][NB];
+    float gb[2][NB];
+    auto load_batch = [&](auto bb, int slot) {
+      constexpr int b0 = decltype(bb)::value * NB;
+      static_for<0, NB>([&](auto uu) {
+        constexpr int e = b0 + decltype(uu)::value;
+        const int ky = t + T * (e / RL) + (e % RL) * ML;
+        if constexpr (OP == COL_NESTEROV) zb[slot][decltype(uu)::value] = gld(I.z_hat, o_up + (uint32_t)((ky - t) * nx));
+        gb[slot][decltype(uu)::value] = gldf(I.gy, ky);
+      });
+    };
+    load_batch(std::integral_constant<int, 0>{}, 0);
+    static_for<0, E / NB>([&](auto bb) {
+      constexpr int b = decltype(bb)::value;
+      if constexpr (b + 1 < E / NB) load_batch(std::integral_constant<int, b + 1>{}, (b + 1) & 1);
+      static_for<0, NB>([&](auto uu) {
+        constexpr int u = decltype(uu)::value, e = b * NB + u;
+        const int ky = t + T * (e / RL) + (e % RL) * ML;
+        const float2 pk = lv.at(ky);
+        const float2 pm = lm.at((NY - ky) & (NY - 1));
+        const float g2 = gxv + (1.f - gxv) * gb[b & 1][u];   // 1 - STFx STFy without cancellation
+        // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
+        const float2 reg = make_float2(I.alpha_c1 * pk.x + I.alpha_c2 * pm.x, I.alpha_c1 * pk.y - I.alpha_c2 * pm.y);
+        const float2 d = make_float2(v[e].x + g2 * reg.x, v[e].y + g2 * reg.y);
+        if constexpr (OP == COL_NESTEROV) {
+          const uint32_t gi = o_up + (uint32_t)((ky - t) * nx);
+          const float2 zo = zb[b & 1][u];
+          const float2 z = make_float2(pk.x - I.eta * d.x, pk.y - I.eta * d.y);
+          const float2 pn = make_float2(z.x + bf * (z.x - zo.x), z.y + bf * (z.y - zo.y));
+          gst(I.z_hat, gi, z);
+          gst(I.psi_hat, gi, pn);
+          v[e] = cscale(pn, I.inv_m);
+        } else {
+          v[e] = cscale(d, I.inv_m);
+        }
+      });
     });
     __syncthreads();
   } else {
