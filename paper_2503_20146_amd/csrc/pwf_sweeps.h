@@ -227,6 +227,33 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   const bool corr_sum = corr && S.iter > 0;
   double c_re = 0.0, c_im = 0.0, n_new = 0.0, n_old = 0.0;
   const uint32_t rb_rs = opaque(rbase);
+  if constexpr (OP == ROW_MUL_CONJ_T) {
+    if (I.u1) {
+      // Joint diffuser mode: u1 <- conj(u1) a2 with a2 = this back-propagated
+      // field (dL/dt*).  In batches of four elements, each batch's u1 loads
+      // issued before the previous batch's stores: behind the stores the
+      // compiler would load one element per memory round trip.
+      constexpr int NB = 4;
+      static_assert(E % NB == 0, "joint batches");
+      float2 ub[2][NB];
+      auto load_u1 = [&](auto bb) {
+        constexpr int b = decltype(bb)::value;
+        static_for<0, NB>([&](auto uu) {
+          constexpr int u = decltype(uu)::value, e = b * NB + u;
+          ub[b & 1][u] = gld(I.u1, rb_rs + t + T * (e / R1) + (e % R1) * M1);
+        });
+      };
+      load_u1(std::integral_constant<int, 0>{});
+      static_for<0, E / NB>([&](auto bb) {
+        constexpr int b = decltype(bb)::value;
+        if constexpr (b + 1 < E / NB) load_u1(std::integral_constant<int, b + 1>{});
+        static_for<0, NB>([&](auto uu) {
+          constexpr int u = decltype(uu)::value, e = b * NB + u;
+          gst(I.u1, rb_rs + t + T * (e / R1) + (e % R1) * M1, cmulc(v[e], ub[b & 1][u]));
+        });
+      });
+    }
+  }
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
@@ -254,10 +281,6 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
         }
         v[e] = cmul(v[e], side[e]);
       } else if constexpr (OP == ROW_MUL_CONJ_T) {
-        if (I.u1) {  // joint diffuser mode: dL/dt* = conj(u1) a2, a2 = this back-propagated field
-          const float2 u = gld(I.u1, idx);
-          gst(I.u1, idx, cmulc(v[e], u));
-        }
         v[e] = cmulc(v[e], side[e]);
       } else if constexpr (OP == ROW_INTENSITY) {
         if (I.v) gst(I.v, idx, v[e]);
