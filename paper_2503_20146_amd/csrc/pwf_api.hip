@@ -425,7 +425,7 @@ struct Launcher {
   pwf_status row(int op, int iter = 0) const {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
-      const bool alt = row_alt(c.nx, op);
+      const bool alt = row_alt(c.nx, op == pwf::ROW_PSI_UPDATE_CORR ? (int)pwf::ROW_PSI_UPDATE : op);
       S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx, alt);
       PWF_HIP(pwf::launch_row(c.nx, op, alt, S.blocks_per_inst * c.count, S, st));
     }
@@ -823,7 +823,7 @@ pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, st
   PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.status, 16, K.st));
   PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.W[0], K.L.v[0] - K.L.W[0], K.st));
   for (int k = 0; k < iters; ++k) {
-    PWF_TRY(K.row(pwf::ROW_PSI_UPDATE, k));
+    PWF_TRY(K.row(K.corr_tol > 0.0 ? pwf::ROW_PSI_UPDATE_CORR : pwf::ROW_PSI_UPDATE, k));
     PWF_TRY(K.col(pwf::COL_CHIRP1, k));
     PWF_TRY(K.row(pwf::ROW_MUL_T, k));
     PWF_TRY(K.col(pwf::COL_CHIRP2, k));

@@ -22,6 +22,7 @@ enum RowOp {
   ROW_REAL_FFT,        // W = FFT_x(y)
   ROW_CPLX_FFT,        // W = FFT_x(psi_src) (psi_src null: zeros)
   ROW_IFFT_OUT,        // out = IFFT_x(W)
+  ROW_PSI_UPDATE_CORR, // S0 with the stopping rule's sums (runs with the plan of ROW_PSI_UPDATE)
 };
 
 // Row sweeps of the iteration (S0, S2, S4, S6, S8, S10) are compiled with both

@@ -38,6 +38,7 @@ template <int OP> struct RowOpTraits;
 #define PWF_ROW_TRAIT(op, in_freq, out_freq) \
   template <> struct RowOpTraits<op> { static constexpr bool kInFreq = in_freq, kOutFreq = out_freq; };
 PWF_ROW_TRAIT(ROW_PSI_UPDATE, true, true)
+PWF_ROW_TRAIT(ROW_PSI_UPDATE_CORR, true, true)
 PWF_ROW_TRAIT(ROW_START, false, true)
 PWF_ROW_TRAIT(ROW_MUL_T, true, true)
 PWF_ROW_TRAIT(ROW_MUL_CONJ_T, true, true)
@@ -130,7 +131,7 @@ __device__ __forceinline__ int xcd_contiguous(int b, int g) {
 
 // Waves per SIMD the compiler must leave room for (launch bound).
 template <int NX, int OP> constexpr int row_min_waves() {
-  return OP == ROW_PSI_UPDATE ? 3 : OP == ROW_GRAD ? (NX >= 2048 ? 2 : 3) : 4;
+  return (OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR) ? 3 : OP == ROW_GRAD ? (NX >= 2048 ? 2 : 3) : 4;
 }
 
 template <int NX, bool ALT>
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   const LdsView lv{lds + rw * lds_len(NX), 1};
   // The update sweep stages half of w_N^m: the 4 KB saved let a fourth
   // workgroup of the 16x16x4 plan fit in a CU's LDS (its registers allow it).
-  using TS = TwSel<Plan, OP == ROW_PSI_UPDATE>;
+  using TS = TwSel<Plan, OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR>;
   __shared__ float2 twl[TS::kLds];
   const float2* twg = ALT ? S.tw_alt : S.tw_row;
   const auto tw = TS::forward(twl, twg);
@@ -223,7 +224,8 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   float u1max = 0.f;  // joint diffuser mode (S2): max |u1|^2 over this lane's elements
   if constexpr (OP == ROW_GRAD) inv_maxt2 = I.grad_mul > 0.f ? I.grad_mul : 1.0f / *I.maxt2;
   // stopping correlation of exp(psi) with the previous iterate (FP64 sums)
-  const bool corr = (OP == ROW_PSI_UPDATE) && I.corr_partial != nullptr;
+  constexpr bool PSI = OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR;
+  const bool corr = PSI && I.corr_partial != nullptr;
   const bool corr_sum = corr && S.iter > 0;
   double c_re = 0.0, c_im = 0.0, n_new = 0.0, n_old = 0.0;
   const uint32_t rb_rs = opaque(rbase);
@@ -254,16 +256,38 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
       });
     }
   }
+  // With the stopping rule the previous x is read where the new one is
+  // stored: the S0 variant for it loads it four elements at a time, the next
+  // batch before this batch's stores (behind them the compiler would load one
+  // element per memory round trip).  The fixed-iteration S0 keeps the
+  // registers this costs.
+  constexpr bool XB = OP == ROW_PSI_UPDATE_CORR;
+  constexpr int NBX = 4;
+  static_assert(!XB || E % NBX == 0, "stopping-rule batches");
+  float2 xb[XB ? 2 : 1][NBX];
+  auto load_x = [&](auto bb) {
+    constexpr int b = decltype(bb)::value;
+    static_for<0, NBX>([&](auto uu) {
+      constexpr int u = decltype(uu)::value, e = b * NBX + u;
+      xb[XB ? b & 1 : 0][u] = gld(I.x, rb_rs + t + T * (e / R1) + (e % R1) * M1);
+    });
+  };
+  if constexpr (XB) {
+    if (corr_sum) load_x(std::integral_constant<int, 0>{});
+  }
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
       constexpr int e = c * R1 + q;
       const uint32_t idx = rb_rs + t + T * c + q * M1;
-      if constexpr (OP == ROW_PSI_UPDATE) {
+      if constexpr (PSI) {
+        if constexpr (XB) {
+          if (corr_sum && e % NBX == 0 && e / NBX + 1 < E / NBX) load_x(std::integral_constant<int, e / NBX + 1>{});
+        }
         if (corr) gst(I.out, idx, v[e]);  // psi of this iterate, kept in case the stop fires
         const float2 xn = cexp_f(v[e]);
         if (corr_sum) {
-          const float2 xo = gld(I.x, idx);
+          const float2 xo = XB ? xb[XB ? (e / NBX) & 1 : 0][e % NBX] : gld(I.x, idx);
           c_re += (double)xn.x * xo.x + (double)xn.y * xo.y;
           c_im += (double)xn.x * xo.y - (double)xn.y * xo.x;
           n_new += (double)xn.x * xn.x + (double)xn.y * xn.y;
@@ -328,7 +352,7 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
     }
   }
 
-  if constexpr (OP == ROW_PSI_UPDATE) {
+  if constexpr (PSI) {
     if (corr_sum) {
       // deterministic block reduction of the four sums -> corr_partial[blk]
       __shared__ double cred[4][RW * T / 64 + 1];
@@ -728,7 +752,7 @@ hipError_t launch_row_n(int op, bool alt, int nblocks, const Sweep& S, hipStream
 #define PWF_TUNABLE(o) \
   case o: return alt ? launch_row_one<N, o, true>(nblocks, S, st) : launch_row_one<N, o, false>(nblocks, S, st);
 #define PWF_FIXED(o) case o: return launch_row_one<N, o, row_alt_default<N>(o)>(nblocks, S, st);
-    PWF_TUNABLE(ROW_PSI_UPDATE) PWF_TUNABLE(ROW_MUL_T) PWF_TUNABLE(ROW_MUL_CONJ_T) PWF_TUNABLE(ROW_INTENSITY)
+    PWF_TUNABLE(ROW_PSI_UPDATE) PWF_TUNABLE(ROW_PSI_UPDATE_CORR) PWF_TUNABLE(ROW_MUL_T) PWF_TUNABLE(ROW_MUL_CONJ_T) PWF_TUNABLE(ROW_INTENSITY)
     PWF_TUNABLE(ROW_BACKBLUR) PWF_TUNABLE(ROW_GRAD)
     PWF_FIXED(ROW_START) PWF_FIXED(ROW_FORWARD_OUT) PWF_FIXED(ROW_REAL_FFT) PWF_FIXED(ROW_CPLX_FFT)
     PWF_FIXED(ROW_IFFT_OUT)
