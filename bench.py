@@ -302,6 +302,45 @@ def share_2048(dev) -> dict:
     return res
 
 
+def uneven_batch(dev) -> dict:
+    """The uneven ROI batch (24 x 512^2, 32 x 1024^2, 8 x 2048^2, IPSF sigma per instance):
+    one instance's fields per size class, repeated, noise-free; autotuned; one 50-iteration
+    solve timed after a warm-up."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    from paper_2503_20146_amd import PWF, problem_from_geometry
+
+    specs = S.roi_batch_specs()
+    first = {}
+    for i, (side, sigma) in enumerate(specs):
+        if side not in first:
+            first[side] = S.instance_inputs(3, side, instance=i, sigma_px=sigma)
+    diffusers = {side: torch.from_numpy(inp["t"]).to(dev) for side, inp in first.items()}
+    batch = PWF([problem_from_geometry(dataclasses.replace(first[side]["geometry"], sigma_x_px=sigma, sigma_y_px=sigma),
+                                       diffusers[side]) for side, sigma in specs])
+    psis = {side: torch.from_numpy(inp["psi_true"].astype(np.complex64)).to(dev) for side, inp in first.items()}
+    f = batch.forward([psis[side] for side, _ in specs])
+    ys = [f[j] for j in range(len(specs))]
+    autotune(batch)
+    iters = 50
+    batch.solve(ys, 2, loss_hist=False)
+    torch.cuda.synchronize()
+    sec = time_events(lambda: batch.solve(ys, iters, loss_hist=False))
+    px = sum(side * side for side, _ in specs)
+    frac = px * iters / sec * ITER_BYTES_PER_PX / (HBM_PEAK_GBS * 1e9)
+    res = {"iteration_ms": round(sec / iters * 1e3, 3), "iteration_frac_of_hbm_roofline": round(frac, 4),
+           "config": "24 x 512^2 + 32 x 1024^2 + 8 x 2048^2 (one instance's inputs per size class, repeated), "
+                     f"{iters} iterations, size classes on parallel streams"}
+    del batch, ys, f, psis, diffusers
+    torch.cuda.empty_cache()
+    print(f"[bench] uneven batch {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def time_events(fn, reps_note=None):
     import torch
     s = torch.cuda.current_stream()
@@ -475,6 +514,7 @@ def main() -> int:
     extras = None if args.no_extras else secondary_measurements(batch, ys, out, probs, geo, d_inputs, dev)
     if extras is not None:
         extras["share_45x2048"] = share_2048(dev)
+        extras["uneven_roi_batch"] = uneven_batch(dev)
 
     cpu = None
     if not args.no_cpu_baseline:

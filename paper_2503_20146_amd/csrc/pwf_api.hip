@@ -62,6 +62,10 @@ struct Context {
   double* beta = nullptr;      // momentum table
   hipStream_t side = nullptr;  // internal stream for graph launches
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // streams that run the size classes of an uneven batch side by side
+  static constexpr int kForks = 3;
+  hipStream_t fork[kForks] = {};
+  hipEvent_t fork_ev[kForks + 1] = {};
   std::map<GraphKey, hipGraphExec_t> graphs;
   // pinned staging for descriptor uploads (ring of slots)
   static constexpr int kSlots = 4;
@@ -178,6 +182,8 @@ pwf_status context_for_current(Context** out) {
     PWF_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
     PWF_HIP(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
     PWF_HIP(hipEventCreateWithFlags(&c.ev_out, hipEventDisableTiming));
+    for (int i = 0; i < Context::kForks; ++i) PWF_HIP(hipStreamCreateWithFlags(&c.fork[i], hipStreamNonBlocking));
+    for (int i = 0; i <= Context::kForks; ++i) PWF_HIP(hipEventCreateWithFlags(&c.fork_ev[i], hipEventDisableTiming));
     for (int i = 0; i < Context::kSlots; ++i) PWF_HIP(hipEventCreateWithFlags(&c.stage_ev[i], hipEventDisableTiming));
     c.ready = true;
   }
@@ -822,22 +828,49 @@ pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, st
   PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
   PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.status, 16, K.st));
   PWF_HIP(pwf::launch_fill_zero(K.ws + K.L.W[0], K.L.v[0] - K.L.W[0], K.st));
-  for (int k = 0; k < iters; ++k) {
-    PWF_TRY(K.row(K.corr_tol > 0.0 ? pwf::ROW_PSI_UPDATE_CORR : pwf::ROW_PSI_UPDATE, k));
-    PWF_TRY(K.col(pwf::COL_CHIRP1, k));
-    PWF_TRY(K.row(pwf::ROW_MUL_T, k));
-    PWF_TRY(K.col(pwf::COL_CHIRP2, k));
-    PWF_TRY(K.row(pwf::ROW_INTENSITY, k));
-    PWF_TRY(K.col(pwf::COL_BLUR_LOSS, k));
-    PWF_TRY(K.row(pwf::ROW_BACKBLUR, k));
-    PWF_TRY(K.col(pwf::COL_CHIRP2_CONJ, k));
-    PWF_TRY(K.row(pwf::ROW_MUL_CONJ_T, k));
-    PWF_TRY(K.col(pwf::COL_CHIRP1_CONJ, k));
-    PWF_TRY(K.row(pwf::ROW_GRAD, k));
-    PWF_TRY(K.col(pwf::COL_NESTEROV, k));
-    if (jc.on) PWF_TRY(joint_step(K, probs, n, jc));
+  const int s0 = K.corr_tol > 0.0 ? pwf::ROW_PSI_UPDATE_CORR : pwf::ROW_PSI_UPDATE;
+  auto iterate = [&](const Launcher& Q) -> pwf_status {
+    for (int k = 0; k < iters; ++k) {
+      PWF_TRY(Q.row(s0, k));
+      PWF_TRY(Q.col(pwf::COL_CHIRP1, k));
+      PWF_TRY(Q.row(pwf::ROW_MUL_T, k));
+      PWF_TRY(Q.col(pwf::COL_CHIRP2, k));
+      PWF_TRY(Q.row(pwf::ROW_INTENSITY, k));
+      PWF_TRY(Q.col(pwf::COL_BLUR_LOSS, k));
+      PWF_TRY(Q.row(pwf::ROW_BACKBLUR, k));
+      PWF_TRY(Q.col(pwf::COL_CHIRP2_CONJ, k));
+      PWF_TRY(Q.row(pwf::ROW_MUL_CONJ_T, k));
+      PWF_TRY(Q.col(pwf::COL_CHIRP1_CONJ, k));
+      PWF_TRY(Q.row(pwf::ROW_GRAD, k));
+      PWF_TRY(Q.col(pwf::COL_NESTEROV, k));
+      if (jc.on) PWF_TRY(joint_step(Q, probs, n, jc));
+    }
+    PWF_TRY(Q.row(pwf::ROW_IFFT_OUT, iters));
+    return PWF_OK;
+  };
+  const int nc = (int)K.B.classes.size();
+  if (nc <= 1 || jc.on) return iterate(K);
+  // The size classes of an uneven batch are independent problems: their
+  // iterations run on parallel streams (classes dealt round-robin), forked
+  // from and joined back into K.st with events, so that a small class's short
+  // launches overlap the large ones instead of alternating with them.
+  const int ns = std::min(nc, Context::kForks + 1);
+  std::vector<Batch> subs(ns);
+  for (int c = 0; c < nc; ++c) {
+    subs[c % ns].order = K.B.order;
+    subs[c % ns].classes.push_back(K.B.classes[c]);
   }
-  PWF_TRY(K.row(pwf::ROW_IFFT_OUT, iters));
+  PWF_HIP(hipEventRecord(K.ctx.fork_ev[0], K.st));
+  for (int j = 1; j < ns; ++j) PWF_HIP(hipStreamWaitEvent(K.ctx.fork[j - 1], K.ctx.fork_ev[0], 0));
+  for (int j = 0; j < ns; ++j) {
+    Launcher Kj{K.ctx, K.ws, K.L, subs[j], j == 0 ? K.st : K.ctx.fork[j - 1]};
+    Kj.corr_tol = K.corr_tol;
+    PWF_TRY(iterate(Kj));
+  }
+  for (int j = 1; j < ns; ++j) {
+    PWF_HIP(hipEventRecord(K.ctx.fork_ev[j], K.ctx.fork[j - 1]));
+    PWF_HIP(hipStreamWaitEvent(K.st, K.ctx.fork_ev[j], 0));
+  }
   return PWF_OK;
 }
 
@@ -1683,6 +1716,10 @@ void pwf_finalize(void) {
       if (c.stage_ev[i]) hipEventDestroy(c.stage_ev[i]);
       c.stage_ev[i] = nullptr;
     }
+    for (hipStream_t& f : c.fork)
+      if (f) hipStreamDestroy(f);
+    for (hipEvent_t& e : c.fork_ev)
+      if (e) hipEventDestroy(e);
     if (c.ev_in) hipEventDestroy(c.ev_in);
     if (c.ev_out) hipEventDestroy(c.ev_out);
     if (c.side) hipStreamDestroy(c.side);
