@@ -336,6 +336,39 @@ def test_graph_replay_equals_eager():
         assert torch.equal(hg, he)
 
 
+def test_uneven_batch_graph_replays_equal_eager():
+    """Size classes run on parallel streams (branches of the captured graph): replays of the
+    cached graph, with eager work and synchronisations between them, equal the eager solve."""
+    import torch
+    from paper_2503_20146_amd import set_graph_mode
+    dev = device()
+    say("uneven batch: graph replays vs eager")
+    specs = [(128, 128, 1.0), (256, 256, 1.3), (512, 512, 0.8), (128, 128, 1.6), (256, 256, 0.6)]
+    probs, ys = [], []
+    for k, (ny, nx, sig) in enumerate(specs):
+        rng = np.random.default_rng(300 + k)
+        geo = S.Geometry(ny=ny, nx=nx, sigma_x_px=sig, sigma_y_px=sig)
+        t = S.diffuser(rng, ny, nx)
+        prob = O.make_problem(t, geo)
+        f, _, _ = O.physical_model(S.phase_object(rng, ny, nx, 4.0, 2.0), prob)
+        probs.append(gpu_problem(geo, t, dev))
+        ys.append(to_dev(S.poisson_intensity(f, (9, k)), dev))
+    batch = _pwf(probs)
+    set_graph_mode(False)
+    try:
+        eager, he = batch.solve(ys, 7)
+    finally:
+        set_graph_mode(True)
+    for _ in range(3):
+        g, hg = batch.solve(ys, 7)
+        torch.cuda.synchronize()
+        _ = batch.forward([g[0], g[1], g[2], g[3], g[4]])
+        torch.cuda.synchronize()
+        for i in range(len(specs)):
+            assert torch.equal(g[i], eager[i]), i
+            assert torch.equal(hg[i], he[i]), i
+
+
 def test_repeatable_bitwise():
     import torch
     dev = device()
