@@ -56,7 +56,7 @@ def test_autograd_small_matches_oracle_and_fd():
     loss.sum().backward()
     grad = p.grad[0].cpu().numpy()
     l_ref, g_ref, _ = O.gradient(psi.astype(np.complex128), y, prob)
-    assert abs(float(loss[0]) - l_ref) <= 1e-5 * l_ref
+    assert abs(float(loss[0].detach()) - l_ref) <= 1e-5 * l_ref
     assert rel(grad, 4 * np.max(np.abs(prob.t) ** 2) * g_ref) <= GRAD_TOL
     rng = np.random.default_rng(11)
     pix = [tuple(int(v) for v in divmod(int(k), 128)) for k in rng.choice(128 * 128, 8, replace=False)]
@@ -107,7 +107,7 @@ def test_autograd_2048_projection_fd_and_oracle():
     y0 = ys[0].cpu().numpy()
     l_ref, g_ref, _ = O.gradient(psis[0].astype(np.complex128), y0, prob)
     f_ref, _, _ = O.physical_model(psis[0].astype(np.complex128), prob)
-    assert abs(float(loss[0]) - l_ref) <= loss_tolerance(y0, f_ref) * l_ref
+    assert abs(float(loss[0].detach()) - l_ref) <= loss_tolerance(y0, f_ref) * l_ref
     r = rel(grad0, 4 * np.max(np.abs(prob.t) ** 2) * g_ref)
     say(f"autograd 2048^2: gradient rel-L2 {r:.2e}")
     assert r <= GRAD_TOL
