@@ -93,8 +93,13 @@ typedef struct {
 /* Iterate of Algorithm S1 for pwf_step, in caller memory (all device,
  * complex64 [ny][nx]):
  *   psi      extrapolated iterate psi in real space (read/written)
- *   psi_hat  spectrum of psi in the library's frequency layout
- *   z_hat    spectrum of the gradient-step iterate z, same layout
+ *   psi_hat, z_hat
+ *            spectra of the last two gradient-step iterates z_k and z_{k-1}
+ *            in the library's frequency layout: z_k is in psi_hat for even k
+ *            and in z_hat for odd k, and pwf_step overwrites z_{k-1} with
+ *            z_{k+1}.  The spectrum of psi_k, z_k + beta_{k-1} (z_k - z_{k-1}),
+ *            is formed from them when needed; pwf_state_init sets both to the
+ *            spectrum of psi_0 (z_{-1} = z_0 = psi_0).
  *   y_hat    spectrum of the measured speckle y, same layout
  *   k        iterations done so far (host value, advanced by pwf_step)
  * The frequency layout is row-major [ky][s]: column kx of the 2-D DFT sits at

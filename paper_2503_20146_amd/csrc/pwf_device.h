@@ -26,8 +26,8 @@ struct Inst {
   float2* x;            // sample transmission x = exp(psi), saved for the gradient
   const float2* psi_src;// real-space psi that a forward pass starts from
   float2* psi;          // real-space psi written by a state initialisation
-  float2* psi_hat;      // spectrum of the extrapolated iterate psi
-  float2* z_hat;        // spectrum of the gradient-step iterate z
+  float2* psi_hat;      // spectrum of psi (one-shot calls), or of z_k / z_{k-1} (iterations, k even / odd)
+  float2* z_hat;        // spectrum of z_{k-1} / z_k (iterations, k even / odd)
   float2* y_hat;        // spectrum of the measured speckle
   const float* y;       // measured speckle (real space, float32)
   const float2* t;      // diffuser transmission

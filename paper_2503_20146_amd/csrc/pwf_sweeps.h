@@ -18,7 +18,7 @@
 //   S9 C  x conj Q_L1                                     (FreePropagation -L1)
 //   S10 R g = x* b / max|t|^2
 //   S11 C direction d (Preconditioner + Regularizer) and the Nesterov step on
-//         the spectra of psi and z; IFFT towards the next S0.
+//         the spectra of z_k, z_{k-1}; IFFT of psi_{k+1} towards the next S0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -432,12 +432,15 @@ __device__ __noinline__ float2 transfer_direct(double chirp_rev, double s_coef, 
   return transfer(chirp_rev, s_coef, 0, fx, fy, false);
 }
 
-// Waves per SIMD the column sweeps must leave room for: 3 for the update
+// Waves per SIMD the column sweeps must leave room for: 4 (128 registers)
+// for the Nesterov sweep where the LDS lets four waves per SIMD in (two
+// 512-thread or four 256-thread workgroups per CU), else 3 for the update
 // sweeps (168 registers; at 256 points the 16-column tile would spill), 2 for
 // the others, which need fewer registers than that anyway (a 4-wave bound,
 // 128 registers, makes the chirp sweeps spill).
 template <int NY, int W, int OP> constexpr int col_min_waves() {
-  return (OP == COL_NESTEROV || OP == COL_DIRECTION) && !(NY == 256 && W == 16) ? 3 : 2;
+  return OP == COL_NESTEROV && (NY == 512 || (NY > 512 && ColCfg<NY>::T * W == 512)) ? 4
+         : (OP == COL_NESTEROV || OP == COL_DIRECTION) && !(NY == 256 && W == 16) ? 3 : 2;
 }
 
 template <int NY, int W, int OP>
@@ -520,13 +523,54 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
       v[e] = make_float2(a * v[e].x + b * gm.x, a * v[e].y - b * gm.y);
     });
     __syncthreads();
-    static_for<0, E>([&](auto ee) {  // Psi to LDS: each lane needs Psi(k) and Psi(-k)
-      constexpr int e = decltype(ee)::value;
-      const int ky = t + T * (e / RL) + (e % RL) * ML;
-      lv.at(ky) = gld(I.psi_hat, o_ld + (uint32_t)((ky - t) * nx));
-    });
+    // The Nesterov state is the last two gradient-step spectra Z_k and Z_{k-1},
+    // in psi_hat and z_hat with roles alternating on the parity of k, so one
+    // field is written per iteration (Z_{k+1} over Z_{k-1}); the extrapolated
+    // Psi_k = Z_k + beta_{k-1} (Z_k - Z_{k-1}) is rebuilt here, the same
+    // expression that formed it at the end of the previous iteration.
+    const int kg = I.k0 + S.iter;
+    float2* const z_cur = (OP == COL_NESTEROV && (kg & 1)) ? I.z_hat : I.psi_hat;
+    float2* const z_old = (OP == COL_NESTEROV && (kg & 1)) ? I.psi_hat : I.z_hat;
+    const float bp = (OP == COL_NESTEROV && kg > 0) ? (float)S.beta[kg - 1] : 0.f;
+    // Psi to LDS: each lane needs Psi(k) and Psi(-k)
+    if constexpr (OP == COL_NESTEROV) {
+      // Two loads per element, in batches of NA, the next batch in flight
+      // while this one is combined; the scheduling barriers keep the compiler
+      // from hoisting every load, which would not fit in 128 registers.
+      constexpr int NA = 4;
+      static_assert(E % NA == 0, "state batches");
+      float2 zk[2][NA], zp[2][NA];
+      const uint32_t o_a = opaque(o_ld);
+      auto load_state = [&](auto bb, int slot) {
+        static_for<0, NA>([&](auto uu) {
+          constexpr int u = decltype(uu)::value, e = decltype(bb)::value * NA + u;
+          const int ky = t + T * (e / RL) + (e % RL) * ML;
+          zk[slot][u] = gld(z_cur, o_a + (uint32_t)((ky - t) * nx));
+          zp[slot][u] = gld(z_old, o_a + (uint32_t)((ky - t) * nx));
+        });
+      };
+      load_state(std::integral_constant<int, 0>{}, 0);
+      static_for<0, E / NA>([&](auto bb) {
+        constexpr int b = decltype(bb)::value;
+        if constexpr (b + 1 < E / NA) load_state(std::integral_constant<int, b + 1>{}, (b + 1) & 1);
+        __builtin_amdgcn_sched_barrier(0);
+        static_for<0, NA>([&](auto uu) {
+          constexpr int u = decltype(uu)::value, e = b * NA + u;
+          const int ky = t + T * (e / RL) + (e % RL) * ML;
+          const float2 a = zk[b & 1][u], c = zp[b & 1][u];
+          lv.at(ky) = make_float2(a.x + bp * (a.x - c.x), a.y + bp * (a.y - c.y));
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    } else {
+      static_for<0, E>([&](auto ee) {
+        constexpr int e = decltype(ee)::value;
+        const int ky = t + T * (e / RL) + (e % RL) * ML;
+        lv.at(ky) = gld(I.psi_hat, o_ld + (uint32_t)((ky - t) * nx));
+      });
+    }
     __syncthreads();
-    const float bf = (OP == COL_NESTEROV) ? (float)S.beta[I.k0 + S.iter] : 0.f;
+    const float bf = (OP == COL_NESTEROV) ? (float)S.beta[kg] : 0.f;
     const float gxv = gldf(I.gx, kx);
     const uint32_t o_up = opaque(o_ld);
     // The update runs in batches of NB elements; z and the STF factors of the
@@ -543,7 +587,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
       static_for<0, NB>([&](auto uu) {
         constexpr int e = b0 + decltype(uu)::value;
         const int ky = t + T * (e / RL) + (e % RL) * ML;
-        if constexpr (OP == COL_NESTEROV) zb[slot][decltype(uu)::value] = gld(I.z_hat, o_up + (uint32_t)((ky - t) * nx));
+        if constexpr (OP == COL_NESTEROV) zb[slot][decltype(uu)::value] = gld(z_cur, o_up + (uint32_t)((ky - t) * nx));
         gb[slot][decltype(uu)::value] = gldf(I.gy, ky);
       });
     };
@@ -554,8 +598,11 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
       static_for<0, NB>([&](auto uu) {
         constexpr int u = decltype(uu)::value, e = b * NB + u;
         const int ky = t + T * (e / RL) + (e % RL) * ML;
-        const float2 pk = lv.at(ky);
-        const float2 pm = lm.at((NY - ky) & (NY - 1));
+        // LDS indices from a fresh copy of t: reusing the direction step's
+        // addresses would keep E of them live across the state loads
+        const int kl = (int)opaque((uint32_t)t) + T * (e / RL) + (e % RL) * ML;
+        const float2 pk = lv.at(kl);
+        const float2 pm = lm.at((NY - kl) & (NY - 1));
         const float g2 = gxv + (1.f - gxv) * gb[b & 1][u];   // 1 - STFx STFy without cancellation
         // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
         const float2 reg = make_float2(I.alpha_c1 * pk.x + I.alpha_c2 * pm.x, I.alpha_c1 * pk.y - I.alpha_c2 * pm.y);
@@ -565,8 +612,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
           const float2 zo = zb[b & 1][u];
           const float2 z = make_float2(pk.x - I.eta * d.x, pk.y - I.eta * d.y);
           const float2 pn = make_float2(z.x + bf * (z.x - zo.x), z.y + bf * (z.y - zo.y));
-          gst(I.z_hat, gi, z);
-          gst(I.psi_hat, gi, pn);
+          gst(z_old, gi, z);  // Z_{k+1}; this lane read Z_{k-1} here above
           v[e] = cscale(pn, I.inv_m);
         } else {
           v[e] = cscale(d, I.inv_m);
@@ -629,7 +675,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
           gst(I.y_hat, (uint32_t)(ky * nx + s), v[e]);
         } else if constexpr (OP == COL_SPEC_PSIHAT) {
           gst(I.psi_hat, (uint32_t)(ky * nx + s), v[e]);
-          if (I.z_hat) gst(I.z_hat, (uint32_t)(ky * nx + s), make_float2(0.f, 0.f));
+          if (I.z_hat) gst(I.z_hat, (uint32_t)(ky * nx + s), v[e]);  // Z_{-1} = Z_0 = Psi_0
         }
       });
     }
