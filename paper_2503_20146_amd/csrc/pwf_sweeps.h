@@ -503,7 +503,79 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
   const float fx = freq_of(kx, nx);
   double acc = 0.0;
 
-  if constexpr (OP == COL_NESTEROV || OP == COL_DIRECTION) {
+  if constexpr (OP == COL_NESTEROV) {
+    // d = F{Re g} + i P F{Im g} + STF-weighted regulariser; with
+    // F{Re a}_k = (A_k + conj A_{-k})/2 and P, 1 - STF even in k, its terms in
+    // G(-k) and Psi(-k) are conj(h(-k)) with h = (1-P)/2 G + g2 c2 Psi: each
+    // lane hands h of its elements to their mirror lanes through LDS (column
+    // -kx is the neighbour position mirror_col(s), inside this tile) and keeps
+    // the rest of the step in registers.
+    //
+    // The Nesterov state is the last two gradient-step spectra Z_k and Z_{k-1},
+    // in psi_hat and z_hat with roles alternating on the parity of k, so one
+    // field is written per iteration (Z_{k+1} over Z_{k-1}); the extrapolated
+    // Psi_k = Z_k + beta_{k-1} (Z_k - Z_{k-1}) is rebuilt here, the same
+    // expression that formed it at the end of the previous iteration.
+    const int wm = mirror_col(s) - tile * W;
+    const LdsView lm{lds + wm, W};
+    const int kg = I.k0 + S.iter;
+    float2* const z_cur = (kg & 1) ? I.z_hat : I.psi_hat;
+    float2* const z_old = (kg & 1) ? I.psi_hat : I.z_hat;
+    const float bp = kg > 0 ? (float)S.beta[kg - 1] : 0.f;
+    const float bf = (float)S.beta[kg];
+    const float gxv = gldf(I.gx, kx);
+    // State and STF loads in batches of NA, the next batch in flight while
+    // this one is combined; the scheduling barriers keep the compiler from
+    // hoisting every load, which would not fit in 128 registers.  Z_k stays
+    // in registers for the momentum term.
+    constexpr int NA = 4;
+    static_assert(E % NA == 0, "state batches");
+    float2 zk[E], zp[2][NA];
+    float gb[2][NA];
+    const uint32_t o_a = opaque(o_ld);
+    auto load_state = [&](auto bb, int slot) {
+      static_for<0, NA>([&](auto uu) {
+        constexpr int u = decltype(uu)::value, e = decltype(bb)::value * NA + u;
+        const int ky = t + T * (e / RL) + (e % RL) * ML;
+        zk[e] = gld(z_cur, o_a + (uint32_t)((ky - t) * nx));
+        zp[slot][u] = gld(z_old, o_a + (uint32_t)((ky - t) * nx));
+        gb[slot][u] = gldf(I.gy, ky);
+      });
+    };
+    load_state(std::integral_constant<int, 0>{}, 0);
+    static_for<0, E / NA>([&](auto bb) {
+      constexpr int b = decltype(bb)::value;
+      if constexpr (b + 1 < E / NA) load_state(std::integral_constant<int, b + 1>{}, (b + 1) & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      static_for<0, NA>([&](auto uu) {
+        constexpr int u = decltype(uu)::value, e = b * NA + u;
+        const int ky = t + T * (e / RL) + (e % RL) * ML;
+        const float2 z0 = zk[e], z1 = zp[b & 1][u];
+        const float2 ps = make_float2(z0.x + bp * (z0.x - z1.x), z0.y + bp * (z0.y - z1.y));
+        const float P = pinv_of(I, fx, freq_of(ky, NY));
+        const float a = 0.5f * (1.f + P), c = 0.5f * (1.f - P);
+        const float g2 = gxv + (1.f - gxv) * gb[b & 1][u];  // 1 - STFx STFy without cancellation
+        const float r1 = g2 * I.alpha_c1, r2 = g2 * I.alpha_c2;
+        lv.at(ky) = make_float2(c * v[e].x + r2 * ps.x, c * v[e].y + r2 * ps.y);
+        // Psi - eta (a G + g2 c1 Psi); the mirror's share follows the exchange
+        v[e] = make_float2(ps.x - I.eta * (a * v[e].x + r1 * ps.x), ps.y - I.eta * (a * v[e].y + r1 * ps.y));
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    __syncthreads();
+    const uint32_t o_up = opaque(o_ld);
+    static_for<0, E>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      const int ky = t + T * (e / RL) + (e % RL) * ML;
+      const int kl = (int)opaque((uint32_t)t) + T * (e / RL) + (e % RL) * ML;
+      const float2 hm = lm.at((NY - kl) & (NY - 1));
+      const float2 z = make_float2(v[e].x - I.eta * hm.x, v[e].y + I.eta * hm.y);  // - eta conj(h(-k))
+      const float2 pn = make_float2(z.x + bf * (z.x - zk[e].x), z.y + bf * (z.y - zk[e].y));
+      gst(z_old, o_up + (uint32_t)((ky - t) * nx), z);  // Z_{k+1}; this lane read Z_{k-1} here above
+      v[e] = cscale(pn, I.inv_m);
+    });
+    __syncthreads();
+  } else if constexpr (OP == COL_DIRECTION) {
     // Needs G(-k) and Psi(-k): exchange through LDS.  Column -kx is the
     // neighbour position mirror_col(s), inside this tile.
     const int wm = mirror_col(s) - tile * W;
@@ -523,101 +595,22 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
       v[e] = make_float2(a * v[e].x + b * gm.x, a * v[e].y - b * gm.y);
     });
     __syncthreads();
-    // The Nesterov state is the last two gradient-step spectra Z_k and Z_{k-1},
-    // in psi_hat and z_hat with roles alternating on the parity of k, so one
-    // field is written per iteration (Z_{k+1} over Z_{k-1}); the extrapolated
-    // Psi_k = Z_k + beta_{k-1} (Z_k - Z_{k-1}) is rebuilt here, the same
-    // expression that formed it at the end of the previous iteration.
-    const int kg = I.k0 + S.iter;
-    float2* const z_cur = (OP == COL_NESTEROV && (kg & 1)) ? I.z_hat : I.psi_hat;
-    float2* const z_old = (OP == COL_NESTEROV && (kg & 1)) ? I.psi_hat : I.z_hat;
-    const float bp = (OP == COL_NESTEROV && kg > 0) ? (float)S.beta[kg - 1] : 0.f;
-    // Psi to LDS: each lane needs Psi(k) and Psi(-k)
-    if constexpr (OP == COL_NESTEROV) {
-      // Two loads per element, in batches of NA, the next batch in flight
-      // while this one is combined; the scheduling barriers keep the compiler
-      // from hoisting every load, which would not fit in 128 registers.
-      constexpr int NA = 4;
-      static_assert(E % NA == 0, "state batches");
-      float2 zk[2][NA], zp[2][NA];
-      const uint32_t o_a = opaque(o_ld);
-      auto load_state = [&](auto bb, int slot) {
-        static_for<0, NA>([&](auto uu) {
-          constexpr int u = decltype(uu)::value, e = decltype(bb)::value * NA + u;
-          const int ky = t + T * (e / RL) + (e % RL) * ML;
-          zk[slot][u] = gld(z_cur, o_a + (uint32_t)((ky - t) * nx));
-          zp[slot][u] = gld(z_old, o_a + (uint32_t)((ky - t) * nx));
-        });
-      };
-      load_state(std::integral_constant<int, 0>{}, 0);
-      static_for<0, E / NA>([&](auto bb) {
-        constexpr int b = decltype(bb)::value;
-        if constexpr (b + 1 < E / NA) load_state(std::integral_constant<int, b + 1>{}, (b + 1) & 1);
-        __builtin_amdgcn_sched_barrier(0);
-        static_for<0, NA>([&](auto uu) {
-          constexpr int u = decltype(uu)::value, e = b * NA + u;
-          const int ky = t + T * (e / RL) + (e % RL) * ML;
-          const float2 a = zk[b & 1][u], c = zp[b & 1][u];
-          lv.at(ky) = make_float2(a.x + bp * (a.x - c.x), a.y + bp * (a.y - c.y));
-        });
-        __builtin_amdgcn_sched_barrier(0);
-      });
-    } else {
-      static_for<0, E>([&](auto ee) {
-        constexpr int e = decltype(ee)::value;
-        const int ky = t + T * (e / RL) + (e % RL) * ML;
-        lv.at(ky) = gld(I.psi_hat, o_ld + (uint32_t)((ky - t) * nx));
-      });
-    }
+    static_for<0, E>([&](auto ee) {  // Psi to LDS: each lane needs Psi(k) and Psi(-k)
+      constexpr int e = decltype(ee)::value;
+      const int ky = t + T * (e / RL) + (e % RL) * ML;
+      lv.at(ky) = gld(I.psi_hat, o_ld + (uint32_t)((ky - t) * nx));
+    });
     __syncthreads();
-    const float bf = (OP == COL_NESTEROV) ? (float)S.beta[kg] : 0.f;
     const float gxv = gldf(I.gx, kx);
-    const uint32_t o_up = opaque(o_ld);
-    // The update runs in batches of NB elements; z and the STF factors of the
-    // next batch are loaded before this batch's stores (behind them the
-    // compiler could not move the loads up, and one memory round trip per
-    // element followed), two batches in registers at a time: the sweep then
-    // fits 128 registers and two 8-column workgroups per CU.
-    constexpr int NB = 4;
-    static_assert(E % NB == 0, "update batches");
-    float2 zb[2][NB];
-    float gb[2][NB];
-    auto load_batch = [&](auto bb, int slot) {
-      constexpr int b0 = decltype(bb)::value * NB;
-      static_for<0, NB>([&](auto uu) {
-        constexpr int e = b0 + decltype(uu)::value;
-        const int ky = t + T * (e / RL) + (e % RL) * ML;
-        if constexpr (OP == COL_NESTEROV) zb[slot][decltype(uu)::value] = gld(z_cur, o_up + (uint32_t)((ky - t) * nx));
-        gb[slot][decltype(uu)::value] = gldf(I.gy, ky);
-      });
-    };
-    load_batch(std::integral_constant<int, 0>{}, 0);
-    static_for<0, E / NB>([&](auto bb) {
-      constexpr int b = decltype(bb)::value;
-      if constexpr (b + 1 < E / NB) load_batch(std::integral_constant<int, b + 1>{}, (b + 1) & 1);
-      static_for<0, NB>([&](auto uu) {
-        constexpr int u = decltype(uu)::value, e = b * NB + u;
-        const int ky = t + T * (e / RL) + (e % RL) * ML;
-        // LDS indices from a fresh copy of t: reusing the direction step's
-        // addresses would keep E of them live across the state loads
-        const int kl = (int)opaque((uint32_t)t) + T * (e / RL) + (e % RL) * ML;
-        const float2 pk = lv.at(kl);
-        const float2 pm = lm.at((NY - kl) & (NY - 1));
-        const float g2 = gxv + (1.f - gxv) * gb[b & 1][u];   // 1 - STFx STFy without cancellation
-        // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
-        const float2 reg = make_float2(I.alpha_c1 * pk.x + I.alpha_c2 * pm.x, I.alpha_c1 * pk.y - I.alpha_c2 * pm.y);
-        const float2 d = make_float2(v[e].x + g2 * reg.x, v[e].y + g2 * reg.y);
-        if constexpr (OP == COL_NESTEROV) {
-          const uint32_t gi = o_up + (uint32_t)((ky - t) * nx);
-          const float2 zo = zb[b & 1][u];
-          const float2 z = make_float2(pk.x - I.eta * d.x, pk.y - I.eta * d.y);
-          const float2 pn = make_float2(z.x + bf * (z.x - zo.x), z.y + bf * (z.y - zo.y));
-          gst(z_old, gi, z);  // Z_{k+1}; this lane read Z_{k-1} here above
-          v[e] = cscale(pn, I.inv_m);
-        } else {
-          v[e] = cscale(d, I.inv_m);
-        }
-      });
+    static_for<0, E>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      const int ky = t + T * (e / RL) + (e % RL) * ML;
+      const float2 pk = lv.at(ky);
+      const float2 pm = lm.at((NY - ky) & (NY - 1));
+      const float g2 = gxv + (1.f - gxv) * gldf(I.gy, ky);   // 1 - STFx STFy without cancellation
+      // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
+      const float2 reg = make_float2(I.alpha_c1 * pk.x + I.alpha_c2 * pm.x, I.alpha_c1 * pk.y - I.alpha_c2 * pm.y);
+      v[e] = cscale(make_float2(v[e].x + g2 * reg.x, v[e].y + g2 * reg.y), I.inv_m);
     });
     __syncthreads();
   } else {
