@@ -252,6 +252,28 @@ def test_step_resume_equals_uninterrupted():
     assert torch.equal(s1[0]["psi"], saved[0]["psi"])
 
 
+def test_step_batch_with_mixed_iteration_counts():
+    """States at odd and even k stepped in one batch (the momentum state's two
+    spectra swap roles with the parity of k, per instance) equal each state
+    stepped alone, bit for bit."""
+    import torch
+    dev = device()
+    say("step batch with k = 0 and k = 1")
+    inps = [instance(0, instance=i) for i in range(2)]
+    probs = [gpu_problem(x[1], x[0]["t"], dev) for x in inps]
+    ys = [to_dev(x[3], dev) for x in inps]
+    pair = _pwf(probs).init_states(ys)
+    _pwf([probs[1]]).step([pair[1]])            # instance 1 one step ahead
+    for _ in range(3):
+        _pwf(probs).step(pair)
+    assert (pair[0]["k"], pair[1]["k"]) == (3, 4)
+    for i, n in ((0, 3), (1, 4)):
+        alone = _pwf([probs[i]]).init_states([ys[i]])
+        for _ in range(n):
+            _pwf([probs[i]]).step(alone)
+        assert torch.equal(pair[i]["psi"], alone[0]["psi"]), i
+
+
 def test_step_from_initial_psi_matches_oracle():
     dev = device()
     inp, geo, prob, y = instance(0)
