@@ -202,6 +202,37 @@ def test_row_plans_match_oracle(plan):
     assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
+ALT_TILE = {128: 16, 256: 32, 512: 8, 1024: 4, 2048: 2}   # the second compiled width per side
+
+
+@pytest.mark.parametrize("side", [128, 256, 512, 1024, 2048])
+def test_alternative_column_tiles_match_oracle(side):
+    """Every column sweep forced onto the second compiled tile width (the
+    autotuner may pick either per sweep): forward and 8 iterations against the
+    oracle, and the iterate against the default width's."""
+    from paper_2503_20146_amd import set_column_tile
+    dev = device()
+    inp, geo, prob, y = instance(3, n=side)
+    p = gpu_problem(geo, inp["t"], dev)
+    yd = to_dev(y, dev)
+    psi0 = (0.5 * inp["psi_true"]).astype(np.complex64)
+    say(f"column tile {ALT_TILE[side]} at {side}^2")
+    out_d, _ = _pwf([p]).solve([yd], 8)
+    set_column_tile(side, ALT_TILE[side])
+    try:
+        batch = _pwf([p])
+        f = batch.forward([to_dev(psi0, dev)])[0].cpu().numpy()
+        out, _ = batch.solve([yd], 8)
+    finally:
+        set_column_tile(side, 0)
+    f_ref, _, _ = O.physical_model(psi0.astype(np.complex128), prob)
+    assert rel(f, f_ref) <= FWD_TOL
+    psi, psi_d = out[0].cpu().numpy(), out_d[0].cpu().numpy()
+    psi_ref, _, _ = O.pwf(y, prob, 8)
+    assert np.sqrt(np.mean(np.abs(psi - psi_ref) ** 2)) <= PHASE_TOL
+    assert np.max(np.abs(psi - psi_d)) <= 1e-5 * max(1.0, np.max(np.abs(psi_d)))
+
+
 def test_plain_path_parity():
     dev = device()
     inp, geo, prob, y = instance(0)
