@@ -244,7 +244,7 @@ pwf_status validate_batch(const pwf_problem* probs, int32_t n) {
 
 size_t field_bytes(const pwf_problem& p) { return align_up((size_t)p.geom.nx * p.geom.ny * sizeof(float2)); }
 // loss partials: one per column tile of the residual sweep
-int n_partials(const pwf_problem& p) { return p.geom.nx / col_width(p.geom.ny, pwf::COL_BLUR_LOSS); }
+int n_partials(const pwf_problem& p) { return p.geom.nx / 2 / col_width(p.geom.ny, pwf::COL_BLUR_LOSS); }
 size_t table_bytes(const pwf_problem& p) {
   return align_up((size_t)(p.geom.nx + p.geom.ny) * (2 * sizeof(float2) + 2 * sizeof(float)));
 }
@@ -410,6 +410,7 @@ struct Launcher {
   const Batch& B;
   hipStream_t st;
   double corr_tol = 0.0;
+  bool full_intensity = false;  // S4 writes the full x-spectrum (forward model only)
   Inst* dev_desc() const { return (Inst*)(ws + L.desc); }
   int32_t* status() const { return (int32_t*)(ws + L.status); }
 
@@ -426,6 +427,7 @@ struct Launcher {
     S.status = status();
     S.blocks_per_inst = 0;
     S.corr_tol = corr_tol;
+    S.half = full_intensity ? 0 : 1;
     return S;
   }
   pwf_status row(int op, int iter = 0) const {
@@ -441,7 +443,7 @@ struct Launcher {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
       const int width = col_width(c.ny, op);
-      S.blocks_per_inst = c.nx / width;
+      S.blocks_per_inst = (pwf::col_op_half(op) ? c.nx / 2 : c.nx) / width;
       PWF_HIP(pwf::launch_col(c.ny, width, op, S.blocks_per_inst * c.count, S, st));
     }
     return PWF_OK;
@@ -552,7 +554,7 @@ pwf_status forward_impl(const pwf_problem* problems, int32_t n, const void* cons
   }
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
   PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
-  const Launcher K{*ctx, ws, L, B, st};
+  const Launcher K{*ctx, ws, L, B, st, 0.0, true};
   PWF_TRY(K.row(pwf::ROW_START));
   PWF_TRY(K.col(pwf::COL_CHIRP1));
   PWF_TRY(K.row(pwf::ROW_MUL_T));

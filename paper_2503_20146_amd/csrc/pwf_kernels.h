@@ -50,8 +50,17 @@ enum ColOp {
   COL_NESTEROV,        // S11
   COL_DIRECTION,       // spectrum of the update direction d
   COL_SPEC_YHAT,       // y_hat = FFT_y(W)
-  COL_SPEC_PSIHAT,     // psi_hat = FFT_y(W); z_hat = 0
+  COL_SPEC_PSIHAT,     // psi_hat = FFT_y(W); z_hat = psi_hat
 };
+
+// Sweeps on the real intensity path work on x-spectra in half form: the
+// spectra of real rows are Hermitian, so a row keeps kx = 1 .. nx/2 - 1 at
+// position kx and packs the two real values at kx = 0 and kx = nx/2 into
+// position 0 (the latter scaled by the x factor of the IOTF at nx/2, so that
+// the column sweep treats the packed column like any other and the row sweep
+// after it undoes the factor).  A row keeps its place (pitch nx, the first nx/2
+// values used), so each row sweep still rewrites only the row it read.
+constexpr bool col_op_half(int op) { return op == COL_BLUR_LOSS || op == COL_SPEC_YHAT; }
 
 enum PlainWindow {
   PLAIN_W_Q1 = 0, PLAIN_W_Q2, PLAIN_W_Q2C, PLAIN_W_Q1C, PLAIN_W_IOTF, PLAIN_W_PINV, PLAIN_W_GAMMA2,

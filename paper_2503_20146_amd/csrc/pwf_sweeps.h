@@ -182,12 +182,31 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   float2 side[SIDE ? E : 1];
   float2 v[E];
   if constexpr (IN_FREQ) {
-    static_for<0, E / RL>([&](auto cc) {
-      static_for<0, RL>([&](auto rr) {
-        constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
-        v[c * RL + r] = gld(I.W, rbase + col_of_kx(t + T * c + r * ML, NX));
+    if constexpr (OP == ROW_BACKBLUR) {
+      // half-form x-spectrum (see col_op_half): kx > nx/2 from conj at nx - kx,
+      // kx = 0 and nx/2 from the packed position 0
+      const uint32_t rh = rbase;
+      const float s_ny = gldf(I.ix, NX / 2);
+      static_for<0, E / RL>([&](auto cc) {
+        static_for<0, RL>([&](auto rr) {
+          constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
+          const int kx = t + T * c + r * ML;
+          const int kk = kx <= NX / 2 ? kx : NX - kx;
+          float2 a = gld(I.W, rh + (uint32_t)(kk == NX / 2 ? 0 : kk));
+          if (kx > NX / 2) a.y = -a.y;
+          else if (kx == 0) a.y = 0.f;
+          else if (kx == NX / 2) a = make_float2(s_ny * a.y, 0.f);
+          v[c * RL + r] = a;
+        });
       });
-    });
+    } else {
+      static_for<0, E / RL>([&](auto cc) {
+        static_for<0, RL>([&](auto rr) {
+          constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
+          v[c * RL + r] = gld(I.W, rbase + col_of_kx(t + T * c + r * ML, NX));
+        });
+      });
+    }
     load_twiddles();
     if constexpr (SIDE) {
       const float2* __restrict__ sp = (OP == ROW_MUL_T || OP == ROW_MUL_CONJ_T) ? I.t
@@ -329,13 +348,30 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
 
   if constexpr (OUT_FREQ) {
     fft_forward<Plan, T>(v, t, tw, lv);
-    const uint32_t rb_st = opaque(rbase);
-    static_for<0, E / RL>([&](auto cc) {
-      static_for<0, RL>([&](auto rr) {
-        constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
-        gst(I.W, rb_st + col_of_kx(t + T * c + r * ML, NX), v[c * RL + r]);
+    if ((OP == ROW_INTENSITY && S.half) || OP == ROW_REAL_FFT) {
+      // spectrum of a real row in half form (see col_op_half); lane 0 holds
+      // kx = 0 in v[0] and kx = nx/2 in v[RL/2]
+      const uint32_t rh = opaque(rbase);
+      static_for<0, E / RL>([&](auto cc) {
+        static_for<0, RL>([&](auto rr) {
+          constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
+          const int kx = t + T * c + r * ML;
+          if (kx > 0 && kx < NX / 2) gst(I.W, rh + (uint32_t)kx, v[c * RL + r]);
+        });
       });
-    });
+      if (t == 0) {
+        const float s_ny = OP == ROW_INTENSITY ? gldf(I.ix, NX / 2) : 1.f;
+        gst(I.W, rh, make_float2(v[0].x, s_ny * v[RL / 2].x));
+      }
+    } else {
+      const uint32_t rb_st = opaque(rbase);
+      static_for<0, E / RL>([&](auto cc) {
+        static_for<0, RL>([&](auto rr) {
+          constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
+          gst(I.W, rb_st + col_of_kx(t + T * c + r * ML, NX), v[c * RL + r]);
+        });
+      });
+    }
   }
 
   if constexpr (OP == ROW_MUL_T) {
@@ -462,6 +498,8 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
   const int tile = col_tile_of<W>(b - inst * S.blocks_per_inst, S.blocks_per_inst);
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
   if (instance_stopped(I)) return;  // uniform over the workgroup
+  // x-spectra in half form (col_op_half) use columns 0 .. nx/2 - 1 only
+  constexpr bool HALF = col_op_half(OP);
   const int nx = I.nx;
   if constexpr (OP == COL_CHIRP1) {
     // Stopping rule (Methods, "Reconstruction procedure"): |<x_k, x_k-1>| /
@@ -499,7 +537,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
   fft_forward<Plan, T>(v, t, tw, lv);
 
   // Fourier-domain step; element e = c*RL + r holds ky = t + T c + r ML.
-  const int kx = kx_of_col(s, nx);
+  const int kx = HALF ? s : kx_of_col(s, nx);
   const float fx = freq_of(kx, nx);
   double acc = 0.0;
 
@@ -618,7 +656,10 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
     float ixv = 1.f;
     if constexpr (OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ) qx = gld(I.qx1, kx);
     if constexpr (OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ) qx = gld(I.qx2, kx);
-    if constexpr (OP == COL_BLUR || OP == COL_BLUR_LOSS) ixv = gldf(I.ix, kx);
+    // (half form: the packed column 0 carries its x factors from the row sweeps)
+    if constexpr (OP == COL_BLUR || OP == COL_BLUR_LOSS) ixv = (HALF && s == 0) ? 1.f : gldf(I.ix, kx);
+    // half form: columns s > 0 stand for kx and -kx in the loss
+    const double wgt = (HALF && s > 0) ? 2.0 : 1.0;
     constexpr bool CHIRP = OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ || OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ;
     constexpr bool CONJ = OP == COL_CHIRP1_CONJ || OP == COL_CHIRP2_CONJ;
     constexpr bool L1 = OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ;
@@ -662,7 +703,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
           const float h = ixv * gldf(I.iy, ky);
           const float2 yh = gld(I.y_hat, (uint32_t)(ky * nx + s));
           const float2 rr = make_float2(h * v[e].x - yh.x, h * v[e].y - yh.y);
-          acc += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
+          acc += wgt * ((double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y);
           v[e] = cscale(rr, h * I.inv_m);
         } else if constexpr (OP == COL_SPEC_YHAT) {
           gst(I.y_hat, (uint32_t)(ky * nx + s), v[e]);
