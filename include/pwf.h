@@ -100,7 +100,11 @@ typedef struct {
  *            z_{k+1}.  The spectrum of psi_k, z_k + beta_{k-1} (z_k - z_{k-1}),
  *            is formed from them when needed; pwf_state_init sets both to the
  *            spectrum of psi_0 (z_{-1} = z_0 = psi_0).
- *   y_hat    spectrum of the measured speckle y, same layout
+ *   y_hat    spectrum of the measured speckle y in half form: y is real, so
+ *            row ky keeps kx = 1 .. nx/2 - 1 at position kx and the real
+ *            x-spectra at kx = 0 and nx/2, packed as one complex column, at
+ *            position 0 (transformed along y together); positions nx/2 .. nx-1
+ *            of each row are unused
  *   k        iterations done so far (host value, advanced by pwf_step)
  * The frequency layout is row-major [ky][s]: column kx of the 2-D DFT sits at
  * s = 2 kx for 0 < kx < nx/2, at s = 2 (nx - kx) + 1 for nx/2 < kx < nx, at
