@@ -410,7 +410,6 @@ struct Launcher {
   const Batch& B;
   hipStream_t st;
   double corr_tol = 0.0;
-  bool full_intensity = false;  // S4 writes the full x-spectrum (forward model only)
   Inst* dev_desc() const { return (Inst*)(ws + L.desc); }
   int32_t* status() const { return (int32_t*)(ws + L.status); }
 
@@ -427,7 +426,6 @@ struct Launcher {
     S.status = status();
     S.blocks_per_inst = 0;
     S.corr_tol = corr_tol;
-    S.half = full_intensity ? 0 : 1;
     return S;
   }
   pwf_status row(int op, int iter = 0) const {
@@ -554,7 +552,7 @@ pwf_status forward_impl(const pwf_problem* problems, int32_t n, const void* cons
   }
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
   PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
-  const Launcher K{*ctx, ws, L, B, st, 0.0, true};
+  const Launcher K{*ctx, ws, L, B, st};
   PWF_TRY(K.row(pwf::ROW_START));
   PWF_TRY(K.col(pwf::COL_CHIRP1));
   PWF_TRY(K.row(pwf::ROW_MUL_T));

@@ -187,7 +187,6 @@ struct Sweep {
   const float2* tw_col;   // twiddles of the column plan (forward, then reversed plan)
   int32_t* status;        // bit 0: non-finite loss seen
   double corr_tol;        // stopping correlation threshold (used when corr_partial is set)
-  int32_t half;           // ROW_INTENSITY: write the x-spectrum in half form (see col_op_half)
 };
 
 // True when the instance has met the correlation stop: its sweeps are skipped.

@@ -56,11 +56,13 @@ enum ColOp {
 // Sweeps on the real intensity path work on x-spectra in half form: the
 // spectra of real rows are Hermitian, so a row keeps kx = 1 .. nx/2 - 1 at
 // position kx and packs the two real values at kx = 0 and kx = nx/2 into
-// position 0 (the latter scaled by the x factor of the IOTF at nx/2, so that
-// the column sweep treats the packed column like any other and the row sweep
-// after it undoes the factor).  A row keeps its place (pitch nx, the first nx/2
-// values used), so each row sweep still rewrites only the row it read.
-constexpr bool col_op_half(int op) { return op == COL_BLUR_LOSS || op == COL_SPEC_YHAT; }
+// position 0.  S4 scales the kx = nx/2 value by the IOTF's x factor there, so
+// that the blur sweeps apply only the y factors to the packed column (the x
+// factor at kx = 0 is 1); the residual sweep applies the IOTF a second time,
+// and the back-blur row sweep multiplies the kx = nx/2 value by that x factor
+// once more.  A row keeps its place (pitch nx, the first nx/2 values used), so
+// each row sweep still rewrites only the row it read.
+constexpr bool col_op_half(int op) { return op == COL_BLUR_LOSS || op == COL_BLUR || op == COL_SPEC_YHAT; }
 
 enum PlainWindow {
   PLAIN_W_Q1 = 0, PLAIN_W_Q2, PLAIN_W_Q2C, PLAIN_W_Q1C, PLAIN_W_IOTF, PLAIN_W_PINV, PLAIN_W_GAMMA2,

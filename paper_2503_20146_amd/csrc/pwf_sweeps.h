@@ -182,11 +182,12 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   float2 side[SIDE ? E : 1];
   float2 v[E];
   if constexpr (IN_FREQ) {
-    if constexpr (OP == ROW_BACKBLUR) {
+    if constexpr (OP == ROW_BACKBLUR || OP == ROW_FORWARD_OUT) {
       // half-form x-spectrum (see col_op_half): kx > nx/2 from conj at nx - kx,
-      // kx = 0 and nx/2 from the packed position 0
+      // kx = 0 and nx/2 from the packed position 0 (after the residual sweep's
+      // second IOTF, kx = nx/2 still lacks its second x factor)
       const uint32_t rh = rbase;
-      const float s_ny = gldf(I.ix, NX / 2);
+      const float s_ny = OP == ROW_BACKBLUR ? gldf(I.ix, NX / 2) : 1.f;
       static_for<0, E / RL>([&](auto cc) {
         static_for<0, RL>([&](auto rr) {
           constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
@@ -348,7 +349,7 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
 
   if constexpr (OUT_FREQ) {
     fft_forward<Plan, T>(v, t, tw, lv);
-    if ((OP == ROW_INTENSITY && S.half) || OP == ROW_REAL_FFT) {
+    if constexpr (OP == ROW_INTENSITY || OP == ROW_REAL_FFT) {
       // spectrum of a real row in half form (see col_op_half); lane 0 holds
       // kx = 0 in v[0] and kx = nx/2 in v[RL/2]
       const uint32_t rh = opaque(rbase);
