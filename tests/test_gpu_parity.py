@@ -109,6 +109,28 @@ def test_gradient_and_direction_parity(workload):
     assert abs(float(loss[0].cpu()) - l_ref) <= 1e-5 * l_ref
 
 
+@pytest.mark.parametrize("sigma", [0.0, 0.3])
+def test_weak_blur_forward_gradient_solve(sigma):
+    """Little or no source blur: the IOTF's x factor at kx = nx/2 is 1 or 0.64
+    (1.5e-5 at the workloads' 1.5 px), so the Nyquist column of the half-form
+    intensity spectra carries weight in the forward model, loss and gradient."""
+    dev = device()
+    inp, geo, prob, y = instance(0, sigma=sigma)
+    say(f"weak blur sigma {sigma}")
+    psi = (0.5 * inp["psi_true"]).astype(np.complex64)
+    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    f = batch.forward([to_dev(psi, dev)])[0].cpu().numpy()
+    f_ref, _, _ = O.physical_model(psi.astype(np.complex128), prob)
+    assert rel(f, f_ref) <= FWD_TOL
+    l_ref, g_ref, _ = O.gradient(psi.astype(np.complex128), y, prob)
+    loss, g, _ = batch.gradient([to_dev(psi, dev)], [to_dev(y, dev)])
+    assert rel(g[0].cpu().numpy(), g_ref) <= GRAD_TOL
+    assert abs(float(loss[0].cpu()) - l_ref) <= 1e-5 * l_ref
+    out, _ = batch.solve([to_dev(y, dev)], 10)
+    psi_ref, _, _ = O.pwf(y, prob, 10)
+    assert np.sqrt(np.mean(np.abs(out[0].cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL
+
+
 def test_gradient_without_preconditioner_and_other_alpha():
     dev = device()
     inp, geo, _, y = instance(0)
