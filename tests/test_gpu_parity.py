@@ -43,6 +43,31 @@ def test_forward_parity_sizes(ny, nx):
     assert rel(f, f_ref) <= FWD_TOL
 
 
+@pytest.mark.parametrize("ny,nx", [(128, 512), (512, 128), (256, 2048)])
+def test_weak_blur_nonsquare_forward_and_gradient(ny, nx):
+    """Non-square grids with a weak x blur (sigma_x 0.3 px: the IOTF's x factor
+    at kx = nx/2 is 0.64), so the packed Nyquist column of the half-form
+    intensity spectra carries weight; the loss and gradient too."""
+    dev = device()
+    say(f"weak blur forward/gradient {ny}x{nx}")
+    rng = np.random.default_rng(ny * 11 + nx)
+    geo = S.Geometry(ny=ny, nx=nx, sigma_x_px=0.3, sigma_y_px=0.8)
+    t = S.diffuser(rng, ny, nx)
+    psi_true = S.phase_object(rng, ny, nx, 6.0, 3.0)
+    prob = O.make_problem(t, geo)
+    f_true, _, _ = O.physical_model(psi_true, prob)
+    y = (f_true * (1.0 + 0.01 * rng.standard_normal((ny, nx)))).astype(np.float32)
+    psi = (0.6 * psi_true).astype(np.complex64)
+    batch = _pwf([gpu_problem(geo, t, dev)])
+    f = batch.forward([to_dev(psi, dev)])[0].cpu().numpy()
+    f_ref, _, _ = O.physical_model(psi.astype(np.complex128), prob)
+    assert rel(f, f_ref) <= FWD_TOL
+    l_ref, g_ref, _ = O.gradient(psi.astype(np.complex128), y, prob)
+    loss, g, _ = batch.gradient([to_dev(psi, dev)], [to_dev(y, dev)])
+    assert rel(g[0].cpu().numpy(), g_ref) <= GRAD_TOL
+    assert abs(float(loss[0].cpu()) - l_ref) <= 1e-5 * l_ref
+
+
 def test_forward_parity_workload1_zero_and_truth():
     dev = device()
     inp, geo, prob, y = instance(1)
