@@ -218,6 +218,65 @@ def test_weak_object_contrast_transfer():
     assert 3.0 <= errs[1] / errs[0] <= 5.0   # residual is second order in eps
 
 
+def _gaussian_otf(ny, nx, sx, sy):
+    """Fourier transform of a unit-integral Gaussian of std (sx, sy) px: exp(-2 pi^2 (sx^2 fx^2 + sy^2 fy^2))."""
+    fy = np.fft.fftfreq(ny)[:, None]
+    fx = np.fft.fftfreq(nx)[None, :]
+    return np.exp(-2.0 * math.pi ** 2 * (sx * sx * fx * fx + sy * sy * fy * fy))
+
+
+@pytest.mark.parametrize("sx,sy", [(1.5, 1.5), (1.0, 2.0)])
+def test_weak_object_contrast_transfer_with_source_blur(sx, sy):
+    """Weak object, t = 1, Gaussian IPSF of std (sx, sy) px (Eqs. 1, 4-5): the intensity
+    spectrum is the weak-object CTF times the Gaussian's transform,
+    F{f} = OTF [delta + 2 eps (sin(pi lam L rho^2) Phi - cos(pi lam L rho^2) M)] + O(eps^2).
+    Fails if the blur is left out, applied twice, or with the wrong width."""
+    n, p, lam, l1, l2 = 64, 1e-6, 0.05e-9, 5e-3, 0.2
+    geo = _geo(n, pixel_m=p, wavelength_m=lam, z1_m=l1, z2_m=l2, sigma_x_px=sx, sigma_y_px=sy)
+    prob = O.make_problem(np.ones((n, n)), geo)
+    rng = np.random.default_rng(14)
+    mu1, phi1 = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    u, v = O.spatial_frequencies(n, n, p)
+    arg = math.pi * lam * (l1 + l2) * (u * u + v * v)
+    otf = _gaussian_otf(n, n, sx, sy)
+    errs = []
+    for eps in (1e-3, 2e-3):
+        f, _, _ = O.physical_model(eps * (-mu1 + 1j * phi1), prob)
+        spec = O.fft2(f)
+        spec[0, 0] -= n * n
+        pred = otf * 2 * eps * (np.sin(arg) * O.fft2(phi1) - np.cos(arg) * O.fft2(mu1))
+        # the DC bin holds the O(eps^2) change of the mean intensity: compare the others
+        spec[0, 0] = pred[0, 0] = 0.0
+        errs.append(np.max(np.abs(spec - pred)))
+        assert np.max(np.abs(spec - pred)) <= 0.05 * np.max(np.abs(pred))
+        # without the blur the same comparison is far off
+        assert np.max(np.abs(spec - pred / otf)) >= 0.2 * np.max(np.abs(pred))
+    assert 3.0 <= errs[1] / errs[0] <= 5.0
+
+
+def test_source_blur_is_convolution_with_sampled_ipsf():
+    """Eq. 1's blur: f at sigma = 2 px equals the circular convolution of the coherent
+    intensity (sigma = 0) with the unit-sum Gaussian exp(-r^2 / 2 sigma^2) (Eq. 4 in
+    pixels), summed shift by shift on 32 x 32 (aliasing of a 2 px Gaussian < 1e-12)."""
+    n, sig = 32, 2.0
+    rng = np.random.default_rng(15)
+    t = S.diffuser(rng, n, n)
+    psi = S.phase_object(rng, n, n, 3.0, 2.0)
+    coh = O.make_problem(t, _geo(n, sigma_x_px=0.0, sigma_y_px=0.0))
+    blur = O.make_problem(t, _geo(n, sigma_x_px=sig, sigma_y_px=sig))
+    i0, _, _ = O.physical_model(psi, coh)
+    f, _, _ = O.physical_model(psi, blur)
+    d = np.where(np.arange(n) <= n // 2, np.arange(n), np.arange(n) - n).astype(np.float64)
+    ker = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * sig * sig))
+    ker /= ker.sum()
+    conv = np.zeros((n, n))
+    for dy in range(n):
+        for dx in range(n):
+            conv += ker[dy, dx] * np.roll(np.roll(i0, dy, axis=0), dx, axis=1)
+    assert np.max(np.abs(f - conv)) <= 1e-10 * np.max(np.abs(conv))
+    assert np.max(np.abs(i0 - conv)) >= 1e-3 * np.max(np.abs(conv))   # the blur is not vacuous
+
+
 def test_truth_point_has_zero_loss_and_gradient():
     """Noise-free y made at psi_true: L = 0 and g = 0 there."""
     prob, rng = _small_problem(32, z1_m=5e-3, z2_m=0.2, sigma_x_px=1.0, sigma_y_px=1.0)
@@ -361,6 +420,85 @@ def test_loss_decreases_on_small_workload():
     _, hist, _ = O.pwf(y, prob, 50)
     assert np.all(np.diff(hist) < 0)
     assert hist[-1] < O.loss(y, f)   # below the noise floor of the truth
+
+
+# --------------------------------------------------------------------------- stopping correlation
+#
+# The stopping rule (Methods, "Reconstruction procedure") correlates the
+# retrieved fields exp(psi) of consecutive iterations.  The pins below fix the
+# normalisation, the modulus and the use of exp(psi) rather than psi.
+
+def _corr_field(n=16, seed=11):
+    rng = np.random.default_rng(seed)
+    # varying amplitude (so a missing normalisation shows) and phase
+    return -0.3 * rng.uniform(0.0, 1.0, (n, n)) + 1j * rng.uniform(-3.0, 3.0, (n, n))
+
+
+def test_field_correlation_of_global_phase_shift_is_one():
+    """x_b = exp(i theta) x_a is the same field: the correlation is exactly 1."""
+    psi = _corr_field()
+    for theta in (0.0, 0.4, -2.5, 3.0):
+        assert abs(O.field_correlation(psi, psi + 1j * theta) - 1.0) <= 1e-14
+
+
+def test_field_correlation_of_orthogonal_fields_is_zero():
+    """Plane waves of two different DFT bins are orthogonal fields: correlation 0.
+
+    As phases (psi itself) the two are far from orthogonal, so correlating psi
+    instead of exp(psi) fails here."""
+    n = 16
+    yy, xx = np.mgrid[0:n, 0:n]
+    amp = -0.7   # a constant attenuation leaves the fields orthogonal
+    for (a, b) in (((1, 0), (0, 1)), ((2, 3), (5, 3)), ((0, 0), (4, 7))):
+        pa = amp + 2j * math.pi * (a[0] * yy + a[1] * xx) / n
+        pb = 2j * math.pi * (b[0] * yy + b[1] * xx) / n
+        assert O.field_correlation(pa, pb) <= 1e-13
+        assert abs(np.vdot(pa, pb)) / (np.linalg.norm(pa) * np.linalg.norm(pb)) > 0.1
+
+
+def test_field_correlation_second_order_closed_form():
+    """psi_b = psi_a + eps xi: 1 - corr = (eps^2 / 2) Var_w(xi) + O(eps^3), w = |x_a|^2.
+
+    For a phase perturbation (xi = i eta) the correlation is the modulus of
+    the w-weighted characteristic function of eta, for an amplitude one the
+    ratio of moment generating functions; both expand to the weighted
+    variance at second order."""
+    psi = _corr_field(24, 5)
+    rng = np.random.default_rng(6)
+    w = np.exp(2.0 * psi.real)
+    w = w / w.sum()
+    for kind in ("phase", "amplitude"):
+        xi = rng.standard_normal(psi.shape)
+        var = float(np.sum(w * xi * xi) - np.sum(w * xi) ** 2)
+        ratios = []
+        for eps in (1e-3, 2e-3):
+            d = 1j * eps * xi if kind == "phase" else eps * xi
+            got = 1.0 - O.field_correlation(psi, psi + d)
+            ratios.append(got / (0.5 * eps * eps * var))
+        assert abs(ratios[0] - 1.0) <= 1e-2, (kind, ratios)
+        # the deviation from the closed form shrinks with eps
+        assert abs(ratios[1] - 1.0) >= abs(ratios[0] - 1.0) - 1e-6
+
+
+def test_field_correlation_brute_force_8x8():
+    """Explicit double loop over the 8 x 8 pixels of |sum conj(x_a) x_b| / (|x_a| |x_b|)."""
+    rng = np.random.default_rng(8)
+    pa = rng.uniform(-0.5, 0.2, (8, 8)) + 1j * rng.uniform(-3, 3, (8, 8))
+    pb = rng.uniform(-0.5, 0.2, (8, 8)) + 1j * rng.uniform(-3, 3, (8, 8))
+    num_re = num_im = na = nb = 0.0
+    for r in range(8):
+        for c in range(8):
+            ar = math.exp(pa[r, c].real) * math.cos(pa[r, c].imag)
+            ai = math.exp(pa[r, c].real) * math.sin(pa[r, c].imag)
+            br = math.exp(pb[r, c].real) * math.cos(pb[r, c].imag)
+            bi = math.exp(pb[r, c].real) * math.sin(pb[r, c].imag)
+            num_re += ar * br + ai * bi
+            num_im += ar * bi - ai * br
+            na += ar * ar + ai * ai
+            nb += br * br + bi * bi
+    expect = math.hypot(num_re, num_im) / math.sqrt(na * nb)
+    assert abs(O.field_correlation(pa, pb) - expect) <= 1e-14
+    assert 0.0 < expect < 1.0
 
 
 def test_correlation_stop():
