@@ -5,13 +5,16 @@ TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 with the HIP path.
 
 The oracle follows the paper "Speckle-based X-ray microtomography via
-preconditioned Wirtinger flow" (Lee, Hugonnet, Lim, Park; arXiv 2503.20146):
-Algorithm S1 (the PWF loop) and Algorithm S2 (PhysicalModel,
-WirtingerDerivative, Preconditioner, Regularizer, FreePropagation, Filter),
-with the windows of Eq. 5 (IOTF), Eq. 11 (inverse-Laplacian preconditioner),
-Eqs. 14-15 (STF and regularisation window) and the loss of Eq. 2.  Every
-operation is complex128/float64 and uses ``scipy.fft`` as the Fourier
-transform primitive; nothing is blocked, fused or reordered.
+preconditioned Wirtinger flow" (Lee, Hugonnet, Lim, Park; arXiv 2503.20146).
+The forward model is Eq. 1 written as a composition of operators
+(propagation, diffuser, squared modulus, source blur); the gradient of the
+loss of Eq. 2 is the transpose of that model's Jacobian applied to the
+misfit, scaled as the paper's Wirtinger gradient; the direction adds the
+inverse-Laplacian preconditioner of Eqs. 6-11 and the gradient of the
+Tikhonov term with the window of Eqs. 14-15; the loop is the Nesterov
+iteration of Algorithm S1.  Every operation is complex128/float64 and uses
+``scipy.fft`` as the Fourier transform primitive; nothing is blocked or
+fused.
 
 Notation.  ``psi = log x = -mu + i phi`` is the complex phase (Results,
 "Preconditioned Wirtinger flow").  Algorithm S1 reuses the letters phi and mu
@@ -177,7 +180,19 @@ def make_problem(t, geometry, *, alpha: complex = PAPER_ALPHA, gamma: float = PA
     )
 
 
-# --------------------------------------------------------------------------- Algorithm S2
+# --------------------------------------------------------------------------- Eq. 1 as an operator
+#
+# Eq. 1 composes three stages.  The sample's transmission x = exp(psi) passes a
+# linear map A (free-space propagation over L1, multiplication by the diffuser
+# t, free-space propagation over L2); the squared modulus of the detector field
+# is taken; the partially coherent source blurs it with the IPSF, a linear,
+# real and self-adjoint operator B:
+#     f(psi) = B |A exp(psi)|^2.
+# The gradient of the loss of Eq. 2 is the chain rule through these stages:
+# with J the Jacobian of f, the real gradient dL/dRe psi + i dL/dIm psi equals
+# -2 J^T (y - f), and J^T is written out below from the adjoints of A and B.
+# Algorithm S2 evaluates the same expression with the constant factors folded
+# into its normalisation by max|t|^2.
 
 FFT_WORKERS = -1  # scipy.fft threads (-1: all cores); the transform itself is unchanged
 
@@ -193,50 +208,91 @@ def ifft2(a):
 
 
 def filter_(x, w):
-    """Filter: ``F^-1{ F{x} W_k }`` (Algorithm S2)."""
+    """Fourier multiplier ``F^-1{ W_k F{x} }`` (the Filter primitive of Algorithm S2)."""
     return ifft2(fft2(x) * w)
 
 
 def free_propagation(x, prob: Problem, distance_m: float):
-    """FreePropagation over ``distance_m`` (negative distances propagate backwards)."""
+    """Angular-spectrum propagation over ``distance_m`` (FreePropagation).
+
+    The transfer function has unit modulus on propagating bins, so propagation
+    over ``-L`` is the adjoint (and inverse) of propagation over ``L``."""
     return filter_(x, transfer_function(prob.u, prob.v, prob.wavelength_m, distance_m))
 
 
+def detector_field(x, prob: Problem):
+    """``A x = P_L2(t P_L1(x))``: the field at the detector for the sample transmission x."""
+    return free_propagation(prob.t * free_propagation(x, prob, prob.z1_m), prob, prob.z2_m)
+
+
+def detector_field_adjoint(w, prob: Problem):
+    """``A^H w = P_L1^H(conj(t) P_L2^H(w))``, the adjoint of :func:`detector_field`."""
+    return free_propagation(np.conj(prob.t) * free_propagation(w, prob, -prob.z2_m), prob, -prob.z1_m)
+
+
+def source_blur(image, prob: Problem):
+    """``B``: convolution of a real image with the IPSF of Eq. 4, applied as the IOTF window of Eq. 5.
+
+    The window is real and even, so ``B`` maps real images to real images and is self-adjoint."""
+    return np.real(filter_(image, prob.iotf))
+
+
 def physical_model(psi, prob: Problem):
-    """PhysicalModel (Eq. 1): returns ``f, x, v``."""
+    """Eq. 1: ``f = B |A exp(psi)|^2``.  Returns ``f``, ``x = exp(psi)`` and ``v = A x``."""
     x = np.exp(psi)
-    v = free_propagation(x, prob, prob.z1_m)             # sample -> diffuser
-    v = free_propagation(prob.t * v, prob, prob.z2_m)    # diffuser -> detector
-    f = np.real(filter_(np.abs(v) ** 2, prob.iotf))      # IPSF convolution
-    return f, x, v
+    v = detector_field(x, prob)
+    return source_blur(np.abs(v) ** 2, prob), x, v
 
 
-def wirtinger_derivative(e, x, v, prob: Problem):
-    """WirtingerDerivative: back-propagate the misfit ``e = y - f``."""
-    g = np.real(filter_(-e, prob.iotf))
-    g = free_propagation(v * g, prob, -prob.z2_m)
-    g = free_propagation(np.conj(prob.t) * g, prob, -prob.z1_m)
-    g = np.conj(x) * g
-    return g / np.max(np.abs(prob.t) ** 2)
+def model_jvp(psi, dpsi, prob: Problem):
+    """Directional derivative ``J dpsi`` of f at psi along a complex ``dpsi``.
+
+    ``d exp(psi) = x dpsi``, ``dv = A(x dpsi)``, ``d|v|^2 = 2 Re(conj(v) dv)``, then ``B``."""
+    _, x, v = physical_model(psi, prob)
+    dv = detector_field(x * dpsi, prob)
+    return source_blur(2.0 * np.real(np.conj(v) * dv), prob)
 
 
-def preconditioner(g, prob: Problem):
-    """Preconditioner: inverse-Laplacian filter on the phase part ``Im g`` only."""
-    gi = np.imag(g)
-    if prob.precondition:
-        gi = np.real(filter_(gi, prob.p_inv))
-    return np.real(g) + 1j * gi
+def model_vjp(x, v, w, prob: Problem):
+    """``J^T w`` for a real image w: the complex image with ``Re<J^T w, dpsi> = sum_r w_r (J dpsi)_r``.
 
-
-def regularizer(psi, prob: Problem):
-    """Regularizer: ``Re(alpha) Re(rho) + i Im(alpha) Im(rho)``, ``rho = Filter(psi, Gamma^2)``."""
-    rho = filter_(psi, prob.gamma2)
-    return prob.alpha.real * np.real(rho) + 1j * prob.alpha.imag * np.imag(rho)
+    Transposing the three stages of :func:`model_jvp` in reverse order gives
+    ``J^T w = 2 conj(x) A^H(v B w)``."""
+    return 2.0 * np.conj(x) * detector_field_adjoint(v * source_blur(w, prob), prob)
 
 
 def loss(y, f) -> float:
     """Eq. 2: ``sum_r (y_r - f_r)^2``."""
     return float(np.sum((np.asarray(y, np.float64) - f) ** 2))
+
+
+def wirtinger_derivative(e, x, v, prob: Problem):
+    """The gradient ``g`` of Algorithm S2 for the misfit ``e = y - f``.
+
+    The real gradient of Eq. 2 is ``-2 J^T e``; the paper's ``g`` leaves out
+    the factor 4 (2 of the Wirtinger convention, 2 of the squared modulus) and
+    divides by ``max|t|^2``, so ``g = -J^T e / (2 max|t|^2)``."""
+    return -model_vjp(x, v, e, prob) / (2.0 * np.max(np.abs(prob.t) ** 2))
+
+
+def preconditioner(g, prob: Problem):
+    """Eqs. 6-11: the phase part ``Im g`` is smoothed by the inverse Laplacian ``P^-1``
+    (a Fourier multiplier, 0 at DC); the attenuation part ``Re g`` is kept."""
+    phase = np.imag(g)
+    if prob.precondition:
+        phase = np.real(filter_(phase, prob.p_inv))
+    return np.real(g) + 1j * phase
+
+
+def regularizer(psi, prob: Problem):
+    """Real gradient of the Tikhonov term (Results, PWF subsection; Eqs. 14-15).
+
+    ``R = Re(alpha)/2 ||Gamma Re psi||^2 + Im(alpha)/2 ||Gamma Im psi||^2`` with
+    the real, even window ``Gamma^2 = 1 - STF`` has the gradient
+    ``Re(alpha) Gamma^2 * Re psi + i Im(alpha) Gamma^2 * Im psi``."""
+    attenuation = np.real(filter_(np.real(psi), prob.gamma2))
+    phase = np.real(filter_(np.imag(psi), prob.gamma2))
+    return prob.alpha.real * attenuation + 1j * prob.alpha.imag * phase
 
 
 def gradient(psi, y, prob: Problem):
@@ -254,7 +310,7 @@ def nesterov_tau(tau: float) -> float:
 
 
 def field_correlation(psi_a, psi_b) -> float:
-    """Normalised correlation of the fields ``exp(psi_a)`` and ``exp(psi_b)``."""
+    """Normalised correlation ``|<x_a, x_b>| / (|x_a| |x_b|)`` of the fields ``x = exp(psi)``."""
     xa, xb = np.exp(psi_a), np.exp(psi_b)
     num = abs(np.vdot(xa, xb))
     return float(num / math.sqrt(np.vdot(xa, xa).real * np.vdot(xb, xb).real))
@@ -288,13 +344,9 @@ def nesterov_update(psi, z_prev, tau_prev: float, d, eta: float):
 
 def pwf_step(state: PWFState, y, prob: Problem):
     """One iteration of Algorithm S1.  Returns (new state, loss at the entering ``psi``)."""
-    f, x, v = physical_model(state.psi, prob)
-    e = np.asarray(y, np.float64) - f
-    l = float(np.sum(e * e))
+    l, g, d = gradient(state.psi, y, prob)
     if not math.isfinite(l):
         raise FloatingPointError("PWF loss is not finite")
-    g = wirtinger_derivative(e, x, v, prob)
-    d = preconditioner(g, prob) + regularizer(state.psi, prob)
     z, tau, psi = nesterov_update(state.psi, state.z, state.tau, d, prob.eta)
     return PWFState(psi=psi, z=z, tau=tau, k=state.k + 1), l
 
@@ -315,16 +367,6 @@ def pwf(y, prob: Problem, iters: int, corr_tol: float = 0.0, psi0=None, state: P
         if corr_tol > 0 and field_correlation(st.psi, prev) > corr_tol:
             break
     return st.psi, np.array(hist), st
-
-
-# --------------------------------------------------------------------------- linearisation (test aid)
-
-def physical_model_jvp(psi, dpsi, prob: Problem):
-    """Directional derivative of ``f`` at ``psi`` along the complex perturbation ``dpsi``."""
-    x = np.exp(psi)
-    v = free_propagation(prob.t * free_propagation(x, prob, prob.z1_m), prob, prob.z2_m)
-    dv = free_propagation(prob.t * free_propagation(x * dpsi, prob, prob.z1_m), prob, prob.z2_m)
-    return np.real(filter_(2.0 * np.real(np.conj(v) * dv), prob.iotf))
 
 
 # --------------------------------------------------------------------------- joint diffuser refinement
@@ -352,9 +394,13 @@ DEFAULT_ETA_T = 0.5
 
 def diffuser_gradient(e, x, v, prob: Problem):
     """``(conj(u1) a2, max|u1|^2)`` of one projection: the derivative of the loss
-    with respect to ``t*`` and the normalisation of its step."""
-    a2 = free_propagation(v * np.real(filter_(-e, prob.iotf)), prob, -prob.z2_m)
+    with respect to ``t*`` and the normalisation of its step.
+
+    t enters Eq. 1 through ``v = P_L2(t u1)``; the chain rule as in
+    :func:`model_vjp` gives the real gradient ``-4 conj(u1) P_L2^H(v B e)``,
+    i.e. 4 conj(u1) a2 with ``a2 = P_L2^H(v B(-e))``."""
     u1 = free_propagation(x, prob, prob.z1_m)
+    a2 = -free_propagation(v * source_blur(e, prob), prob, -prob.z2_m)
     return np.conj(u1) * a2, float(np.max(np.abs(u1) ** 2))
 
 

@@ -288,16 +288,24 @@ def test_truth_point_has_zero_loss_and_gradient():
 
 
 def test_linearised_model_adjoint():
-    """<J dpsi, w> = Re<J^T w, dpsi> with J^T w = -2 max|t|^2 g(e = w)."""
+    """Dot-product test of the Jacobian: <J dpsi, w> = Re<J^T w, dpsi>, and J^T w = -2 max|t|^2 g(e = w).
+
+    The JVP is checked against central differences of the forward model, so
+    both sides of the adjoint identity are tied to f itself."""
     prob, rng = _small_problem(32, z1_m=5e-3, z2_m=0.2, sigma_x_px=1.5, sigma_y_px=1.0)
     psi = _rand_c(rng, (32, 32), 0.2)
     dpsi = _rand_c(rng, (32, 32))
     w = rng.standard_normal((32, 32))
-    lhs = np.sum(O.physical_model_jvp(psi, dpsi, prob) * w)
+    jv = O.model_jvp(psi, dpsi, prob)
+    h = 1e-6
+    fd = (O.physical_model(psi + h * dpsi, prob)[0] - O.physical_model(psi - h * dpsi, prob)[0]) / (2 * h)
+    assert np.max(np.abs(jv - fd)) <= 1e-7 * np.max(np.abs(jv))
+    lhs = np.sum(jv * w)
     _, x, v = O.physical_model(psi, prob)
-    jt_w = -2.0 * np.max(np.abs(prob.t) ** 2) * O.wirtinger_derivative(w, x, v, prob)
-    rhs = np.real(np.vdot(jt_w, dpsi))
-    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    jt_w = O.model_vjp(x, v, w, prob)
+    assert abs(lhs - np.real(np.vdot(jt_w, dpsi))) <= 1e-12 * abs(lhs)
+    g_w = O.wirtinger_derivative(w, x, v, prob)
+    assert np.max(np.abs(jt_w + 2.0 * np.max(np.abs(prob.t) ** 2) * g_w)) <= 1e-13 * np.max(np.abs(jt_w))
 
 
 def test_gradient_matches_central_differences():
