@@ -35,7 +35,10 @@ SWEEP_BYTES_PER_PX = [24, 16, 24, 16, 20, 12, 20, 16, 24, 16, 24, 40]
 SWEEP_NAMES = ["S0 row psi-update", "S1 col Q_L1", "S2 row x t", "S3 col Q_L2", "S4 row |v|^2",
                "S5 col blur+loss", "S6 row back-blur", "S7 col conj Q_L2", "S8 row x conj t",
                "S9 col conj Q_L1", "S10 row gradient", "S11 col direction+Nesterov"]
-ITER_BYTES_PER_PX = sum(SWEEP_BYTES_PER_PX)   # 256
+ITER_BYTES_PER_PX = sum(SWEEP_BYTES_PER_PX)   # 252
+# the unfused-state schedule the roofline was first stated for (psi written and read, both
+# Nesterov spectra read and written, real intensity spectra in full): reported beside it
+SURVEY_SCHEDULE_BYTES_PER_PX = 280
 
 
 # sources that define the 1024^2 sweep kernels: counters taken before a change to any

@@ -339,10 +339,10 @@ pwf_status pwf_fbp(const void* const* psi, int32_t n_proj, int32_t nx, int32_t n
 size_t pwf_background_workspace_size(int32_t n_slices, int32_t n);
 
 /* Quadratic background removal after tomography (Methods, "Reconstruction
- * procedure": the background area of the tomogram is fitted with a
- * two-dimensional quadratic function, which removes the low-frequency
- * curvature of phase-gradient sensing).  vol: device complex64
- * [n_slices][n][n] (e.g. a pwf_fbp volume, slice-major [y][Z][X]), modified in
+ * procedure"; slow phase variations are weakly constrained by the speckle
+ * data, which leaves a smooth per-slice background in the tomogram).
+ * vol: device complex64 [n_slices][n][n] (e.g. a pwf_fbp volume, slice-major
+ * [y][Z][X]), modified in
  * place.  For every slice, the background area is the set of voxels whose
  * centre lies at distance >= r_bg (voxels) from the rotation axis (the slice
  * centre); the real and imaginary parts are fitted separately by least

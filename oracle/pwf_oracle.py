@@ -583,16 +583,14 @@ def refractive_index(vol, wavelength_m: float, pixel_m: float):
 
 # --------------------------------------------------------------------------- background removal
 #
-# Methods ("Reconstruction procedure"): the low-frequency background curvature
-# of the tomograms (phase-gradient sensing is weak on slow phase variations) is
-# removed by fitting the background area with a two-dimensional quadratic
-# function after the reconstruction.  Readings: the fit is per slice; the
-# background area of a slice is every voxel whose centre lies at a distance
-# >= r_bg (voxels) from the rotation axis, the sample being inside that
-# cylinder; the model is b = c0 + c1 x + c2 z + c3 x^2 + c4 x z + c5 z^2 with
-# x, z the voxel-centre coordinates divided by N/2; the real and imaginary
-# parts are fitted separately by least squares, and the fitted surface is
-# subtracted from the whole slice.
+# Methods ("Reconstruction procedure"): phase-gradient sensing recovers slow
+# phase variations poorly, so each reconstructed slice carries a smooth
+# background, removed after tomography by a quadratic surface fit.  Readings:
+# the fit is per slice, by least squares over the voxels whose centre lies at
+# a distance >= r_bg (voxels) from the rotation axis, the sample being inside
+# that radius; the surface is b = c0 + c1 x + c2 z + c3 x^2 + c4 x z + c5 z^2
+# in the voxel-centre coordinates divided by N/2; real and imaginary parts are
+# fitted separately and the surface is subtracted from the whole slice.
 
 
 def background_basis(n: int) -> np.ndarray:
