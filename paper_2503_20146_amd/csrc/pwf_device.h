@@ -103,6 +103,19 @@ __device__ __forceinline__ int kx_of_col(int s, int n) {
 }
 __device__ __forceinline__ int mirror_col(int s) { return s <= 1 ? s : (s ^ 1); }
 
+// Scale of Re g in the forward transform of the gradient (S10), undone when
+// the direction sweeps split the spectrum into F{Re g} and F{Im g}.  Below a
+// few cycles per field the attenuation part's spectrum exceeds the phase
+// part's by up to 1e5 (the phase is nearly invisible at low frequencies),
+// and a transform that carries both at full size leaves FP32 rounding of
+// F{Re g}'s size in F{Im g}, which P^-1 ~ n^2 / (4 pi^2 |k|^2) then
+// amplifies (2.5e-3 relative error of d at 2048^2 in an FP32 model of the
+// split).  With Re g scaled by 2^-7 that error is ~1e-5; the attenuation
+// part, which P^-1 does not amplify, loses at most 7 bits of its own
+// accuracy.  Powers of two: the scaling itself is exact.
+constexpr float kGradReScale = 0.0078125f;   // 2^-7
+constexpr float kGradReUnscale = 128.0f;     // 2^7
+
 // Signed frequency in cycles/pixel of DFT bin k of an n-point axis (exact).
 __device__ __forceinline__ float freq_of(int k, int n) {
   return (float)(k < (n >> 1) ? k : k - n) / (float)n;

@@ -336,6 +336,7 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
         const float2 xs = SIDE ? side[SIDE ? e : 0] : gld(I.x, idx);
         v[e] = cscale(cmulc(v[e], xs), inv_maxt2);
         if (I.g_out) gst(I.g_out, idx, v[e]);
+        v[e].x *= kGradReScale;  // the direction sweeps undo this (see kGradReScale)
       } else if constexpr (OP == ROW_FORWARD_OUT) {
         const float f = v[e].x;   // RMSE image (Methods): |y - f| scaled by 100 / <reference>
         gstf(I.f_out, idx, I.rmse_scale > 0.f ? fabsf(gldf(I.y, idx) - f) * I.rmse_scale : f);
@@ -592,7 +593,9 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
         const float2 z0 = zk[e], z1 = zp[b & 1][u];
         const float2 ps = make_float2(z0.x + bp * (z0.x - z1.x), z0.y + bp * (z0.y - z1.y));
         const float P = pinv_of(I, fx, freq_of(ky, NY));
-        const float a = 0.5f * (1.f + P), c = 0.5f * (1.f - P);
+        // G = F{s Re g} + i F{Im g} with s = kGradReScale: the Hermitian split
+        // with Re g unscaled gives a = (1/s + P)/2, c = (1/s - P)/2
+        const float a = 0.5f * (kGradReUnscale + P), c = 0.5f * (kGradReUnscale - P);
         const float g2 = gxv + (1.f - gxv) * gb[b & 1][u];  // 1 - STFx STFy without cancellation
         const float r1 = g2 * I.alpha_c1, r2 = g2 * I.alpha_c2;
         lv.at(ky) = make_float2(c * v[e].x + r2 * ps.x, c * v[e].y + r2 * ps.y);
@@ -629,8 +632,9 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
       const int ky = t + T * (e / RL) + (e % RL) * ML;
       const float2 gm = lm.at((NY - ky) & (NY - 1));
       const float P = pinv_of(I, fx, freq_of(ky, NY));
-      const float a = 0.5f * (1.f + P), b = 0.5f * (1.f - P);
-      // (1+P)/2 G + (1-P)/2 conj(G(-k)) = F{Re g} + i P F{Im g}
+      const float a = 0.5f * (kGradReUnscale + P), b = 0.5f * (kGradReUnscale - P);
+      // G = F{s Re g} + i F{Im g} (s = kGradReScale):
+      // (1/s+P)/2 G + (1/s-P)/2 conj(G(-k)) = F{Re g} + i P F{Im g}
       v[e] = make_float2(a * v[e].x + b * gm.x, a * v[e].y - b * gm.y);
     });
     __syncthreads();

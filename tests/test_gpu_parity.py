@@ -103,34 +103,46 @@ def test_forward_special_geometries():
 
 # --------------------------------------------------------------------------- gradient
 
-def direction_tolerance(n: int) -> float:
-    """End-to-end tolerance of d on an n x n grid.
-
-    d's phase part is P^-1 applied to Im g, and P^-1 = s_P / rho^2 (rho in
-    cycles/pixel) reaches s_P n^2 at the lowest frequency.  White FP32 rounding
-    noise of g is amplified in RMS by sqrt(mean_k P_k^2) ~ sqrt(6) s_P n, which
-    grows linearly in n, so the 1e-4 budget that holds at 128^2 scales as n/128.
-    The preconditioner/regulariser arithmetic itself is held to 1e-4 by
-    comparing against the FP64 functions applied to the GPU's own g.
-    """
-    return GRAD_TOL * max(1.0, n / 128.0)
+# End-to-end tolerance of d per case, about twice the error measured on MI355X.
+# d's phase part is P^-1 Im g with P^-1 = s_P / rho^2, which reaches s_P n^2 at the
+# lowest frequency, where the phase part of the gradient is nearly empty: g's FP32
+# error (2.5e-6, 1.5e-6, 6.4e-6 relative) reaches d amplified 2x, 146x and 101x
+# (measured: 5.7e-6, 2.2e-4, 6.5e-4, the same to three digits as the GPU's g pushed
+# through the FP64 preconditioner).  The direction sweep's own arithmetic is held to
+# 1e-4 separately (measured <= 7.6e-6).
+DIRECTION_TOL = {0: 1.5e-5, 1: 5e-4, 4: 1.5e-3}
 
 
-@pytest.mark.parametrize("workload", [0, 1])
+def _direction_case(workload):
+    """(label, geometry, oracle problem, t, psi float32, y) of a gradient-parity case."""
+    if workload == 4:
+        d = S.tomo_projection_inputs(4, [0])
+        geo = d["geometry"]
+        prob = O.make_problem(d["t"], geo)
+        f, _, _ = O.physical_model(d["psi_true"][0], prob)
+        y = S.poisson_intensity(f, d["seed_keys"][0])
+        return "2048^2 projection 0 of 720", geo, prob, d["t"], (0.5 * d["psi_true"][0]).astype(np.complex64), y
+    inp, geo, prob, y = instance(workload)
+    return f"workload {workload} ({geo.nx}^2)", geo, prob, inp["t"], (0.5 * inp["psi_true"]).astype(np.complex64), y
+
+
+@pytest.mark.parametrize("workload", [0, 1, 4])
 def test_gradient_and_direction_parity(workload):
     dev = device()
-    inp, geo, prob, y = instance(workload)
-    say(f"gradient workload {workload}")
-    psi = (0.5 * inp["psi_true"]).astype(np.complex64)
+    label, geo, prob, t, psi, y = _direction_case(workload)
+    say(f"gradient {label}")
     l_ref, g_ref, d_ref = O.gradient(psi.astype(np.complex128), y, prob)
-    batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+    batch = _pwf([gpu_problem(geo, t, dev)])
     loss, g, d = batch.gradient([to_dev(psi, dev)], [to_dev(y, dev)])
     g_gpu, d_gpu = g[0].cpu().numpy(), d[0].cpu().numpy()
-    assert rel(g_gpu, g_ref) <= GRAD_TOL
     # S11 arithmetic: oracle Preconditioner + Regularizer applied to the GPU's g
     d_stage = O.preconditioner(g_gpu.astype(np.complex128), prob) + O.regularizer(psi.astype(np.complex128), prob)
-    assert rel(d_gpu, d_stage) <= GRAD_TOL
-    assert rel(d_gpu, d_ref) <= direction_tolerance(geo.nx)
+    e_g, e_d, e_stage, e_prop = rel(g_gpu, g_ref), rel(d_gpu, d_ref), rel(d_gpu, d_stage), rel(d_stage, d_ref)
+    say(f"gradient {label}: g {e_g:.3e}  d {e_d:.3e}  (g's error through the FP64 preconditioner {e_prop:.3e}, "
+        f"S11 stage {e_stage:.3e})")
+    assert e_g <= GRAD_TOL
+    assert e_stage <= GRAD_TOL
+    assert e_d <= DIRECTION_TOL[workload]
     assert abs(float(loss[0].cpu()) - l_ref) <= 1e-5 * l_ref
 
 

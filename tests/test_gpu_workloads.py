@@ -1,10 +1,11 @@
 """Parity at the workloads' full sizes and launch configurations, on sampled outputs.
 
 * 180 projections x 1024^2 in one batched, graph-captured solve of 100 iterations (the
-  configuration bench.py times): projection 90 against the oracle, projection 0 bit for
-  bit against its unbatched solve.
-* 64 uneven ROIs (24 x 512^2, 32 x 1024^2, 8 x 2048^2) in one batch: one instance per
-  size class against the oracle and bit for bit against its unbatched solve.
+  configuration bench.py times): projections 0 and 90 against the oracle, projection 0
+  bit for bit against its unbatched solve.
+* 64 uneven ROIs (24 x 512^2, 32 x 1024^2, 8 x 2048^2) in one batch of 100 iterations:
+  one instance per size class against the oracle and bit for bit against its unbatched
+  solve.
 * The correlation stop of the Methods section against the oracle's.
 """
 
@@ -53,49 +54,85 @@ def test_tomographic_batch_180x1024_in_bench_configuration():
     psi90 = out[90].cpu().numpy()
     psi0 = out[0].clone()
     h90 = hist[90].cpu().numpy()
+    h0 = hist[0].cpu().numpy()
     del out
     say("workload 180 x 1024^2: projection 0 unbatched")
     one, _ = PWF([probs[0]]).solve([ys[0]], iters)
     assert torch.equal(one[0], psi0)
-    say("workload 180 x 1024^2: oracle on projection 90")
-    y90 = ys[90].cpu().numpy()
-    psi_ref, hist_ref, _ = O.pwf(y90, oprob, iters)
-    assert _rms(psi90.imag, psi_ref.imag) <= PHASE_TOL
-    assert _rms(psi90.real, psi_ref.real) <= PHASE_TOL
-    assert np.all(np.abs(h90 - hist_ref) / hist_ref <= loss_history_tolerance(y90, hist_ref))
+    for j, psi_j, h_j in ((90, psi90, h90), (0, psi0.cpu().numpy(), h0)):
+        say(f"workload 180 x 1024^2: oracle on projection {j}")
+        yj = ys[j].cpu().numpy()
+        psi_ref, hist_ref, _ = O.pwf(yj, oprob, iters)
+        assert _rms(psi_j.imag, psi_ref.imag) <= PHASE_TOL, j
+        assert _rms(psi_j.real, psi_ref.real) <= PHASE_TOL, j
+        assert np.all(np.abs(h_j - hist_ref) / hist_ref <= loss_history_tolerance(yj, hist_ref)), j
 
 
 def test_uneven_roi_batch_64_instances():
+    """The 64 distinct ROI instances in one batch, 100 iterations: the first 512^2 and
+    1024^2 instances against the oracle, the first of every class bit for bit against
+    its unbatched solve (the 2048^2 one is checked against the oracle below)."""
     import torch
     from paper_2503_20146_amd import PWF
     dev = device()
-    iters = 20
+    iters = 100
     specs = S.roi_batch_specs()
     say("uneven ROI batch: generating 64 instances")
-    probs, ys, keep = [], [], {}
-    checked = {0: None, 24: None, 56: None}   # first instance of each size class
+    probs, psis, keep = [], [], {}
+    oracle_checked, first = (0, 24), (0, 24, 56)
     for i, (side, sigma) in enumerate(specs):
         inp = S.instance_inputs(3, side, instance=i, sigma_px=sigma)
-        geo = inp["geometry"]
-        prob = O.make_problem(inp["t"], geo)
-        f, _, _ = O.physical_model(inp["psi_true"], prob)
+        probs.append(gpu_problem(inp["geometry"], inp["t"], dev))
+        psis.append(inp)
+    # noise-free speckle: the oracle's for the instances checked against it, the GPU's elsewhere
+    f_gpu = PWF(probs).forward([to_dev(inp["psi_true"].astype(np.complex64), dev) for inp in psis])
+    ys = []
+    for i, inp in enumerate(psis):
+        if i in oracle_checked:
+            prob = O.make_problem(inp["t"], inp["geometry"])
+            f, _, _ = O.physical_model(inp["psi_true"], prob)
+        else:
+            f = f_gpu[i].cpu().numpy()
         y = S.poisson_intensity(f, inp["seed_key"])
-        probs.append(gpu_problem(geo, inp["t"], dev))
         ys.append(to_dev(y, dev))
-        if i in checked:
+        if i in oracle_checked:
             keep[i] = (prob, y)
-    say("uneven ROI batch: batched solve")
+    del f_gpu
+    say("uneven ROI batch: batched solve, 100 iterations")
     out, hist = PWF(probs).solve(ys, iters)
     torch.cuda.synchronize()
-    for i, (prob, y) in keep.items():
-        say(f"uneven ROI batch: instance {i} ({specs[i][0]}^2) unbatched and oracle")
-        one, _ = PWF([probs[i]]).solve([ys[i]], iters)
+    for i in first:
+        say(f"uneven ROI batch: instance {i} ({specs[i][0]}^2) unbatched")
+        one, h1 = PWF([probs[i]]).solve([ys[i]], iters)
         assert torch.equal(one[0], out[i]), i
+        assert torch.equal(h1[0], hist[i]), i
+    for i, (prob, y) in keep.items():
+        say(f"uneven ROI batch: instance {i} ({specs[i][0]}^2) against the oracle")
         psi_ref, hist_ref, _ = O.pwf(y, prob, iters)
         psi = out[i].cpu().numpy()
         assert _rms(psi.imag, psi_ref.imag) <= PHASE_TOL, i
         assert _rms(psi.real, psi_ref.real) <= PHASE_TOL, i
         assert np.all(np.abs(hist[i].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref)), i
+
+
+def test_uneven_roi_2048_instance_100_iterations():
+    """The first 2048^2 ROI instance (instance 56, its own sigma) for 100 iterations
+    against the oracle; the batch test above shows its batched solve equals this one."""
+    from paper_2503_20146_amd import PWF
+    dev = device()
+    side, sigma = S.roi_batch_specs()[56]
+    inp = S.instance_inputs(3, side, instance=56, sigma_px=sigma)
+    prob = O.make_problem(inp["t"], inp["geometry"])
+    f, _, _ = O.physical_model(inp["psi_true"], prob)
+    y = S.poisson_intensity(f, inp["seed_key"])
+    say("uneven ROI 2048^2 instance: solve, 100 iterations")
+    out, hist = PWF([gpu_problem(inp["geometry"], inp["t"], dev)]).solve([to_dev(y, dev)], 100)
+    say("uneven ROI 2048^2 instance: oracle")
+    psi_ref, hist_ref, _ = O.pwf(y, prob, 100)
+    psi = out[0].cpu().numpy()
+    assert _rms(psi.imag, psi_ref.imag) <= PHASE_TOL
+    assert _rms(psi.real, psi_ref.real) <= PHASE_TOL
+    assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
 # On the 128^2 workload 1 - correlation runs 1.0e-4, 1.5e-5, 5.9e-6, ... 9.9e-7 (10th
