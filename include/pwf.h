@@ -46,7 +46,8 @@ typedef enum {
   PWF_ERR_EVANESCENT = -3, /* lambda / (2 p) >= 1/sqrt(2): evanescent bins */
   PWF_ERR_WORKSPACE = -4,  /* workspace NULL, misaligned or too small */
   PWF_ERR_HIP = -5,        /* a HIP runtime call failed */
-  PWF_ERR_NONFINITE = -6   /* the loss became NaN or Inf on the GPU */
+  PWF_ERR_NONFINITE = -6,  /* the loss became NaN or Inf on the GPU */
+  PWF_ERR_SCRATCH = -7     /* batch too large for the allocation-free variant */
 } pwf_status;
 
 /* Imaging geometry (Results, PWF subsection; Fig. 1a): grid, pixel pitch p at
@@ -163,6 +164,24 @@ pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* cons
 pwf_status pwf_loss_grad(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
                          void* const* grad_out, double* loss_out, void* workspace, size_t workspace_bytes,
                          void* stream);
+
+/* pwf_loss_grad for callers that cannot allocate device memory (code under
+ * stream or graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, bit for bit, with the workspace in a static
+ * buffer of the library instead of caller memory, so there are no workspace
+ * arguments and nothing is allocated.  The buffer is a fixed 64 MiB per GPU
+ * (the first 1 MiB holds the twiddle tables), held from the library's load
+ * until the process ends; a batch needs 4 fields per instance plus small
+ * tables (one 1024^2 instance takes ~32 MiB), at most 64 instances:
+ * pwf_loss_grad_noalloc_limit() returns the bytes available, and larger
+ * batches get PWF_ERR_SCRATCH before any work is queued.  The first call on a
+ * device resolves the buffer's address there and copies the tables in
+ * (synchronously).  Every call on a GPU uses that GPU's one buffer: calls that
+ * overlap on one GPU (on different streams or threads without ordering)
+ * race; calls in one stream are ordered. */
+size_t pwf_loss_grad_noalloc_limit(void);
+pwf_status pwf_loss_grad_noalloc(const pwf_problem* problems, int32_t n, const void* const* psi,
+                                 const float* const* y, void* const* grad_out, double* loss_out, void* stream);
 
 /* Prepare states for pwf_step: psi = psi0 (or 0 when psi0 or psi0[i] is NULL),
  * z = 0, momentum scalar 1, k = 0 (Algorithm S1 initialisation), and the

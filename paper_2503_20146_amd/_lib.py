@@ -15,6 +15,7 @@ PWF_ERR_EVANESCENT = -3
 PWF_ERR_WORKSPACE = -4
 PWF_ERR_HIP = -5
 PWF_ERR_NONFINITE = -6
+PWF_ERR_SCRATCH = -7
 
 
 class pwf_geometry(ctypes.Structure):
@@ -54,6 +55,8 @@ SIGNATURES = {
     "pwf_gradient": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _P(_vp), _P(_vp), _vp, _vp,
                             ctypes.c_size_t, _vp]),
     "pwf_loss_grad": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _P(_vp), _vp, _vp, ctypes.c_size_t, _vp]),
+    "pwf_loss_grad_noalloc": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _P(_vp), _vp, _vp]),
+    "pwf_loss_grad_noalloc_limit": (ctypes.c_size_t, []),
     "pwf_state_init": (_i32, [_P(pwf_problem), _i32, _P(pwf_state), _P(_vp), _P(_vp), _vp, ctypes.c_size_t, _vp]),
     "pwf_step": (_i32, [_P(pwf_problem), _i32, _P(pwf_state), _vp, _vp, ctypes.c_size_t, _vp]),
     "pwf_solve": (_i32, [_P(pwf_problem), _i32, _P(_vp), _P(_vp), _i32, ctypes.c_double, _vp, _P(_i32), _vp,

@@ -218,6 +218,19 @@ class PWF:
               "pwf_loss_grad")
         return loss, grad
 
+    def loss_grad_noalloc(self, psi, y, grad_out=None, loss_out=None):
+        """pwf_loss_grad on the library's static buffer (pwf_loss_grad_noalloc): no
+        workspace is used and, with ``grad_out`` and ``loss_out`` given, nothing is
+        allocated."""
+        grad = self._empty(torch.complex64) if grad_out is None else list(grad_out)
+        loss = torch.empty(self.n, dtype=torch.float64, device=self.device) if loss_out is None else loss_out
+        check(self.lib.pwf_loss_grad_noalloc(self._c, self.n, _ptrs(psi, torch.complex64, self.shapes),
+                                             _ptrs(y, torch.float32, self.shapes),
+                                             _ptrs(grad, torch.complex64, self.shapes),
+                                             ctypes.c_void_p(loss.data_ptr()), _stream(self.device)),
+              "pwf_loss_grad_noalloc")
+        return loss, grad
+
     def solve_plain(self, y: torch.Tensor, iters: int, psi_out=None, loss_hist: bool = True):
         if self.n != 1:
             raise ValueError("the plain path runs one instance")

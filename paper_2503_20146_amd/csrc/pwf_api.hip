@@ -143,42 +143,71 @@ pwf_status hip_fail(hipError_t e) { return e == hipSuccess ? PWF_OK : PWF_ERR_HI
     if (e_ != hipSuccess) return PWF_ERR_HIP;      \
   } while (0)
 
+// Immutable tables of a device, built on the host in FP64 and rounded: the
+// twiddles of every row, column and alternative-row plan and w_N^m of every
+// supported side, and the momentum table.  `emit` receives each table and
+// returns where it will live on the device.
+struct HostTables {
+  std::vector<float2> plan[5][3];  // which = 0 row, 1 column, 2 alternative row
+  std::vector<float2> twn[5];
+  std::vector<double> beta;
+};
+
+const HostTables& host_tables() {
+  static const HostTables T = [] {
+    HostTables h;
+    for (int i = 0; i < 5; ++i) {
+      for (int which = 0; which < 3; ++which) {
+        const int cnt = pwf::plan_twiddles(kSizes[i], which, nullptr);
+        h.plan[i][which].assign(std::max(cnt, 1), make_float2(0.f, 0.f));
+        pwf::plan_twiddles(kSizes[i], which, h.plan[i][which].data());
+      }
+      const int n = kSizes[i];
+      h.twn[i].resize(n);
+      for (int m = 0; m < n; ++m) {
+        const double ang = -2.0 * M_PI * (double)m / (double)n;
+        h.twn[i][m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      }
+    }
+    // beta_k = (tau_k - 1) / tau_{k+1}, tau_0 = 1, tau_{k+1} = (1 + sqrt(1 + 4 tau_k^2)) / 2
+    h.beta.resize(kBetaCap);
+    double tau = 1.0;
+    for (int k = 0; k < kBetaCap; ++k) {
+      const double nt = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
+      h.beta[k] = (tau - 1.0) / nt;
+      tau = nt;
+    }
+    return h;
+  }();
+  return T;
+}
+
+#define PWF_TRY(x)                      \
+  do {                                  \
+    const pwf_status s_ = (x);          \
+    if (s_ != PWF_OK) return s_;        \
+  } while (0)
+
 pwf_status context_for_current(Context** out) {
   int dev = 0;
   PWF_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDevices) return PWF_ERR_HIP;
   Context& c = g_ctx[dev];
   if (!c.ready) {
+    const HostTables& h = host_tables();
+    auto put = [](const auto& host, auto** dst) -> pwf_status {
+      const size_t bytes = sizeof(host[0]) * host.size();
+      PWF_HIP(hipMalloc((void**)dst, bytes));
+      PWF_HIP(hipMemcpy(*dst, host.data(), bytes, hipMemcpyHostToDevice));
+      return PWF_OK;
+    };
     for (int i = 0; i < 5; ++i) {
-      for (int which = 0; which < 3; ++which) {
-        float2*& dst = which == 0 ? c.tw[i] : which == 1 ? c.twc[i] : c.twa[i];
-        const int cnt = pwf::plan_twiddles(kSizes[i], which, nullptr);
-        std::vector<float2> host(std::max(cnt, 1));
-        pwf::plan_twiddles(kSizes[i], which, host.data());
-        PWF_HIP(hipMalloc(&dst, sizeof(float2) * std::max(cnt, 1)));
-        PWF_HIP(hipMemcpy(dst, host.data(), sizeof(float2) * std::max(cnt, 1), hipMemcpyHostToDevice));
-      }
+      PWF_TRY(put(h.plan[i][0], &c.tw[i]));
+      PWF_TRY(put(h.plan[i][1], &c.twc[i]));
+      PWF_TRY(put(h.plan[i][2], &c.twa[i]));
+      PWF_TRY(put(h.twn[i], &c.twn[i]));
     }
-    for (int i = 0; i < 5; ++i) {
-      const int n = kSizes[i];
-      std::vector<float2> host(n);
-      for (int m = 0; m < n; ++m) {
-        const double ang = -2.0 * M_PI * (double)m / (double)n;
-        host[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-      }
-      PWF_HIP(hipMalloc(&c.twn[i], sizeof(float2) * n));
-      PWF_HIP(hipMemcpy(c.twn[i], host.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
-    }
-    // beta_k = (tau_k - 1) / tau_{k+1}, tau_0 = 1, tau_{k+1} = (1 + sqrt(1 + 4 tau_k^2)) / 2
-    std::vector<double> b(kBetaCap);
-    double tau = 1.0;
-    for (int k = 0; k < kBetaCap; ++k) {
-      const double nt = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
-      b[k] = (tau - 1.0) / nt;
-      tau = nt;
-    }
-    PWF_HIP(hipMalloc(&c.beta, sizeof(double) * kBetaCap));
-    PWF_HIP(hipMemcpy(c.beta, b.data(), sizeof(double) * kBetaCap, hipMemcpyHostToDevice));
+    PWF_TRY(put(h.beta, &c.beta));
     PWF_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
     PWF_HIP(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
     PWF_HIP(hipEventCreateWithFlags(&c.ev_out, hipEventDisableTiming));
@@ -322,6 +351,41 @@ Layout make_layout(const pwf_problem* probs, int n, bool joint = false) {
   return L;
 }
 
+// Layout of only the regions pwf_loss_grad uses (status, descriptors, loss
+// partials, window tables and four fields per instance: W, v, x, y_hat), for
+// the allocation-free variant whose buffer has a fixed size.
+Layout make_loss_grad_layout(const pwf_problem* probs, int n) {
+  Layout L;
+  size_t off = 0;
+  L.status = off;
+  off += kAlign;
+  L.maxt2 = off;
+  off += align_up(sizeof(float) * n);
+  L.desc = off;
+  off += align_up(sizeof(Inst) * n);
+  L.part.resize(n);
+  L.partials = off;
+  for (int i = 0; i < n; ++i) {
+    L.part[i] = off;
+    const int narrow = std::min(pwf::col_default_width(probs[i].geom.ny), pwf::col_alt_width(probs[i].geom.ny));
+    off += align_up(sizeof(double) * (probs[i].geom.nx / narrow));
+  }
+  L.tables.resize(n);
+  for (int i = 0; i < n; ++i) {
+    L.tables[i] = off;
+    off += table_bytes(probs[i]);
+  }
+  for (std::vector<size_t>* r : {&L.W, &L.v, &L.psi, &L.y_hat}) {
+    r->resize(n);
+    for (int i = 0; i < n; ++i) {
+      (*r)[i] = off;
+      off += field_bytes(probs[i]);
+    }
+  }
+  L.total = off;
+  return L;
+}
+
 // ------------------------------------------------------------------ descriptors
 
 Inst base_inst(const pwf_problem& p) {
@@ -448,12 +512,6 @@ struct Launcher {
   }
 };
 
-#define PWF_TRY(x)                      \
-  do {                                  \
-    const pwf_status s_ = (x);          \
-    if (s_ != PWF_OK) return s_;        \
-  } while (0)
-
 pwf_status check_ws(const pwf_problem* probs, int n, void* ws, size_t ws_bytes, Layout* out, bool joint = false) {
   if (!ws || ((uintptr_t)ws % kAlign) != 0) return PWF_ERR_WORKSPACE;
   *out = make_layout(probs, n, joint);
@@ -497,6 +555,7 @@ const char* pwf_status_string(int32_t s) {
     case PWF_ERR_WORKSPACE: return "workspace missing, misaligned (256 B) or too small";
     case PWF_ERR_HIP: return "HIP runtime error";
     case PWF_ERR_NONFINITE: return "non-finite loss (NaN or Inf) on the GPU";
+    case PWF_ERR_SCRATCH: return "batch does not fit the static scratch buffer of pwf_loss_grad_noalloc (64 MiB, 64 instances)";
     default: return "unknown status";
   }
 }
@@ -560,6 +619,59 @@ pwf_status forward_impl(const pwf_problem* problems, int32_t n, const void* cons
   PWF_TRY(K.row(pwf::ROW_INTENSITY));
   PWF_TRY(K.col(pwf::COL_BLUR));
   PWF_TRY(K.row(pwf::ROW_FORWARD_OUT));
+  return PWF_OK;
+}
+
+// pwf_loss_grad (and its allocation-free variant): argument checks, the
+// descriptors at the regions of a layout, and the launch sequence.
+pwf_status validate_loss_grad(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
+                              void* const* grad_out) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!psi || !y || !grad_out) return PWF_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!psi[i] || !y[i] || !grad_out[i]) return PWF_ERR_ARG;
+  return PWF_OK;
+}
+
+void loss_grad_descriptors(const pwf_problem* problems, int32_t n, const Batch& B, const void* const* psi,
+                           const float* const* y, void* const* grad_out, double* loss_out, char* ws,
+                           const Layout& L, Inst* desc) {
+  for (int s = 0; s < n; ++s) {
+    const int i = B.order[s];
+    Inst& I = desc[s];
+    I = base_inst(problems[i]);
+    attach_tables(I, ws, L, i);
+    I.W = (float2*)(ws + L.W[i]);
+    I.v = (float2*)(ws + L.v[i]);
+    I.x = (float2*)(ws + L.psi[i]);
+    I.psi_src = (const float2*)psi[i];
+    I.y_hat = (float2*)(ws + L.y_hat[i]);
+    I.y = y[i];
+    I.g_out = (float2*)grad_out[i];
+    I.grad_mul = 4.0f;  // dL/dRe psi + i dL/dIm psi = 4 x* P1+(t* P2+(v Filter(-e)))
+    I.maxt2 = (const float*)(ws + L.maxt2);
+    I.loss_partial = (double*)(ws + L.part[i]);
+    I.loss_dst = loss_out ? loss_out + i : nullptr;
+  }
+}
+
+// After the descriptors are in place: window tables, spectrum of y, forward
+// model, loss and the back-propagated gradient.
+pwf_status loss_grad_sequence(const Launcher& K, int32_t n) {
+  PWF_HIP(pwf::launch_build_tables((const Inst*)(K.ws + K.L.desc), n, K.st));
+  PWF_TRY(K.row(pwf::ROW_REAL_FFT));
+  PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
+  PWF_TRY(K.row(pwf::ROW_START));
+  PWF_TRY(K.col(pwf::COL_CHIRP1));
+  PWF_TRY(K.row(pwf::ROW_MUL_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP2));
+  PWF_TRY(K.row(pwf::ROW_INTENSITY));
+  PWF_TRY(K.col(pwf::COL_BLUR_LOSS));
+  PWF_TRY(K.row(pwf::ROW_BACKBLUR));
+  PWF_TRY(K.col(pwf::COL_CHIRP2_CONJ));
+  PWF_TRY(K.row(pwf::ROW_MUL_CONJ_T));
+  PWF_TRY(K.col(pwf::COL_CHIRP1_CONJ));
+  PWF_TRY(K.row(pwf::ROW_GRAD));
   return PWF_OK;
 }
 }  // namespace
@@ -647,10 +759,7 @@ pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* cons
 pwf_status pwf_loss_grad(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
                          void* const* grad_out, double* loss_out, void* workspace, size_t workspace_bytes,
                          void* stream) {
-  PWF_TRY(validate_batch(problems, n));
-  if (!psi || !y || !grad_out) return PWF_ERR_ARG;
-  for (int i = 0; i < n; ++i)
-    if (!psi[i] || !y[i] || !grad_out[i]) return PWF_ERR_ARG;
+  PWF_TRY(validate_loss_grad(problems, n, psi, y, grad_out));
   Layout L;
   PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
   std::lock_guard<std::mutex> lk(g_mu);
@@ -660,41 +769,10 @@ pwf_status pwf_loss_grad(const pwf_problem* problems, int32_t n, const void* con
   char* ws = (char*)workspace;
   const Batch B = group(problems, n);
   std::vector<Inst> desc(n);
-  for (int s = 0; s < n; ++s) {
-    const int i = B.order[s];
-    Inst& I = desc[s];
-    I = base_inst(problems[i]);
-    attach_tables(I, ws, L, i);
-    I.W = (float2*)(ws + L.W[i]);
-    I.v = (float2*)(ws + L.v[i]);
-    I.x = (float2*)(ws + L.psi[i]);
-    I.psi_src = (const float2*)psi[i];
-    I.y_hat = (float2*)(ws + L.y_hat[i]);
-    I.y = y[i];
-    I.g_out = (float2*)grad_out[i];
-    I.grad_mul = 4.0f;  // dL/dRe psi + i dL/dIm psi = 4 x* P1+(t* P2+(v Filter(-e)))
-    I.maxt2 = (const float*)(ws + L.maxt2);
-    I.loss_partial = (double*)(ws + L.part[i]);
-    I.loss_dst = loss_out ? loss_out + i : nullptr;
-  }
+  loss_grad_descriptors(problems, n, B, psi, y, grad_out, loss_out, ws, L, desc.data());
   PWF_HIP(pwf::launch_fill_zero(ws + L.status, 16, st));
   PWF_TRY(upload(*ctx, desc.data(), sizeof(Inst) * n, ws + L.desc, st));
-  PWF_HIP(pwf::launch_build_tables((const Inst*)(ws + L.desc), n, st));
-  const Launcher K{*ctx, ws, L, B, st};
-  PWF_TRY(K.row(pwf::ROW_REAL_FFT));
-  PWF_TRY(K.col(pwf::COL_SPEC_YHAT));
-  PWF_TRY(K.row(pwf::ROW_START));
-  PWF_TRY(K.col(pwf::COL_CHIRP1));
-  PWF_TRY(K.row(pwf::ROW_MUL_T));
-  PWF_TRY(K.col(pwf::COL_CHIRP2));
-  PWF_TRY(K.row(pwf::ROW_INTENSITY));
-  PWF_TRY(K.col(pwf::COL_BLUR_LOSS));
-  PWF_TRY(K.row(pwf::ROW_BACKBLUR));
-  PWF_TRY(K.col(pwf::COL_CHIRP2_CONJ));
-  PWF_TRY(K.row(pwf::ROW_MUL_CONJ_T));
-  PWF_TRY(K.col(pwf::COL_CHIRP1_CONJ));
-  PWF_TRY(K.row(pwf::ROW_GRAD));
-  return PWF_OK;
+  return loss_grad_sequence(Launcher{*ctx, ws, L, B, st}, n);
 }
 
 pwf_status pwf_state_init(const pwf_problem* problems, int32_t n, pwf_state* states, const void* const* psi0,
@@ -1674,6 +1752,99 @@ pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int3
   // Eq. 16: shell cross-correlation over the geometric mean of the shell powers
   for (int s = 0; s < nsh; ++s) fsc_out[s] = h[s] / std::sqrt(h[nsh + s] * h[2 * nsh + s]);
   return PWF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ allocation-free variant
+//
+// pwf_loss_grad_noalloc runs pwf_loss_grad's kernels with its workspace in a
+// file-scope device array instead of caller memory.  Each device holds its own
+// copy of the array, at its own address, from the library's load until the
+// process ends.  The array's name is only a host-side stand-in for that
+// memory: host code uses the address that hipGetSymbolAddress returns for the
+// current device (kept per device at the first call there) and nothing else.
+// The first kScratchTableBytes hold the immutable twiddle tables, copied in
+// once per device at that first call; the rest is the per-call workspace.
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchTableBytes = size_t(1) << 20;
+constexpr int kScratchMaxInst = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchDevice {
+  bool ready = false;
+  char* base = nullptr;          // device address of `scratch` on this device
+  Context tables;                // table pointers into base (no streams, events or graphs)
+  hipEvent_t copied = nullptr;   // recorded after the last descriptor copy from host_desc
+  Inst host_desc[kScratchMaxInst];
+};
+ScratchDevice g_scratch[kMaxDevices];
+
+// Set-up of the current device, once: the array's address, the tables, the event.
+pwf_status scratch_for_current(ScratchDevice** out) {
+  int dev = 0;
+  PWF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return PWF_ERR_HIP;
+  ScratchDevice& d = g_scratch[dev];
+  if (!d.ready) {
+    void* p = nullptr;
+    PWF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return PWF_ERR_HIP;
+    char* base = (char*)p;
+    const HostTables& h = host_tables();
+    size_t off = 0;
+    auto put = [&](const std::vector<float2>& host, float2** dst) -> pwf_status {
+      const size_t bytes = sizeof(float2) * host.size();
+      if (off + bytes > kScratchTableBytes) return PWF_ERR_HIP;
+      PWF_HIP(hipMemcpy(base + off, host.data(), bytes, hipMemcpyHostToDevice));
+      *dst = (float2*)(base + off);
+      off = align_up(off + bytes);
+      return PWF_OK;
+    };
+    for (int i = 0; i < 5; ++i) {
+      PWF_TRY(put(h.plan[i][0], &d.tables.tw[i]));
+      PWF_TRY(put(h.plan[i][1], &d.tables.twc[i]));
+      PWF_TRY(put(h.plan[i][2], &d.tables.twa[i]));
+      PWF_TRY(put(h.twn[i], &d.tables.twn[i]));
+    }
+    PWF_HIP(hipEventCreateWithFlags(&d.copied, hipEventDisableTiming));
+    d.base = base;
+    d.tables.ready = true;
+    d.ready = true;
+  }
+  *out = &d;
+  return PWF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pwf_loss_grad_noalloc_limit(void) { return kScratchBytes - kScratchTableBytes; }
+
+pwf_status pwf_loss_grad_noalloc(const pwf_problem* problems, int32_t n, const void* const* psi,
+                                 const float* const* y, void* const* grad_out, double* loss_out, void* stream) {
+  PWF_TRY(validate_loss_grad(problems, n, psi, y, grad_out));
+  if (n > kScratchMaxInst) return PWF_ERR_SCRATCH;
+  const Layout L = make_loss_grad_layout(problems, n);
+  if (L.total > kScratchBytes - kScratchTableBytes) return PWF_ERR_SCRATCH;
+  std::lock_guard<std::mutex> lk(g_mu);
+  ScratchDevice* d;
+  PWF_TRY(scratch_for_current(&d));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = d->base + kScratchTableBytes;
+  const Batch B = group(problems, n);
+  // the previous call's copy must have read host_desc before it is rewritten
+  PWF_HIP(hipEventSynchronize(d->copied));
+  loss_grad_descriptors(problems, n, B, psi, y, grad_out, loss_out, ws, L, d->host_desc);
+  PWF_HIP(pwf::launch_fill_zero(ws + L.status, 16, st));
+  PWF_HIP(hipMemcpyAsync(ws + L.desc, d->host_desc, sizeof(Inst) * n, hipMemcpyHostToDevice, st));
+  PWF_HIP(hipEventRecord(d->copied, st));
+  return loss_grad_sequence(Launcher{d->tables, ws, L, B, st}, n);
 }
 
 pwf_status pwf_sync_status(void* workspace, void* stream) {

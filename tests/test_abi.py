@@ -44,7 +44,7 @@ def test_binding_covers_header():
 
 def test_status_strings(lib):
     from paper_2503_20146_amd import _lib
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = lib.pwf_status_string(code).decode()
         assert s and s != "unknown status"
     assert lib.pwf_status_string(42).decode() == "unknown status"
@@ -137,6 +137,26 @@ def test_bad_workspace_and_pointers(lib):
     assert lib.pwf_solve(arr, 1, ptrs, ptrs, 5, float("nan"), None, None, ctypes.c_void_p(0x100000), size,
                          None) == -1
     assert lib.pwf_sync_status(ctypes.c_void_p(0x100001), None) == -4
+
+
+def test_noalloc_limits_checked_before_any_gpu_work(lib):
+    """pwf_loss_grad_noalloc: batches beyond its static buffer (63 MiB of workspace, 64
+    instances) and null pointers are refused on the host."""
+    from paper_2503_20146_amd import _lib
+    assert lib.pwf_loss_grad_noalloc_limit() == 63 << 20
+    two = (_lib.pwf_problem * 2)(_problem(1024, 1024), _problem(1024, 1024))
+    ptrs2 = (ctypes.c_void_p * 2)(0x2000, 0x3000)
+    assert lib.pwf_loss_grad_noalloc(two, 2, ptrs2, ptrs2, ptrs2, None, None) == _lib.PWF_ERR_SCRATCH
+    many = (_lib.pwf_problem * 65)(*[_problem() for _ in range(65)])
+    ptrs65 = (ctypes.c_void_p * 65)(*([0x2000] * 65))
+    assert lib.pwf_loss_grad_noalloc(many, 65, ptrs65, ptrs65, ptrs65, None, None) == _lib.PWF_ERR_SCRATCH
+    one = (_lib.pwf_problem * 1)(_problem())
+    null = (ctypes.c_void_p * 1)(None)
+    ptrs1 = (ctypes.c_void_p * 1)(0x2000)
+    assert lib.pwf_loss_grad_noalloc(one, 1, ptrs1, ptrs1, null, None, None) == _lib.PWF_ERR_ARG
+    assert lib.pwf_loss_grad_noalloc(one, 1, None, ptrs1, ptrs1, None, None) == _lib.PWF_ERR_ARG
+    bad = (_lib.pwf_problem * 1)(_problem(100, 128))
+    assert lib.pwf_loss_grad_noalloc(bad, 1, ptrs1, ptrs1, ptrs1, None, None) == _lib.PWF_ERR_SIZE
 
 
 def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
