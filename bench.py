@@ -213,7 +213,8 @@ def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
     t_cal = time.perf_counter() - t0
     sec_t = time_events(lambda: diffuser_from_reference(probs[0], ref, 1e-3))
     res["calibration"] = {"coherence_ms": round(t_cal * 1e3, 3), "diffuser_ms": round(sec_t * 1e3, 3),
-                          "sigma_px_fitted": [round(cal["sigma_x_px"], 3), round(cal["sigma_y_px"], 3)],
+                          "coherence_um_fitted": [round(cal["x_coh_m"] * 1e6, 3), round(cal["y_coh_m"] * 1e6, 3)],
+                          "coherence_um_of_the_blur": round(2.0 * math.sqrt(math.pi) * geo.sigma_x_px * geo.pixel_m * 1e6, 3),
                           "config": "one 1024^2 reference speckle, shifts 0..32"}
     print(f"[bench] calibration {res['calibration']}", file=sys.stderr, flush=True)
     # tomography of the retrieved projections
@@ -272,45 +273,91 @@ def secondary_measurements(batch, ys, out, probs, geo, d, dev) -> dict:
     return res
 
 
-def share_2048(dev) -> dict:
-    """One GPU's share of the 720 x 2048^2 workload over 16 GPUs: 45 projections (8
-    distinct projections of that workload's phantom, repeated, noise-free), autotuned,
-    one 20-iteration solve timed after a warm-up."""
+def device_poisson(f, seed: int):
+    """Flat-field-normalised Poisson counts of the noise-free speckle f (a GPU tensor), drawn
+    on the device from a seeded generator (1e4 photons per pixel of unit flat field)."""
+    import torch
+    gen = torch.Generator(device=f.device)
+    gen.manual_seed(seed)
+    return torch.poisson(f.clamp(min=0.0) * 1.0e4, generator=gen).div_(1.0e4)
+
+
+def workload_720x2048(dev, iters: int) -> dict:
+    """The 720 x 2048^2 workload at its full size on one GPU: 720 projections of the 2048^3
+    ellipsoid phantom over 0-180 deg (generated on the device), one shared 2048^2 diffuser,
+    sigma 1.5 px, Poisson noise at 1e4 photons/px on the GPU forward model.  Timed: an
+    autotuned pwf_solve of `iters` iterations on all 720 projections, and one forward and
+    one backward of the differentiable loss (PWFLoss: the backward recomputes the forward
+    fields) at the retrieved psi."""
     import numpy as np
     import torch
 
     import synthetic as S
-    from paper_2503_20146_amd import PWF, problem_from_geometry
+    from paper_2503_20146_amd import PWF, problem_from_geometry, pwf_loss
 
-    d = S.tomo_projection_inputs(4, range(0, 720, 90))
+    n, side = 720, 2048
+    d = S.tomo_projection_inputs(4, [])
     geo = d["geometry"]
     t = torch.from_numpy(d["t"]).to(dev)
-    n, iters = 45, 20
-    batch = PWF([problem_from_geometry(geo, t) for _ in range(n)])
-    distinct = [torch.from_numpy(p.astype(np.complex64)).to(dev) for p in d["psi_true"]]
-    f = batch.forward([distinct[j % len(distinct)] for j in range(n)])
-    ys = [f[j] for j in range(n)]
-    tiles = autotune(batch)
-    batch.solve(ys, 2, loss_hist=False)
+    phantom = S.ellipsoid_phantom(side, 40, (S.BASE_SEED + 2,), 2.0)
+    psi = torch.empty((n, side, side), dtype=torch.complex64, device=dev)
+    t0 = time.perf_counter()
+    S.project_ellipsoids_device(phantom, [math.pi * j / n for j in range(n)], side, side, geo.pixel_m,
+                                geo.wavelength_m, psi)
     torch.cuda.synchronize()
-    sec = time_events(lambda: batch.solve(ys, iters, loss_hist=False))
+    print(f"[bench] 720 x 2048^2: projections generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    batch = PWF([problem_from_geometry(geo, t) for _ in range(n)])
+    views = [psi[j] for j in range(n)]
+    ys = batch.forward(views)
+    for j in range(n):
+        ys[j] = device_poisson(ys[j], S.BASE_SEED + 4 + j)
+    torch.cuda.synchronize()
+    tiles = autotune(batch)
+    print(f"[bench] 720 x 2048^2: workspace {batch.workspace.numel() / 2**30:.1f} GiB, tiles {tiles}",
+          file=sys.stderr, flush=True)
+    batch.solve(ys, 2, psi_out=views, loss_hist=False)
+    torch.cuda.synchronize()
+    sec = time_events(lambda: batch.solve(ys, iters, psi_out=views, loss_hist=True))
+    status = batch.sync_status()
     value = n * iters / sec
-    roof = HBM_PEAK_GBS * 1e9 / (ITER_BYTES_PER_PX * geo.nx * geo.ny)
-    res = {"value": round(value, 1), "unit": "proj-iter/s", "iteration_frac_of_hbm_roofline": round(value / roof, 4),
-           "column_tiles_S1_S3_S5_S7_S9_S11": tiles.get(2048),
-           "config": f"{n} x 2048^2 (8 distinct projections of the 720 x 2048^2 phantom), {iters} iterations"}
-    del batch, ys, f, distinct
+    roof = HBM_PEAK_GBS * 1e9 / (ITER_BYTES_PER_PX * side * side)
+    print(f"[bench] 720 x 2048^2: {value:.1f} proj-iter/s", file=sys.stderr, flush=True)
+    # differentiable loss at the retrieved psi: forward (model + misfit), backward (recomputed fields)
+    p = psi.requires_grad_(True)
+    torch.cuda.synchronize()
+    a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    a.record()
+    loss = pwf_loss(p, batch, ys)
+    b.record()
+    loss.sum().backward()
+    c.record()
+    c.synchronize()
+    fwd_ms, bwd_ms = a.elapsed_time(b), b.elapsed_time(c)
+    finite = bool(torch.isfinite(loss).all()) and bool(torch.isfinite(p.grad).all())
+    res = {"value": round(value, 1), "unit": "proj-iter/s",
+           "iteration_frac_of_hbm_roofline": round(value / roof, 4),
+           "iteration_ms": round(sec / iters * 1e3, 2),
+           "column_tiles_S1_S3_S5_S7_S9_S11": tiles.get(side),
+           "row_plans_S0_S2_S4_S6_S8_S10": [batch.lib.pwf_row_plan(side, s) for s in range(0, 12, 2)],
+           "autograd": {"forward_ms": round(fwd_ms, 1), "backward_ms": round(bwd_ms, 1),
+                        "backward_proj_per_s": round(n / (bwd_ms / 1e3), 1), "finite": finite},
+           "nonfinite_flag": status != 0,
+           "workspace_gib": round(batch.workspace.numel() / 2 ** 30, 1),
+           "config": f"{n} x {side}^2 projections of the 2048^3 40-ellipsoid phantom over 0-180 deg (generated on "
+                     f"the device), shared diffuser, {iters} iterations in one hipGraph; PWFLoss forward and "
+                     "backward over all 720"}
+    del batch, ys, psi, p, views, loss
     torch.cuda.empty_cache()
-    print(f"[bench] 2048 share {res}", file=sys.stderr, flush=True)
+    print(f"[bench] 720 x 2048^2 {res}", file=sys.stderr, flush=True)
     return res
 
 
-def uneven_batch(dev) -> dict:
-    """The uneven ROI batch (24 x 512^2, 32 x 1024^2, 8 x 2048^2, IPSF sigma per instance):
-    one instance's fields per size class, repeated, noise-free; autotuned; one 50-iteration
-    solve timed after a warm-up."""
-    import dataclasses
-
+def uneven_batch(dev, iters: int = 50) -> dict:
+    """The uneven ROI batch: 64 distinct generated instances (24 x 512^2, 32 x 1024^2,
+    8 x 2048^2, each with its own phase object, diffuser and IPSF sigma), the noise-free
+    speckle from the GPU forward model with device Poisson noise; autotuned; one solve of
+    `iters` iterations timed after a warm-up."""
     import numpy as np
     import torch
 
@@ -318,27 +365,24 @@ def uneven_batch(dev) -> dict:
     from paper_2503_20146_amd import PWF, problem_from_geometry
 
     specs = S.roi_batch_specs()
-    first = {}
+    probs, psis = [], []
     for i, (side, sigma) in enumerate(specs):
-        if side not in first:
-            first[side] = S.instance_inputs(3, side, instance=i, sigma_px=sigma)
-    diffusers = {side: torch.from_numpy(inp["t"]).to(dev) for side, inp in first.items()}
-    batch = PWF([problem_from_geometry(dataclasses.replace(first[side]["geometry"], sigma_x_px=sigma, sigma_y_px=sigma),
-                                       diffusers[side]) for side, sigma in specs])
-    psis = {side: torch.from_numpy(inp["psi_true"].astype(np.complex64)).to(dev) for side, inp in first.items()}
-    f = batch.forward([psis[side] for side, _ in specs])
-    ys = [f[j] for j in range(len(specs))]
+        inp = S.instance_inputs(3, side, instance=i, sigma_px=sigma)
+        probs.append(problem_from_geometry(inp["geometry"], torch.from_numpy(inp["t"]).to(dev)))
+        psis.append(torch.from_numpy(inp["psi_true"].astype(np.complex64)).to(dev))
+    batch = PWF(probs)
+    f = batch.forward(psis)
+    ys = [device_poisson(f[j], S.BASE_SEED + 3000 + j) for j in range(len(specs))]
+    del f, psis
     autotune(batch)
-    iters = 50
     batch.solve(ys, 2, loss_hist=False)
     torch.cuda.synchronize()
     sec = time_events(lambda: batch.solve(ys, iters, loss_hist=False))
     px = sum(side * side for side, _ in specs)
     frac = px * iters / sec * ITER_BYTES_PER_PX / (HBM_PEAK_GBS * 1e9)
     res = {"iteration_ms": round(sec / iters * 1e3, 3), "iteration_frac_of_hbm_roofline": round(frac, 4),
-           "config": "24 x 512^2 + 32 x 1024^2 + 8 x 2048^2 (one instance's inputs per size class, repeated), "
-                     f"{iters} iterations, size classes on parallel streams"}
-    del batch, ys, f, psis, diffusers
+           "config": f"24 x 512^2 + 32 x 1024^2 + 8 x 2048^2, 64 distinct instances, {iters} iterations"}
+    del batch, ys, probs
     torch.cuda.empty_cache()
     print(f"[bench] uneven batch {res}", file=sys.stderr, flush=True)
     return res
@@ -360,6 +404,7 @@ def cpu_baseline(iters: int):
 
     import oracle as O
     import synthetic as S
+    # threads: OMP_NUM_THREADS if set (16 on the GPU machine), else every core, at most 16
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     threads = max(1, min(threads, 16))
     O.FFT_WORKERS = threads
@@ -391,7 +436,8 @@ def cpu_baseline(iters: int):
             "sample": f"1 projection of 1024^2 (projection 0 of the workload), {iters} iterations of the "
                       f"FP64 scipy.fft oracle after 1 warm-up iteration, {dt:.1f} s",
             "single_thread": {"value": it1 / dt1, "sample": f"{it1} further iterations on 1 thread, {dt1:.1f} s"},
-            "cpu_model": model}
+            "cpu_model": model, "cpu_count": os.cpu_count(),
+            "threads_note": "scipy.fft workers = OMP_NUM_THREADS (else all cores), capped at 16"}
 
 
 def main() -> int:
@@ -414,6 +460,10 @@ def main() -> int:
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs of a --sweep-only all run "
                          "into profiles/traffic_counters.json and exit")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--iters-2048", type=int, default=10,
+                    help="iterations of the timed 720 x 2048^2 solve (extras)")
+    ap.add_argument("--workload", choices=["720x2048", "uneven"], default=None,
+                    help="only run this secondary workload and print its record (profiling runs)")
     ap.add_argument("--col-tile", type=int, default=0,
                     help="fix the column-tile width at 1024 instead of autotuning (counter runs)")
     args = ap.parse_args()
@@ -429,6 +479,12 @@ def main() -> int:
 
     import torch
     dev = torch.device("cuda:0")
+    if args.workload == "720x2048":
+        print(json.dumps(workload_720x2048(dev, args.iters_2048)), flush=True)
+        return 0
+    if args.workload == "uneven":
+        print(json.dumps(uneven_batch(dev, args.iters)), flush=True)
+        return 0
     print(f"[bench] building workload: {args.projections} x 1024^2", file=sys.stderr, flush=True)
     batch, ys, geo, probs, d_inputs = build_workload(args.projections, dev)
     pixels = args.projections * geo.nx * geo.ny
@@ -465,18 +521,20 @@ def main() -> int:
         return 0
 
     out = [torch.empty((geo.ny, geo.nx), dtype=torch.complex64, device=dev) for _ in range(args.projections)]
+    # the loss history stays on in the timed run: its FP64 sums set the device's non-finite flag
+    hist = torch.empty((args.projections, args.iters), dtype=torch.float64, device=dev)
     for w in range(args.warmup):
-        batch.solve(ys, args.iters, psi_out=out, loss_hist=False)
+        batch.solve(ys, args.iters, psi_out=out, hist_out=hist)
         torch.cuda.synchronize()
         print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        batch.solve(ys, args.iters, psi_out=out, loss_hist=False)
+        batch.solve(ys, args.iters, psi_out=out, hist_out=hist)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    if batch.sync_status() != 0:
+    if batch.sync_status() != 0 or not bool(torch.isfinite(hist).all()):
         print("[bench] non-finite loss during the timed run", file=sys.stderr)
         return 1
     value = args.projections * args.iters * args.steps / dt
@@ -498,7 +556,10 @@ def main() -> int:
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "per_sweep_ms": [round(x * 1e3, 4) for x in sweep_s],
                 "iteration_frac_of_hbm_roofline": round(value * ITER_BYTES_PER_PX * geo.nx * geo.ny / 1e9
-                                                        / HBM_PEAK_GBS, 4)}
+                                                        / HBM_PEAK_GBS, 4),
+                "iteration_frac_of_280B_schedule": round(value * SURVEY_SCHEDULE_BYTES_PER_PX * geo.nx * geo.ny
+                                                         / 1e9 / HBM_PEAK_GBS, 4),
+                "iteration_bytes_per_px": ITER_BYTES_PER_PX}
     print(f"[bench] sweeps ms: {[round(x * 1e3, 3) for x in sweep_s]}", file=sys.stderr, flush=True)
 
     plain = None
@@ -515,8 +576,10 @@ def main() -> int:
         print(f"[bench] plain {pv:.1f} proj-iter/s", file=sys.stderr, flush=True)
 
     extras = None if args.no_extras else secondary_measurements(batch, ys, out, probs, geo, d_inputs, dev)
+    del batch, ys, out, hist
+    torch.cuda.empty_cache()
     if extras is not None:
-        extras["share_45x2048"] = share_2048(dev)
+        extras["workload_720x2048"] = workload_720x2048(dev, args.iters_2048)
         extras["uneven_roi_batch"] = uneven_batch(dev)
 
     cpu = None

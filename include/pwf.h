@@ -61,11 +61,34 @@ typedef struct {
   double z1_m, z2_m;
 } pwf_geometry;
 
-/* Partial coherence (Methods, IOTF; Eqs. 4-5): Gaussian intensity point
- * spread function with standard deviation sigma (pixels) at the detector,
- * x_coh = 2 sqrt(pi) sigma p.  sigma = 0 means a fully coherent source. */
+/* Partial coherence of the source (Methods, "Intensity optical transfer
+ * function (IOTF)", Eqs. 3-5), in one of three forms (`kind`):
+ *   PWF_SRC_GAUSS      Gaussian intensity point spread function of standard
+ *                      deviation sigma_x_px, sigma_y_px (pixels at the
+ *                      detector), i.e. Eq. 4 with x_coh = 2 sqrt(pi) sigma p;
+ *                      0 means a fully coherent source.
+ *   PWF_SRC_COHERENCE  the coherence lengths x_coh_m, y_coh_m (metres) of
+ *                      Eqs. 4-5, as pwf_fit_coherence returns them (Eq. 3);
+ *                      0 means coherent along that axis.
+ *   PWF_SRC_IOTF       the IOTF itself, separable and sampled on the DFT bins:
+ *                      IOTF(kx, ky) = iotf_x[kx] iotf_y[ky], with iotf_x a
+ *                      device float32 array of nx values and iotf_y of ny
+ *                      (bin k > n/2 stands for frequency k - n).  Both arrays
+ *                      must be even (iotf[k] == iotf[n - k]) and finite; the
+ *                      library does not read device memory to check, and
+ *                      non-finite values surface as PWF_ERR_NONFINITE.  The
+ *                      arrays are read by every call that uses the problem.
+ * Unused members are ignored.  The regulariser's sample transfer function
+ * (Eq. 14) is STF = IOTF^(2 gamma) in every form, the relation Eqs. 5 and 14
+ * give for the Gaussian model (negative IOTF samples count as 0 there). */
+typedef enum { PWF_SRC_GAUSS = 0, PWF_SRC_COHERENCE = 1, PWF_SRC_IOTF = 2 } pwf_source_kind;
+
 typedef struct {
+  int32_t kind;
   double sigma_x_px, sigma_y_px;
+  double x_coh_m, y_coh_m;
+  const float* iotf_x;
+  const float* iotf_y;
 } pwf_source;
 
 /* Solver parameters (Results, PWF subsection; Methods, Eqs. 11, 14-15).
@@ -151,7 +174,8 @@ pwf_status pwf_rmse_image(const pwf_problem* problems, int32_t n, const void* co
  *   y[i]        device float32 [ny][nx], measured speckle
  *   g_out[i]    device complex64 or NULL (array itself may be NULL)
  *   d_out[i]    device complex64 or NULL (array itself may be NULL)
- *   loss_out    device float64 [n] or NULL */
+ *   loss_out    device float64 [n] or NULL
+ * With neither g nor d requested only the forward model and the loss run. */
 pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* const* psi, const float* const* y,
                         void* const* g_out, void* const* d_out, double* loss_out, void* workspace,
                         size_t workspace_bytes, void* stream);
@@ -316,7 +340,7 @@ pwf_status pwf_speckle_g2(const float* ref, int32_t nx, int32_t ny, int32_t max_
  * K the last shift before g2 - 1 first drops below 2% of g2(1) - 1 (d = 0
  * holds the noise variance).  coh_m: metres; contrast may be NULL.  Host-only;
  * PWF_ERR_ARG when fewer than two shifts qualify or the fit does not decay.
- * The IOTF of a source with x_coh has sigma_x_px = x_coh / (2 sqrt(pi) p). */
+ * The fitted lengths go to the iteration as a PWF_SRC_COHERENCE source. */
 pwf_status pwf_fit_coherence(const double* g2, int32_t count, double pixel_m, double* coh_m, double* contrast);
 
 /* Diffuser estimate from the reference speckle `ref` (device float32):

@@ -163,19 +163,33 @@ class Problem:
 
 def make_problem(t, geometry, *, alpha: complex = PAPER_ALPHA, gamma: float = PAPER_GAMMA,
                  eta: float = DEFAULT_ETA, precond_scale: float = DEFAULT_PRECOND_SCALE,
-                 precondition: bool = True,
+                 precondition: bool = True, coherence: tuple[float, float] | None = None,
                  iotf: np.ndarray | None = None) -> Problem:
-    """Build the FP64 windows of one projection from a ``synthetic.Geometry``-like object."""
+    """Build the FP64 windows of one projection from a ``synthetic.Geometry``-like object.
+
+    The source is the geometry's Gaussian IPSF (``sigma_*_px``), or the coherence
+    lengths ``coherence = (x_coh, y_coh)`` in metres (Eqs. 4-5), or a given IOTF
+    window ``iotf`` on the DFT grid.  For a given window the sample transfer
+    function is ``STF = IOTF^(2 gamma)`` (negative samples count as 0), the
+    relation that Eqs. 5 and 14 give for the Gaussian model."""
     g = geometry
     u, v = spatial_frequencies(g.ny, g.nx, g.pixel_m)
-    x_coh, y_coh = coherence_lengths(g.sigma_x_px, g.sigma_y_px, g.pixel_m)
-    win = iotf_window(u, v, x_coh, y_coh) if iotf is None else np.asarray(iotf, np.float64)
+    if coherence is None:
+        x_coh, y_coh = coherence_lengths(g.sigma_x_px, g.sigma_y_px, g.pixel_m)
+    else:
+        x_coh, y_coh = float(coherence[0]), float(coherence[1])
+    if iotf is None:
+        win = iotf_window(u, v, x_coh, y_coh)
+        gamma2 = regularization_window(u, v, x_coh, y_coh, gamma)
+    else:
+        win = np.asarray(iotf, np.float64)
+        gamma2 = 1.0 - np.maximum(win, 0.0) ** (2.0 * gamma)
     return Problem(
         t=np.asarray(t, dtype=np.complex128),
         wavelength_m=g.wavelength_m, z1_m=g.z1_m, z2_m=g.z2_m, pixel_m=g.pixel_m,
         iotf=win,
         p_inv=preconditioning_filter(u, v, g.pixel_m, precond_scale),
-        gamma2=regularization_window(u, v, x_coh, y_coh, gamma),
+        gamma2=gamma2,
         alpha=complex(alpha), eta=float(eta), u=u, v=v, precondition=precondition,
     )
 

@@ -23,8 +23,15 @@ class pwf_geometry(ctypes.Structure):
                 ("wavelength_m", ctypes.c_double), ("z1_m", ctypes.c_double), ("z2_m", ctypes.c_double)]
 
 
+PWF_SRC_GAUSS = 0
+PWF_SRC_COHERENCE = 1
+PWF_SRC_IOTF = 2
+
+
 class pwf_source(ctypes.Structure):
-    _fields_ = [("sigma_x_px", ctypes.c_double), ("sigma_y_px", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int32), ("sigma_x_px", ctypes.c_double), ("sigma_y_px", ctypes.c_double),
+                ("x_coh_m", ctypes.c_double), ("y_coh_m", ctypes.c_double),
+                ("iotf_x", ctypes.c_void_p), ("iotf_y", ctypes.c_void_p)]
 
 
 class pwf_params(ctypes.Structure):

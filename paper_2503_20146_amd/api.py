@@ -26,7 +26,13 @@ DEFAULT_ETA_T = 0.5  # diffuser step of the joint refinement (pwf_solve_joint)
 
 @dataclasses.dataclass
 class Problem:
-    """One PWF instance (projection or region of interest)."""
+    """One PWF instance (projection or region of interest).
+
+    The source's partial coherence is given by ``sigma_x_px``/``sigma_y_px`` (Gaussian
+    IPSF in pixels), or by ``x_coh_m``/``y_coh_m`` (coherence lengths in metres, e.g.
+    from :func:`calibrate_source`), or by a separable IOTF ``iotf_x``/``iotf_y`` (float32
+    GPU tensors of nx and ny values on the DFT bins); the first of these that is set,
+    in the order IOTF, coherence lengths, sigma, is passed to the library."""
 
     nx: int
     ny: int
@@ -42,6 +48,30 @@ class Problem:
     gamma: float = DEFAULT_GAMMA
     precond_scale: float = DEFAULT_PRECOND_SCALE
     precondition: bool = True
+    x_coh_m: float | None = None
+    y_coh_m: float | None = None
+    iotf_x: torch.Tensor | None = None
+    iotf_y: torch.Tensor | None = None
+
+    def _source(self) -> _lib.pwf_source:
+        src = _lib.pwf_source()
+        if self.iotf_x is not None or self.iotf_y is not None:
+            for t, n in ((self.iotf_x, self.nx), (self.iotf_y, self.ny)):
+                if (t is None or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous()
+                        or tuple(t.shape) != (n,)):
+                    raise ValueError("iotf_x / iotf_y must be contiguous float32 GPU tensors of nx / ny values")
+            src.kind = _lib.PWF_SRC_IOTF
+            src.iotf_x = self.iotf_x.data_ptr()
+            src.iotf_y = self.iotf_y.data_ptr()
+        elif self.x_coh_m is not None or self.y_coh_m is not None:
+            src.kind = _lib.PWF_SRC_COHERENCE
+            src.x_coh_m = float(self.x_coh_m or 0.0)
+            src.y_coh_m = float(self.y_coh_m or 0.0)
+        else:
+            src.kind = _lib.PWF_SRC_GAUSS
+            src.sigma_x_px = float(self.sigma_x_px)
+            src.sigma_y_px = float(self.sigma_y_px)
+        return src
 
     def to_c(self) -> _lib.pwf_problem:
         d = self.diffuser
@@ -49,7 +79,7 @@ class Problem:
             raise ValueError("diffuser must be a contiguous complex64 tensor of shape (ny, nx)")
         p = _lib.pwf_problem()
         p.geom = _lib.pwf_geometry(self.nx, self.ny, self.pixel_m, self.wavelength_m, self.z1_m, self.z2_m)
-        p.source = _lib.pwf_source(self.sigma_x_px, self.sigma_y_px)
+        p.source = self._source()
         p.params = _lib.pwf_params(self.eta, self.alpha.real, self.alpha.imag, self.gamma, self.precond_scale,
                                    1 if self.precondition else 0)
         p.diffuser = d.data_ptr()
@@ -172,10 +202,18 @@ class PWF:
         return loss
 
     def solve(self, y, iters: int, psi_out=None, loss_hist: bool = True, corr_tol: float = 0.0,
-              return_iters: bool = False):
-        """Algorithm S1 from psi = 0.  ``corr_tol`` in (0, 1) enables the correlation stop."""
+              return_iters: bool = False, hist_out: torch.Tensor | None = None):
+        """Algorithm S1 from psi = 0.  ``corr_tol`` in (0, 1) enables the correlation stop.
+        ``hist_out`` (float64 [n, iters] on the GPU) receives the loss history in place of a
+        new tensor."""
         psi_out = self._empty(torch.complex64) if psi_out is None else list(psi_out)
-        hist = torch.empty((self.n, max(iters, 1)), dtype=torch.float64, device=self.device) if loss_hist else None
+        if hist_out is not None:
+            if hist_out.dtype != torch.float64 or not hist_out.is_contiguous() or hist_out.numel() < self.n * iters:
+                raise ValueError("hist_out must be a contiguous float64 tensor of n * iters values")
+            hist = hist_out
+        else:
+            hist = (torch.empty((self.n, max(iters, 1)), dtype=torch.float64, device=self.device)
+                    if loss_hist else None)
         done = (ctypes.c_int32 * self.n)()
         ws, nb = self._ws()
         check(self.lib.pwf_solve(self._c, self.n, _ptrs(y, torch.float32, self.shapes),
@@ -207,9 +245,9 @@ class PWF:
                                        _stream(self.device)), "pwf_solve_joint")
         return psi_out, hist
 
-    def loss_grad(self, psi, y):
+    def loss_grad(self, psi, y, grad_out=None):
         """Loss and real gradient dL/dRe psi + i dL/dIm psi (forward fields recomputed)."""
-        grad = self._empty(torch.complex64)
+        grad = self._empty(torch.complex64) if grad_out is None else list(grad_out)
         loss = torch.empty(self.n, dtype=torch.float64, device=self.device)
         ws, nb = self._ws()
         check(self.lib.pwf_loss_grad(self._c, self.n, _ptrs(psi, torch.complex64, self.shapes),
@@ -293,12 +331,12 @@ def fit_coherence(g2, pixel_m: float):
 
 
 def calibrate_source(ref: torch.Tensor, pixel_m: float, max_shift: int = 32):
-    """Coherence lengths (x_coh, y_coh) in metres and the IPSF sigmas in pixels."""
+    """Coherence lengths (x_coh, y_coh) in metres of a reference speckle (Eq. 3), to be
+    passed on as ``Problem(x_coh_m=..., y_coh_m=...)``, with the fitted contrasts and g2."""
     gx, gy = speckle_g2(ref, max_shift)
-    xc, _ = fit_coherence(gx, pixel_m)
-    yc, _ = fit_coherence(gy, pixel_m)
-    k = 2.0 * math.sqrt(math.pi) * pixel_m
-    return {"x_coh_m": xc, "y_coh_m": yc, "sigma_x_px": xc / k, "sigma_y_px": yc / k, "g2x": gx, "g2y": gy}
+    xc, cx = fit_coherence(gx, pixel_m)
+    yc, cy = fit_coherence(gy, pixel_m)
+    return {"x_coh_m": xc, "y_coh_m": yc, "contrast_x": cx, "contrast_y": cy, "g2x": gx, "g2y": gy}
 
 
 def diffuser_from_reference(problem: Problem, ref: torch.Tensor, eps: float = 1e-3) -> torch.Tensor:

@@ -1,7 +1,8 @@
 """``torch.autograd.Function`` view of the PWF loss (Eq. 2) on a batch.
 
-The forward pass returns the per-instance loss; only psi is saved.  The
-backward pass calls the library again, recomputing every forward field, and
+The forward pass returns the per-instance loss (the library's forward model
+and misfit only); only psi is saved.  The backward pass calls the library
+again, recomputing every forward field, and
 returns dL/dRe psi + i dL/dIm psi, which is torch's gradient convention for a
 real function of complex inputs.  Memory per instance is therefore one complex
 field (psi) between the two passes, however large the batch.
@@ -30,10 +31,10 @@ class PWFLoss(torch.autograd.Function):
     def backward(ctx, grad_loss: torch.Tensor):
         (psi,) = ctx.saved_tensors
         parts = [psi[i] for i in range(psi.shape[0])]
-        _, grads = ctx.batch.loss_grad(parts, list(ctx.y))
-        g = torch.stack(grads)
-        scale = grad_loss.to(torch.float32).reshape(-1, 1, 1)
-        return g * scale, None, None
+        g = torch.empty_like(psi)   # one buffer; the library writes each instance's slice
+        ctx.batch.loss_grad(parts, list(ctx.y), grad_out=[g[i] for i in range(psi.shape[0])])
+        g.mul_(grad_loss.to(torch.float32).reshape(-1, 1, 1))
+        return g, None, None
 
 
 def pwf_loss(psi: torch.Tensor, batch: PWF, y) -> torch.Tensor:

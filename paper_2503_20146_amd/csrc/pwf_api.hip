@@ -22,7 +22,7 @@ using pwf::Sweep;
 
 namespace {
 
-constexpr int kVersion = 10000;        // 1.0.0
+constexpr int kVersion = 10100;        // 1.1.0
 constexpr int kBetaCap = 1 << 16;      // iterations covered by the momentum table
 constexpr size_t kAlign = 256;
 constexpr int kSizes[] = {128, 256, 512, 1024, 2048};
@@ -251,7 +251,19 @@ pwf_status validate_problem(const pwf_problem& p) {
   const double lp = g.wavelength_m / g.pixel_m;
   if (0.5 * lp * lp >= 1.0) return PWF_ERR_EVANESCENT;
   const pwf_source& s = p.source;
-  if (!finite(s.sigma_x_px) || !finite(s.sigma_y_px) || s.sigma_x_px < 0 || s.sigma_y_px < 0) return PWF_ERR_ARG;
+  switch (s.kind) {
+    case PWF_SRC_GAUSS:
+      if (!finite(s.sigma_x_px) || !finite(s.sigma_y_px) || s.sigma_x_px < 0 || s.sigma_y_px < 0) return PWF_ERR_ARG;
+      break;
+    case PWF_SRC_COHERENCE:
+      if (!finite(s.x_coh_m) || !finite(s.y_coh_m) || s.x_coh_m < 0 || s.y_coh_m < 0) return PWF_ERR_ARG;
+      break;
+    case PWF_SRC_IOTF:
+      if (!s.iotf_x || !s.iotf_y) return PWF_ERR_ARG;
+      break;
+    default:
+      return PWF_ERR_ARG;
+  }
   const pwf_params& q = p.params;
   if (!finite(q.eta) || !finite(q.alpha_re) || !finite(q.alpha_im) || !finite(q.gamma) || q.gamma < 0)
     return PWF_ERR_ARG;
@@ -412,11 +424,26 @@ Inst base_inst(const pwf_problem& p) {
   I.two_pi_a1 = (float)(2.0 * M_PI * I.chirp1_rev);
   I.two_pi_a2 = (float)(2.0 * M_PI * I.chirp2_rev);
   I.s_coef_f = (float)I.s_coef;
-  const double pi2 = M_PI * M_PI;
-  I.iotf_cx = (float)(2.0 * pi2 * p.source.sigma_x_px * p.source.sigma_x_px);
-  I.iotf_cy = (float)(2.0 * pi2 * p.source.sigma_y_px * p.source.sigma_y_px);
-  I.stf_cx = (float)(4.0 * pi2 * p.params.gamma * p.source.sigma_x_px * p.source.sigma_x_px);
-  I.stf_cy = (float)(4.0 * pi2 * p.params.gamma * p.source.sigma_y_px * p.source.sigma_y_px);
+  // Coherence lengths in pixels: Eq. 4's Gaussian of std sigma has x_coh = 2 sqrt(pi) sigma p.
+  // IOTF (Eq. 5) exp(-(pi/2) u^2 x_coh^2) and STF (Eq. 14) exp(-pi gamma u^2 x_coh^2), with
+  // u = f / p for f in cycles per pixel.
+  const pwf_source& src = p.source;
+  double cx = 0.0, cy = 0.0;
+  if (src.kind == PWF_SRC_GAUSS) {
+    cx = 2.0 * std::sqrt(M_PI) * src.sigma_x_px;
+    cy = 2.0 * std::sqrt(M_PI) * src.sigma_y_px;
+  } else if (src.kind == PWF_SRC_COHERENCE) {
+    cx = src.x_coh_m / g.pixel_m;
+    cy = src.y_coh_m / g.pixel_m;
+  } else {
+    I.src_ix = src.iotf_x;
+    I.src_iy = src.iotf_y;
+  }
+  I.iotf_cx = (float)(0.5 * M_PI * cx * cx);
+  I.iotf_cy = (float)(0.5 * M_PI * cy * cy);
+  I.stf_cx = (float)(M_PI * p.params.gamma * cx * cx);
+  I.stf_cy = (float)(M_PI * p.params.gamma * cy * cy);
+  I.two_gamma = (float)(2.0 * p.params.gamma);
   I.pinv_scale = p.params.precondition ? (float)p.params.precond_scale : -1.0f;
   I.alpha_c1 = (float)(0.5 * (p.params.alpha_re + p.params.alpha_im));
   I.alpha_c2 = (float)(0.5 * (p.params.alpha_re - p.params.alpha_im));
@@ -695,10 +722,11 @@ pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* cons
                         size_t workspace_bytes, void* stream) {
   PWF_TRY(validate_batch(problems, n));
   if (!psi || !y) return PWF_ERR_ARG;
-  bool want_d = false;
+  bool want_d = false, want_g = false;
   for (int i = 0; i < n; ++i) {
     if (!psi[i] || !y[i]) return PWF_ERR_ARG;
     if (d_out && d_out[i]) want_d = true;
+    if (g_out && g_out[i]) want_g = true;
   }
   Layout L;
   PWF_TRY(check_ws(problems, n, workspace, workspace_bytes, &L));
@@ -744,6 +772,11 @@ pwf_status pwf_gradient(const pwf_problem* problems, int32_t n, const void* cons
   PWF_TRY(K.col(pwf::COL_CHIRP2));
   PWF_TRY(K.row(pwf::ROW_INTENSITY));
   PWF_TRY(K.col(pwf::COL_BLUR_LOSS));
+  if (!want_g && !want_d) {
+    // loss only: the forward half (Eq. 1) and the misfit (Eq. 2)
+    PWF_HIP(pwf::launch_loss_final((const Inst*)(ws + L.desc), n, (int32_t*)(ws + L.status), st));
+    return PWF_OK;
+  }
   PWF_TRY(K.row(pwf::ROW_BACKBLUR));
   PWF_TRY(K.col(pwf::COL_CHIRP2_CONJ));
   PWF_TRY(K.row(pwf::ROW_MUL_CONJ_T));
@@ -1325,10 +1358,12 @@ pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi
   const int nx = p.geom.nx, ny = p.geom.ny;
   const size_t m = (size_t)nx * ny;
   Inst I = base_inst(p);
+  attach_tables(I, ws, L, 0);
   I.y = y;
   I.maxt2 = (const float*)(ws + L.maxt2);
   Inst* dI = (Inst*)(ws + L.desc);
   PWF_TRY(upload(*ctx, &I, sizeof(Inst), dI, st));
+  PWF_HIP(pwf::launch_build_tables(dI, 1, st));
   float2* psi = (float2*)psi_out;
   float2* Z = (float2*)(ws + L.W[0]);
   float2* X = (float2*)(ws + L.psi_hat[0]);
@@ -1458,10 +1493,12 @@ pwf_status pwf_diffuser_from_reference(const pwf_problem* problem, const float* 
   const int nx = p.geom.nx, ny = p.geom.ny;
   const size_t m = (size_t)nx * ny;
   Inst I = base_inst(p);
+  attach_tables(I, ws, L, 0);
   I.y = ref;
   I.wiener_eps = (float)eps;
   Inst* dI = (Inst*)(ws + L.desc);
   PWF_TRY(upload(*ctx, &I, sizeof(Inst), dI, st));
+  PWF_HIP(pwf::launch_build_tables(dI, 1, st));
   float2* X = (float2*)(ws + L.W[0]);
   float2* t = (float2*)t_out;
   double* part = (double*)(ws + L.part[0]);

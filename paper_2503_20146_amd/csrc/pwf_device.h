@@ -54,8 +54,11 @@ struct Inst {
   int32_t cross;        // 1: the cross term can change an FP32 result and is applied
   float two_pi_a1, two_pi_a2;  // 2 pi chirp_rev (radians per f^2), FP32 copy for the cross term
   float s_coef_f;
-  float iotf_cx, iotf_cy;  // IOTF = exp(-(cx fx^2 + cy fy^2)), c = 2 pi^2 sigma^2
-  float stf_cx, stf_cy;    // STF  = exp(-(cx fx^2 + cy fy^2)), c = 4 pi^2 gamma sigma^2
+  float iotf_cx, iotf_cy;  // IOTF = exp(-(cx fx^2 + cy fy^2)), c = (pi/2) (x_coh/p)^2
+  float stf_cx, stf_cy;    // STF  = exp(-(cx fx^2 + cy fy^2)), c = pi gamma (x_coh/p)^2
+  const float* src_ix;     // caller's separable IOTF (PWF_SRC_IOTF) by DFT bin, or null
+  const float* src_iy;
+  float two_gamma;         // STF = IOTF^(2 gamma) for a caller's IOTF
   float pinv_scale;        // s_P; negative: preconditioner off
   float alpha_c1, alpha_c2;// (Re a + Im a)/2, (Re a - Im a)/2
   float eta;
@@ -145,11 +148,12 @@ __device__ __forceinline__ float2 transfer(double chirp_rev, double s_coef, int 
   return make_float2(cs, conj ? -sn : sn);
 }
 
-__device__ __forceinline__ float iotf_of(const Inst& I, float fx, float fy) {
-  return expf(-(I.iotf_cx * fx * fx + I.iotf_cy * fy * fy));
-}
-__device__ __forceinline__ float gamma2_of(const Inst& I, float fx, float fy) {
-  return -expm1f(-(I.stf_cx * fx * fx + I.stf_cy * fy * fy));
+// IOTF and regularisation window Gamma^2 = 1 - STF at DFT bin (kx, ky), from the
+// per-call 1-D tables (see build_tables_kernel).
+__device__ __forceinline__ float iotf_at(const Inst& I, int kx, int ky) { return I.ix[kx] * I.iy[ky]; }
+__device__ __forceinline__ float gamma2_at(const Inst& I, int kx, int ky) {
+  const float gx = I.gx[kx];
+  return gx + (1.f - gx) * I.gy[ky];   // 1 - STFx STFy without cancellation
 }
 __device__ __forceinline__ float pinv_of(const Inst& I, float fx, float fy) {
   const float r2 = fx * fx + fy * fy;

@@ -99,6 +99,8 @@ hipError_t launch_plain_loss_final(const double* partial, int np, double* dst, i
                                    hipStream_t st);
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// loss_dst[0] = inv_m * sum of the instance's loss partials, per instance (one workgroup each)
+hipError_t launch_loss_final(const Inst* insts, int n, int32_t* status, hipStream_t st);
 // Filtered back-projection (pwf_tomo.hip)
 hipError_t launch_fbp_pad(const float2* const* psi, int n_proj, int nx, int ny, int n_pad, float2* dst,
                           hipStream_t st);

@@ -32,11 +32,11 @@ __global__ void plain_window(float2* __restrict__ a, const Inst* __restrict__ ip
       case PLAIN_W_Q2: val = cmul(val, transfer(I.chirp2_rev, I.s_coef, I.series, fx, fy, false)); break;
       case PLAIN_W_Q2C: val = cmul(val, transfer(I.chirp2_rev, I.s_coef, I.series, fx, fy, true)); break;
       case PLAIN_W_Q1C: val = cmul(val, transfer(I.chirp1_rev, I.s_coef, I.series, fx, fy, true)); break;
-      case PLAIN_W_IOTF: val = cscale(val, iotf_of(I, fx, fy)); break;
+      case PLAIN_W_IOTF: val = cscale(val, iotf_at(I, kx, ky)); break;
       case PLAIN_W_PINV: val = cscale(val, pinv_of(I, fx, fy)); break;
-      case PLAIN_W_GAMMA2: val = cscale(val, gamma2_of(I, fx, fy)); break;
+      case PLAIN_W_GAMMA2: val = cscale(val, gamma2_at(I, kx, ky)); break;
       case PLAIN_W_WIENER: {
-        const float h = iotf_of(I, fx, fy);
+        const float h = iotf_at(I, kx, ky);
         val = cscale(val, h / (h * h + I.wiener_eps));
         break;
       }
@@ -109,6 +109,19 @@ __global__ void plain_loss_final(const double* partial, int np, double* dst, int
   }
 }
 
+// Loss of every instance from its column-tile partials (fixed order, FP64),
+// when no back-blur sweep follows to sum them: one workgroup per instance.
+__global__ void loss_final_kernel(const Inst* __restrict__ insts, int32_t* status) {
+  const Inst& I = insts[blockIdx.x];
+  if (threadIdx.x == 0 && I.loss_dst) {
+    double s = 0.0;
+    for (int i = 0; i < I.n_partials; ++i) s += I.loss_partial[i];
+    s *= I.inv_m_d;
+    I.loss_dst[0] = s;
+    if (!isfinite(s)) atomicOr(status, 1);
+  }
+}
+
 // ------------------------------------------------------------------ utilities
 
 __global__ void fill_zero_kernel(float4* __restrict__ p, size_t n16) {
@@ -162,17 +175,28 @@ __global__ void build_tables_kernel(const Inst* __restrict__ insts) {
     const float cio = isx ? I.iotf_cx : I.iotf_cy;
     const float cst = isx ? I.stf_cx : I.stf_cy;
     const float ff = (float)f2;
+    // IOTF factor and 1 - STF factor: Eq. 5 / Eq. 14 in closed form, or from the
+    // caller's separable IOTF with STF = IOTF^(2 gamma)
+    const float* src = isx ? I.src_ix : I.src_iy;
+    float iotf, g2;
+    if (src) {
+      iotf = src[kk];
+      g2 = 1.f - powf(fmaxf(iotf, 0.f), I.two_gamma);
+    } else {
+      iotf = expf(-cio * ff);
+      g2 = -expm1f(-cst * ff);
+    }
     if (isx) {
       I.qx1[kk] = q[0];
       I.qx2[kk] = q[1];
       // (y factors below carry the 1/m of the inverse 2-D transform: exact, m = 2^k)
-      I.ix[kk] = expf(-cio * ff);
-      I.gx[kk] = -expm1f(-cst * ff);
+      I.ix[kk] = iotf;
+      I.gx[kk] = g2;
     } else {
       I.qy1[kk] = make_float2(q[0].x * I.inv_m, q[0].y * I.inv_m);
       I.qy2[kk] = make_float2(q[1].x * I.inv_m, q[1].y * I.inv_m);
-      I.iy[kk] = expf(-cio * ff);
-      I.gy[kk] = -expm1f(-cst * ff);
+      I.iy[kk] = iotf;
+      I.gy[kk] = g2;
     }
   }
 }
@@ -325,6 +349,11 @@ hipError_t launch_plain_elementwise(int op, size_t m, const float2* a, const flo
 hipError_t launch_plain_loss_final(const double* partial, int np, double* dst, int iter, int32_t* status,
                                    hipStream_t st) {
   hipLaunchKernelGGL(plain_loss_final, dim3(1), dim3(64), 0, st, partial, np, dst, iter, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_final(const Inst* insts, int n, int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(loss_final_kernel, dim3(n), dim3(64), 0, st, insts, status);
   return hipGetLastError();
 }
 

@@ -21,3 +21,4 @@ from .generators import (  # noqa: F401
     roi_batch_specs,
     tomo_projection_inputs,
 )
+from .device_phantom import project_ellipsoids_device  # noqa: F401

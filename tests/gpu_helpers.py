@@ -59,3 +59,24 @@ def loss_history_tolerance(y, hist_ref, fwd_tol=1e-5):
     forward tolerance gives |dL_k| / L_k <= 2 fwd_tol ||y|| / sqrt(L_k) (||f_k|| ~ ||y||)."""
     y = np.asarray(y, np.float64)
     return 2.0 * fwd_tol * float(np.linalg.norm(y)) / np.sqrt(np.asarray(hist_ref, np.float64))
+
+
+def fd_check(psi, y, prob, grad, pixels, h=1e-4, rtol=1e-3, grad_tol=1e-4):
+    """Central differences of the FP64 oracle loss against a GPU gradient at the listed pixels.
+
+    Allowed deviation: rtol of the difference quotient (its O(h^2) truncation and FP64
+    cancellation) plus a floor of 5 grad_tol RMS(grad), five times the per-pixel RMS error
+    that the relative-L2 budget of the gradient allows: FP32 rounding of the GPU gradient
+    is spread evenly over pixels, so small entries carry errors of that absolute size.
+    """
+    psi = np.asarray(psi).astype(np.complex128)
+    floor = 5 * grad_tol * float(np.sqrt(np.mean(np.abs(grad) ** 2)))
+    for (r, c) in pixels:
+        for unit in (1.0, 1j):
+            dp = np.zeros(psi.shape, complex)
+            dp[r, c] = h * unit
+            lp = O.loss(y, O.physical_model(psi + dp, prob)[0])
+            lm = O.loss(y, O.physical_model(psi - dp, prob)[0])
+            fd = (lp - lm) / (2 * h)
+            an = grad[r, c].real if unit == 1.0 else grad[r, c].imag
+            assert abs(fd - an) <= rtol * abs(fd) + floor, (r, c, unit, fd, an)

@@ -90,10 +90,21 @@ def _problem(nx=128, ny=128, **kw):
     p = _lib.pwf_problem()
     p.geom = _lib.pwf_geometry(nx, ny, kw.get("pixel", 1e-6), kw.get("lam", 0.05e-9), kw.get("z1", 5e-3),
                                kw.get("z2", 0.2))
-    p.source = _lib.pwf_source(kw.get("sx", 1.0), kw.get("sy", 1.0))
+    p.source = _lib.pwf_source(kind=kw.get("kind", _lib.PWF_SRC_GAUSS), sigma_x_px=kw.get("sx", 1.0),
+                               sigma_y_px=kw.get("sy", 1.0), x_coh_m=kw.get("xc", 0.0), y_coh_m=kw.get("yc", 0.0),
+                               iotf_x=kw.get("ix", None), iotf_y=kw.get("iy", None))
     p.params = _lib.pwf_params(kw.get("eta", 0.5), 0.1, 0.01, kw.get("gamma", 1.0), kw.get("sp", 0.025), 1)
     p.diffuser = kw.get("diffuser", 0x1000)
     return p
+
+
+def test_source_forms_accepted(lib):
+    """Every source form with valid members passes validation (pwf_workspace_size > 0)."""
+    from paper_2503_20146_amd import _lib
+    for kw in (dict(kind=0, sx=0.0, sy=2.0), dict(kind=1, xc=3.47e-6, yc=4.31e-6), dict(kind=1, xc=0.0, yc=0.0),
+               dict(kind=2, ix=0x4000, iy=0x5000)):
+        arr = (_lib.pwf_problem * 1)(_problem(**kw))
+        assert lib.pwf_workspace_size(arr, 1) > 0, kw
 
 
 def test_workspace_size(lib):
@@ -111,6 +122,8 @@ def test_workspace_size(lib):
     (dict(nx=100), -2), (dict(ny=4096), -2), (dict(pixel=0.0), -1), (dict(lam=float("nan")), -1),
     (dict(z1=-1e-3), -1), (dict(sx=-1.0), -1), (dict(eta=float("inf")), -1), (dict(sp=0.0), -1),
     (dict(diffuser=0), -1), (dict(lam=2e-6, pixel=1e-6), -3),
+    (dict(kind=3), -1), (dict(kind=1, xc=-1e-6), -1), (dict(kind=1, yc=float("nan")), -1),
+    (dict(kind=2, ix=0x4000), -1), (dict(kind=2, iy=0x4000), -1),
 ])
 def test_invalid_problems_rejected_before_any_gpu_work(lib, kw, expect):
     from paper_2503_20146_amd import _lib

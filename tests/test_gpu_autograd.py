@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 import synthetic as S
-from gpu_helpers import device, gpu_problem, instance, loss_tolerance, rel, say, to_dev
+from gpu_helpers import device, fd_check, gpu_problem, instance, loss_tolerance, rel, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -21,26 +21,7 @@ GRAD_TOL = 1e-4
 
 
 def _fd_check(psi, y, prob, grad, pixels, h=1e-4, rtol=1e-3):
-    """Central differences of the FP64 oracle loss at the listed pixels.
-
-    Allowed deviation: rtol of the difference quotient (its O(h^2) truncation
-    and FP64 cancellation; at 2048^2 the quotient agrees with the oracle's
-    analytic derivative to 3e-4) plus a floor of 5 GRAD_TOL RMS(grad), five
-    times the per-pixel RMS error that the relative-L2 budget of the gradient
-    allows.  FP32 rounding of the GPU gradient is spread evenly over pixels,
-    so small entries carry errors of that absolute size.
-    """
-    psi = psi.astype(np.complex128)
-    floor = 5 * GRAD_TOL * float(np.sqrt(np.mean(np.abs(grad) ** 2)))
-    for (r, c) in pixels:
-        for unit in (1.0, 1j):
-            dp = np.zeros(psi.shape, complex)
-            dp[r, c] = h * unit
-            lp = O.loss(y, O.physical_model(psi + dp, prob)[0])
-            lm = O.loss(y, O.physical_model(psi - dp, prob)[0])
-            fd = (lp - lm) / (2 * h)
-            an = grad[r, c].real if unit == 1.0 else grad[r, c].imag
-            assert abs(fd - an) <= rtol * abs(fd) + floor, (r, c, unit, fd, an)
+    fd_check(psi, y, prob, grad, pixels, h, rtol, GRAD_TOL)
 
 
 def test_autograd_small_matches_oracle_and_fd():

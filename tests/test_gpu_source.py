@@ -1,0 +1,100 @@
+"""Source forms of the C ABI against the oracle (Methods, "Intensity optical transfer
+function"; Eqs. 3-5 and the STF of Eq. 14).
+
+* Coherence lengths in metres (PWF_SRC_COHERENCE): the paper's beamline values, x_coh =
+  3.47 um and y_coh = 4.31 um, on the 128^2 workload.
+* A caller's separable IOTF (PWF_SRC_IOTF) that is not Gaussian: a Lorentzian factor along
+  x and an exponential one along y, on square and non-square grids; the oracle takes the
+  same float32 samples as its window, with STF = IOTF^(2 gamma).
+* The IOTF form given the samples of the Gaussian equals the sigma form.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from gpu_helpers import device, rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL, GRAD_TOL, PHASE_TOL = 1e-5, 1e-4, 1e-3
+
+
+def _gpu_problem(geo, t, dev, **kw):
+    from paper_2503_20146_amd import problem_from_geometry
+    return problem_from_geometry(geo, to_dev(np.asarray(t, np.complex64), dev), **kw)
+
+
+def _check(label, geo, t, prob, gpu_kw, dev, seed, iters=20):
+    from paper_2503_20146_amd import PWF
+    rng = np.random.default_rng(seed)
+    psi_true = S.phase_object(rng, geo.ny, geo.nx, 4.0, 2.0)
+    f_true, _, _ = O.physical_model(psi_true, prob)
+    y = S.poisson_intensity(f_true, (seed, 1))
+    batch = PWF([_gpu_problem(geo, t, dev, **gpu_kw)])
+    psi = (0.5 * psi_true).astype(np.complex64)
+    say(f"{label}: forward, gradient")
+    f = batch.forward([to_dev(psi, dev)])[0].cpu().numpy()
+    f_ref, _, _ = O.physical_model(psi.astype(np.complex128), prob)
+    assert rel(f, f_ref) <= FWD_TOL, label
+    l_ref, g_ref, d_ref = O.gradient(psi.astype(np.complex128), y, prob)
+    loss, g, d = batch.gradient([to_dev(psi, dev)], [to_dev(y, dev)])
+    e_g, e_d = rel(g[0].cpu().numpy(), g_ref), rel(d[0].cpu().numpy(), d_ref)
+    say(f"{label}: g {e_g:.2e}  d {e_d:.2e}")
+    assert e_g <= GRAD_TOL and e_d <= GRAD_TOL, label
+    assert abs(float(loss[0].cpu()) - l_ref) <= 1e-5 * l_ref, label
+    say(f"{label}: solve, {iters} iterations, fused and plain")
+    out, _ = batch.solve([to_dev(y, dev)], iters)
+    psi_ref, _, _ = O.pwf(y, prob, iters)
+    assert np.sqrt(np.mean(np.abs(out[0].cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL, label
+    plain, _ = batch.solve_plain(to_dev(y, dev), iters)
+    assert np.sqrt(np.mean(np.abs(plain.cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL, label
+
+
+def test_coherence_length_source_matches_oracle():
+    dev = device()
+    inp = S.instance_inputs(0)
+    geo = inp["geometry"]
+    coh = (3.47e-6, 4.31e-6)
+    prob = O.make_problem(inp["t"], geo, coherence=coh)
+    _check("coherence lengths 3.47 / 4.31 um", geo, inp["t"], prob, dict(x_coh_m=coh[0], y_coh_m=coh[1]), dev, 31)
+
+
+def _separable_iotf(ny, nx):
+    """A non-Gaussian separable window, even on the DFT grid: Lorentzian in fx, exponential in fy."""
+    fx = np.fft.fftfreq(nx)
+    fy = np.fft.fftfreq(ny)
+    ix = (1.0 / (1.0 + (fx / 0.12) ** 2)).astype(np.float32)
+    iy = np.exp(-np.abs(fy) / 0.1).astype(np.float32)
+    return ix, iy
+
+
+@pytest.mark.parametrize("ny,nx", [(128, 128), (256, 512)])
+def test_separable_iotf_source_matches_oracle(ny, nx):
+    dev = device()
+    rng = np.random.default_rng(ny + 3 * nx)
+    geo = S.Geometry(ny=ny, nx=nx)
+    t = S.diffuser(rng, ny, nx)
+    ix, iy = _separable_iotf(ny, nx)
+    prob = O.make_problem(t, geo, iotf=np.outer(iy.astype(np.float64), ix.astype(np.float64)))
+    _check(f"separable IOTF {ny}x{nx}", geo, t, prob, dict(iotf_x=to_dev(ix, dev), iotf_y=to_dev(iy, dev)), dev,
+           ny + nx)
+
+
+def test_iotf_source_of_the_gaussian_equals_sigma_source():
+    import torch
+    from paper_2503_20146_amd import PWF
+    dev = device()
+    inp, = [S.instance_inputs(0)]
+    geo = inp["geometry"]
+    sx, sy = geo.sigma_x_px, geo.sigma_y_px
+    fx, fy = np.fft.fftfreq(geo.nx), np.fft.fftfreq(geo.ny)
+    ix = np.exp(-2 * np.pi ** 2 * sx * sx * fx * fx).astype(np.float32)
+    iy = np.exp(-2 * np.pi ** 2 * sy * sy * fy * fy).astype(np.float32)
+    psi = (0.5 * inp["psi_true"]).astype(np.complex64)
+    say("IOTF form of the Gaussian vs sigma form")
+    a = PWF([_gpu_problem(geo, inp["t"], dev)]).forward([to_dev(psi, dev)])[0]
+    b = PWF([_gpu_problem(geo, inp["t"], dev, iotf_x=to_dev(ix, dev), iotf_y=to_dev(iy, dev))]).forward(
+        [to_dev(psi, dev)])[0]
+    assert float(torch.linalg.norm(a - b) / torch.linalg.norm(a)) <= 1e-6

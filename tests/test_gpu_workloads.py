@@ -14,7 +14,8 @@ import pytest
 
 import oracle as O
 import synthetic as S
-from gpu_helpers import device, gpu_problem, instance, loss_history_tolerance, say, to_dev
+from gpu_helpers import (device, fd_check, gpu_problem, instance, loss_history_tolerance, loss_tolerance, rel,
+                         say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -133,6 +134,99 @@ def test_uneven_roi_2048_instance_100_iterations():
     assert _rms(psi.imag, psi_ref.imag) <= PHASE_TOL
     assert _rms(psi.real, psi_ref.real) <= PHASE_TOL
     assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
+
+
+def _workload_720x2048(dev, scale_psi: float):
+    """The 720 x 2048^2 workload at its full size: projections of the 2048^3 phantom made on
+    the device, speckle from the GPU forward model with device Poisson noise; projection 0
+    replaced by the CPU recipe's psi and speckle (the oracle's inputs).  Returns the batch,
+    psi [720, 2048, 2048] at scale_psi * psi_true, the speckles and projection 0's inputs."""
+    import torch
+    from paper_2503_20146_amd import PWF, problem_from_geometry
+    n, side = 720, 2048
+    torch.cuda.empty_cache()
+    d = S.tomo_projection_inputs(4, [0])
+    geo = d["geometry"]
+    prob = O.make_problem(d["t"], geo)
+    t = to_dev(d["t"], dev)
+    psi = torch.empty((n, side, side), dtype=torch.complex64, device=dev)
+    S.project_ellipsoids_device(S.ellipsoid_phantom(side, 40, (S.BASE_SEED + 2,), 2.0),
+                                [np.pi * j / n for j in range(n)], side, side, geo.pixel_m, geo.wavelength_m, psi)
+    batch = PWF([problem_from_geometry(geo, t) for _ in range(n)])
+    ys = batch.forward([psi[j] for j in range(n)])
+    for j in range(1, n):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(S.BASE_SEED + 4 + j)
+        ys[j] = torch.poisson(ys[j].clamp(min=0.0) * 1.0e4, generator=gen).div_(1.0e4)
+    f0, _, _ = O.physical_model(d["psi_true"][0], prob)
+    y0 = S.poisson_intensity(f0, d["seed_keys"][0])
+    ys[0] = to_dev(y0, dev)
+    p0 = (scale_psi * d["psi_true"][0]).astype(np.complex64)
+    psi.mul_(scale_psi)
+    psi[0].copy_(to_dev(p0, dev))
+    return batch, psi, ys, prob, y0, p0, t, geo
+
+
+def test_differentiable_720x2048_full_size():
+    """PWFLoss (forward: model and misfit; backward: forward fields recomputed) over all
+    720 projections of 2048^2 at psi = 0.9 psi_true: projection 0's gradient against the
+    oracle's and central differences of the FP64 loss on 16 pixels, and bit for bit against
+    the same projection differentiated alone."""
+    import torch
+    from paper_2503_20146_amd import PWF, problem_from_geometry, pwf_loss
+    dev = device()
+    say("720 x 2048^2: generating the workload")
+    batch, psi, ys, prob, y0, p0, t, geo = _workload_720x2048(dev, 0.9)
+    say("720 x 2048^2: PWFLoss forward + backward over 720 projections")
+    p = psi.requires_grad_(True)
+    loss = pwf_loss(p, batch, ys)
+    loss.sum().backward()
+    assert bool(torch.isfinite(loss).all()) and bool(torch.isfinite(p.grad).all())
+    grad0 = p.grad[0].cpu().numpy()
+    l0 = float(loss[0].detach())
+    del batch, loss, ys[1:]
+    p.grad = None
+    torch.cuda.empty_cache()
+    say("720 x 2048^2: projection 0 alone")
+    p1 = to_dev(p0[None], dev).requires_grad_(True)
+    one = PWF([problem_from_geometry(geo, t)])
+    l1 = pwf_loss(p1, one, [ys[0]])
+    l1.sum().backward()
+    assert torch.equal(p1.grad[0].cpu(), torch.from_numpy(grad0)) and float(l1[0].detach()) == l0
+    say("720 x 2048^2: oracle gradient of projection 0")
+    l_ref, g_ref, _ = O.gradient(p0.astype(np.complex128), y0, prob)
+    f_ref, _, _ = O.physical_model(p0.astype(np.complex128), prob)
+    assert abs(l0 - l_ref) <= loss_tolerance(y0, f_ref) * l_ref
+    r = rel(grad0, 4 * np.max(np.abs(prob.t) ** 2) * g_ref)
+    say(f"720 x 2048^2: gradient rel-L2 {r:.2e}")
+    assert r <= 1e-4
+    say("720 x 2048^2: central differences on 16 pixels")
+    rng = np.random.default_rng(720)
+    pix = [tuple(int(v) for v in divmod(int(k), 2048)) for k in rng.choice(2048 * 2048, 16, replace=False)]
+    fd_check(p0, y0, prob, grad0, pix)
+
+
+def test_solve_720x2048_full_size():
+    """pwf_solve over all 720 projections of 2048^2, 20 iterations in one graph: projection 0
+    against the oracle's trajectory."""
+    import torch
+    dev = device()
+    say("720 x 2048^2: generating the workload")
+    batch, psi, ys, prob, y0, p0, t, geo = _workload_720x2048(dev, 1.0)
+    iters = 20
+    say("720 x 2048^2: solve, 20 iterations")
+    out, hist = batch.solve(ys, iters, psi_out=[psi[j] for j in range(720)])
+    torch.cuda.synchronize()
+    assert batch.sync_status() == 0
+    psi0 = psi[0].cpu().numpy()
+    h0 = hist[0].cpu().numpy()
+    del batch, ys, out, hist, psi
+    torch.cuda.empty_cache()
+    say("720 x 2048^2: oracle on projection 0")
+    psi_ref, hist_ref, _ = O.pwf(y0, prob, iters)
+    assert _rms(psi0.imag, psi_ref.imag) <= PHASE_TOL
+    assert _rms(psi0.real, psi_ref.real) <= PHASE_TOL
+    assert np.all(np.abs(h0 - hist_ref) / hist_ref <= loss_history_tolerance(y0, hist_ref))
 
 
 # On the 128^2 workload 1 - correlation runs 1.0e-4, 1.5e-5, 5.9e-6, ... 9.9e-7 (10th

@@ -181,6 +181,28 @@ def test_stf_relation_to_iotf():
         assert g2[0, 0] == 0.0 and np.all(g2 >= 0) and np.all(g2 <= 1)
 
 
+def test_source_forms_agree():
+    """The three ways to give the source describe the same windows for a Gaussian IPSF:
+    sigma px (Eq. 4 with x_coh = 2 sqrt(pi) sigma p), the coherence lengths (Eq. 5), and
+    the sampled IOTF with STF = IOTF^(2 gamma) (Eqs. 5, 14)."""
+    n, p = 48, 1e-6
+    rng = np.random.default_rng(21)
+    t = S.diffuser(rng, n, n)
+    sx, sy = 1.3, 0.7
+    geo = _geo(n, pixel_m=p, sigma_x_px=sx, sigma_y_px=sy)
+    for gamma in (1.0, 0.6):
+        a = O.make_problem(t, geo, gamma=gamma)
+        b = O.make_problem(t, _geo(n, pixel_m=p, sigma_x_px=0.0, sigma_y_px=0.0), gamma=gamma,
+                           coherence=(2 * math.sqrt(math.pi) * sx * p, 2 * math.sqrt(math.pi) * sy * p))
+        c = O.make_problem(t, _geo(n, pixel_m=p), gamma=gamma, iotf=a.iotf)
+        fy = np.fft.fftfreq(n)[:, None]
+        fx = np.fft.fftfreq(n)[None, :]
+        gauss = np.exp(-2 * math.pi ** 2 * (sx * sx * fx * fx + sy * sy * fy * fy))   # OTF of the IPSF
+        for prob in (a, b, c):
+            assert np.max(np.abs(prob.iotf - gauss)) <= 1e-15
+            assert np.max(np.abs(prob.gamma2 - (1 - gauss ** (2 * gamma)))) <= 1e-14
+
+
 # --------------------------------------------------------------------------- forward model
 
 def test_no_propagation_forward_and_gradient():
