@@ -79,16 +79,20 @@ SWEEP_KERNELS = ["row_sweep<1024, 0,", "col_sweep<1024, {w}, 0>", "row_sweep<102
                  "row_sweep<1024, 3,", "col_sweep<1024, {w}, 3>", "row_sweep<1024, 6,", "col_sweep<1024, {w}, 6>"]
 
 
+TUNING_CACHE = os.path.join(ROOT, "paper_2503_20146_amd", "tuning_cache.txt")
+RETUNE = False   # --retune: time every candidate again and rewrite this batch's cache entries
+
+
 def autotune(batch) -> dict:
-    """Pick column-tile widths and row plans per grid side (pwf_autotune); report the widths."""
-    from paper_2503_20146_amd import _lib
-    lib = _lib.load()
-    ws, nb = batch._ws()
-    import torch
-    _lib.check(lib.pwf_autotune(batch._c, batch.n, 5, ws, nb,
-                                __import__("ctypes").c_void_p(torch.cuda.current_stream().cuda_stream)),
-               "pwf_autotune")
-    return {n: [lib.pwf_column_tile(n, s) for s in range(1, 12, 2)] for n in sorted({p.ny for p in batch.problems})}
+    """Column-tile widths and row plans per grid side from the persistent tuning cache
+    (pwf_autotune_cached), timed afresh when the cache has no entry for this architecture and
+    class mix, or with --retune; returns the chosen schedule and where it came from."""
+    timed = batch.autotune(5, TUNING_CACHE, force=RETUNE)
+    lib = batch.lib
+    sides = sorted({p.ny for p in batch.problems} | {p.nx for p in batch.problems})
+    return {"source": "timed, written to the tuning cache" if timed else "tuning cache",
+            "column_tiles_S1_S3_S5_S7_S9_S11": {n: [lib.pwf_column_tile(n, s) for s in range(1, 12, 2)] for n in sides},
+            "row_plans_S0_S2_S4_S6_S8_S10": {n: [lib.pwf_row_plan(n, s) for s in range(0, 12, 2)] for n in sides}}
 
 
 def _read_counter_csv(path: str, counter: str):
@@ -338,8 +342,7 @@ def workload_720x2048(dev, iters: int) -> dict:
     res = {"value": round(value, 1), "unit": "proj-iter/s",
            "iteration_frac_of_hbm_roofline": round(value / roof, 4),
            "iteration_ms": round(sec / iters * 1e3, 2),
-           "column_tiles_S1_S3_S5_S7_S9_S11": tiles.get(side),
-           "row_plans_S0_S2_S4_S6_S8_S10": [batch.lib.pwf_row_plan(side, s) for s in range(0, 12, 2)],
+           "schedule": tiles,
            "autograd": {"forward_ms": round(fwd_ms, 1), "backward_ms": round(bwd_ms, 1),
                         "backward_proj_per_s": round(n / (bwd_ms / 1e3), 1), "finite": finite},
            "nonfinite_flag": status != 0,
@@ -374,13 +377,24 @@ def uneven_batch(dev, iters: int = 50) -> dict:
     f = batch.forward(psis)
     ys = [device_poisson(f[j], S.BASE_SEED + 3000 + j) for j in range(len(specs))]
     del f, psis
-    autotune(batch)
+    from paper_2503_20146_amd import set_merged_launch
+    sched = autotune(batch)
     batch.solve(ys, 2, loss_hist=False)
     torch.cuda.synchronize()
     sec = time_events(lambda: batch.solve(ys, iters, loss_hist=False))
+    # the same batch with one launch per sweep over the three size classes (merged kernels,
+    # tile widths and plans as tuned, the classes those kernels do not hold on their own)
+    set_merged_launch(True)
+    batch.solve(ys, 2, loss_hist=False)
+    torch.cuda.synchronize()
+    sec_m = time_events(lambda: batch.solve(ys, iters, loss_hist=False))
+    set_merged_launch(False)
     px = sum(side * side for side, _ in specs)
     frac = px * iters / sec * ITER_BYTES_PER_PX / (HBM_PEAK_GBS * 1e9)
     res = {"iteration_ms": round(sec / iters * 1e3, 3), "iteration_frac_of_hbm_roofline": round(frac, 4),
+           "launch": "one launch per size class per sweep, the classes on parallel streams",
+           "merged_launch_iteration_ms": round(sec_m / iters * 1e3, 3),
+           "schedule": sched,
            "config": f"24 x 512^2 + 32 x 1024^2 + 8 x 2048^2, 64 distinct instances, {iters} iterations"}
     del batch, ys, probs
     torch.cuda.empty_cache()
@@ -460,6 +474,9 @@ def main() -> int:
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs of a --sweep-only all run "
                          "into profiles/traffic_counters.json and exit")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every tile width and row plan again and rewrite the tuning cache's entries")
+    ap.add_argument("--tuning-cache", default=None, help="tuning cache file (default: the package's)")
     ap.add_argument("--iters-2048", type=int, default=10,
                     help="iterations of the timed 720 x 2048^2 solve (extras)")
     ap.add_argument("--workload", choices=["720x2048", "uneven"], default=None,
@@ -468,6 +485,10 @@ def main() -> int:
                     help="fix the column-tile width at 1024 instead of autotuning (counter runs)")
     args = ap.parse_args()
 
+    global RETUNE, TUNING_CACHE
+    RETUNE = args.retune
+    if args.tuning_cache:
+        TUNING_CACHE = args.tuning_cache
     if args.ingest_counters:
         return ingest_counters(*args.ingest_counters, projections=args.projections)
 
@@ -489,16 +510,17 @@ def main() -> int:
     batch, ys, geo, probs, d_inputs = build_workload(args.projections, dev)
     pixels = args.projections * geo.nx * geo.ny
 
-    tiles = {}
+    sched = {"source": "built-in defaults"}
     if args.col_tile:
         from paper_2503_20146_amd import _lib
         _lib.check(_lib.load().pwf_set_column_tile(1024, -1, args.col_tile), "pwf_set_column_tile")
-        tiles = {1024: [args.col_tile] * 6}
+        sched = {"source": f"--col-tile {args.col_tile}"}
     elif not args.no_autotune and args.sweep_only is None:
-        tiles = autotune(batch)
-        print(f"[bench] column tiles {tiles}", file=sys.stderr, flush=True)
+        sched = autotune(batch)
+        print(f"[bench] schedule {sched}", file=sys.stderr, flush=True)
     from paper_2503_20146_amd import _lib as _l
-    row_plans = {1024: [_l.load().pwf_row_plan(1024, s) for s in range(0, 12, 2)]}
+    sched["column_tiles_S1_S3_S5_S7_S9_S11"] = {1024: [_l.load().pwf_column_tile(1024, s) for s in range(1, 12, 2)]}
+    sched["row_plans_S0_S2_S4_S6_S8_S10"] = {1024: [_l.load().pwf_row_plan(1024, s) for s in range(0, 12, 2)]}
 
     if args.sweep_only is not None:
         batch.solve(ys, 2)
@@ -596,7 +618,7 @@ def main() -> int:
         "config": {"workload": f"{args.projections} projections x 1024^2 of a 40-ellipsoid phantom over 0-180 deg, "
                                f"shared diffuser, {args.iters} PWF iterations per step in one hipGraph",
                    "projections": args.projections, "grid": [geo.ny, geo.nx], "iterations_per_step": args.iters,
-                   "column_tiles_S1_S3_S5_S7_S9_S11": tiles, "row_plans_S0_S2_S4_S6_S8_S10": row_plans,
+                   "schedule": sched,
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "plain_baseline": plain, "extras": extras,
     }

@@ -290,12 +290,13 @@ int32_t pwf_column_tile(int32_t n, int32_t sweep);
 /* FFT plan of the row sweep S`sweep` of the iteration (sweep = 0, 2, 4, 6, 8
  * or 10) for grid side n: plan 0 is the side's default radix plan, 1 its
  * alternative plan with fewer elements per lane (e.g. 32x32 and 16x16x4 at
- * 1024), -1 restores the built-in choice.  PWF_ERR_SIZE / PWF_ERR_ARG for an
- * unsupported side, sweep or plan.  Process-wide; applies to calls issued
- * afterwards. */
+ * 1024), 2 (sides 1024 and 2048 only) the alternative's radices with the
+ * small radix first (4x16x16 at 1024, 8x16x16 at 2048); -1 restores the
+ * built-in choice.  PWF_ERR_SIZE / PWF_ERR_ARG for an unsupported side,
+ * sweep or plan.  Process-wide; applies to calls issued afterwards. */
 pwf_status pwf_set_row_plan(int32_t n, int32_t sweep, int32_t plan);
 
-/* Current plan (0 or 1) of row sweep S`sweep` for side n; -1 if unsupported. */
+/* Current plan (0, 1 or 2) of row sweep S`sweep` for side n; -1 if unsupported. */
 int32_t pwf_row_plan(int32_t n, int32_t sweep);
 
 /* Autotuner: for each grid shape in the batch, time each of the twelve
@@ -307,8 +308,31 @@ int32_t pwf_row_plan(int32_t n, int32_t sweep);
 pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, void* workspace,
                         size_t workspace_bytes, void* stream);
 
+/* Autotuner with a persistent cache: a text file at cache_path (host path,
+ * created when missing) keyed by the device's architecture, the batch's
+ * class mix (its grid shapes and instance counts) and the grid side, holding
+ * that side's column-tile widths (S1..S11) and row plans (S0..S10).  When
+ * every side of the batch has an entry for this architecture and mix, the
+ * stored choices are applied and nothing is timed (*tuned = 0, tuned may be
+ * NULL); otherwise, or with force != 0, pwf_autotune runs (same arguments)
+ * and its choices replace this batch's entries in the file (*tuned = 1).
+ * PWF_ERR_ARG when the file cannot be written. */
+pwf_status pwf_autotune_cached(const pwf_problem* problems, int32_t n, int32_t reps, const char* cache_path,
+                               int32_t force, int32_t* tuned, void* workspace, size_t workspace_bytes,
+                               void* stream);
+
 /* Capture pwf_solve's loop in a hipGraph (1, default) or launch eagerly (0). */
 void pwf_set_graph_mode(int32_t on);
+
+/* Batches of several grid shapes (pwf_solve): 1 launches each sweep of the
+ * iteration once over every size class, each workgroup running the sweep
+ * body of its class's side (sides 512, 1024 and 2048; at most 4 classes; a
+ * class whose row plan or column tile width the merged kernels do not hold
+ * gets a launch of its own in that sweep, and the autotuner, tuning such a
+ * batch, keeps to the plans and widths they hold); 0 (default) launches
+ * every class separately, the classes' iterations on parallel streams.
+ * Results are identical bit for bit.  Process-wide. */
+void pwf_set_merged_launch(int32_t on);
 
 /* Wait for `stream` and report PWF_ERR_NONFINITE if a loss computed by the
  * last call that used `workspace` was NaN or Inf, PWF_ERR_HIP on a runtime

@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     problem_from_geometry,
     set_column_tile,
     set_graph_mode,
+    set_merged_launch,
     set_row_plan,
     shell_correlation,
 )

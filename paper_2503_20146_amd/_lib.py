@@ -78,7 +78,10 @@ SIGNATURES = {
     "pwf_set_row_plan": (_i32, [_i32, _i32, _i32]),
     "pwf_row_plan": (_i32, [_i32, _i32]),
     "pwf_autotune": (_i32, [_P(pwf_problem), _i32, _i32, _vp, ctypes.c_size_t, _vp]),
+    "pwf_autotune_cached": (_i32, [_P(pwf_problem), _i32, _i32, ctypes.c_char_p, _i32, _P(_i32), _vp,
+                                   ctypes.c_size_t, _vp]),
     "pwf_set_graph_mode": (None, [_i32]),
+    "pwf_set_merged_launch": (None, [_i32]),
     "pwf_sync_status": (_i32, [_vp, _vp]),
     "pwf_speckle_workspace_size": (ctypes.c_size_t, []),
     "pwf_speckle_g2": (_i32, [_vp, _i32, _i32, _i32, _P(ctypes.c_double), _P(ctypes.c_double), _vp, ctypes.c_size_t,

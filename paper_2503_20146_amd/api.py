@@ -280,6 +280,20 @@ class PWF:
                                        ws, nb, _stream(self.device)), "pwf_solve_plain")
         return psi_out, hist
 
+    def autotune(self, reps: int = 5, cache_path: str | None = None, force: bool = False) -> bool:
+        """Pick column-tile widths and row plans for this batch's grid sides (pwf_autotune).
+        With ``cache_path`` the choices come from / go to that file (pwf_autotune_cached;
+        ``force`` times them again); returns True when timing ran, False when the cache
+        supplied every side."""
+        ws, nb = self._ws()
+        if cache_path is None:
+            check(self.lib.pwf_autotune(self._c, self.n, reps, ws, nb, _stream(self.device)), "pwf_autotune")
+            return True
+        tuned = ctypes.c_int32(0)
+        check(self.lib.pwf_autotune_cached(self._c, self.n, reps, str(cache_path).encode(), 1 if force else 0,
+                                           ctypes.byref(tuned), ws, nb, _stream(self.device)), "pwf_autotune_cached")
+        return bool(tuned.value)
+
     def bench_sweep(self, sweep: int, reps: int) -> None:
         """Launch fused sweep ``sweep`` (0..11) ``reps`` times on the state of the last solve."""
         ws, nb = self._ws()
@@ -293,6 +307,12 @@ class PWF:
 
 def set_graph_mode(on: bool) -> None:
     _lib.load().pwf_set_graph_mode(1 if on else 0)
+
+
+def set_merged_launch(on: bool) -> None:
+    """Uneven batches: one launch per sweep over all size classes (True) or per-class
+    launches on parallel streams (False, default)."""
+    _lib.load().pwf_set_merged_launch(1 if on else 0)
 
 
 def set_column_tile(n: int, width: int, sweep: int = -1) -> None:

@@ -6,8 +6,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
+#include <string>
 #include <memory>
 #include <mutex>
 #include <tuple>
@@ -58,6 +62,7 @@ struct Context {
   float2* tw[5] = {};          // row-plan twiddle tables per supported side
   float2* twc[5] = {};         // column-plan twiddle tables per supported side
   float2* twa[5] = {};         // alternative row-plan twiddle tables per supported side
+  float2* twa2[5] = {};        // third row-plan twiddle tables per supported side
   float2* twn[5] = {};         // w_N^m, m = 0..N-1, per supported side
   double* beta = nullptr;      // momentum table
   hipStream_t side = nullptr;  // internal stream for graph launches
@@ -98,8 +103,8 @@ int col_op_of_sweep(int sweep) {
   }
 }
 
-// Row plan per side and row sweep: -1 = default, 0 = RowCfg, 1 = RowCfgAlt.
-// Set by pwf_set_row_plan or pwf_autotune.
+// Row plan per side and row sweep: -1 = default, 0 = RowCfg, 1 = RowCfgAlt,
+// 2 = RowCfgAlt2 (sides with three plans).  Set by pwf_set_row_plan or pwf_autotune.
 int g_row_plan[5][16];
 struct RowPlanInit {
   RowPlanInit() {
@@ -108,10 +113,10 @@ struct RowPlanInit {
   }
 } g_row_plan_init;
 
-bool row_alt(int n, int op) {
+int row_plan(int n, int op) {
   const int i = size_index(n);
-  if (i < 0 || !pwf::row_plan_tunable(op) || g_row_plan[i][op] < 0) return pwf::row_alt_default_n(n, op);
-  return g_row_plan[i][op] == 1;
+  if (i < 0 || !pwf::row_plan_tunable(op) || g_row_plan[i][op] < 0) return pwf::row_alt_default_n(n, op) ? 1 : 0;
+  return g_row_plan[i][op];
 }
 
 // Row op of iteration sweep S0, S2, ..., S10 (-1 for other indices).
@@ -135,6 +140,10 @@ int g_tune_gen = 0;
 std::mutex g_mu;
 Context g_ctx[kMaxDevices];
 bool g_graph_mode = true;
+// Uneven batches: one launch per sweep over all size classes (1) or one launch
+// per class on parallel streams (0, default: the merged kernels carry the
+// register pressure of all their bodies and measured slower).
+int g_merge_mode = 0;
 
 pwf_status hip_fail(hipError_t e) { return e == hipSuccess ? PWF_OK : PWF_ERR_HIP; }
 #define PWF_HIP(call)                              \
@@ -148,7 +157,7 @@ pwf_status hip_fail(hipError_t e) { return e == hipSuccess ? PWF_OK : PWF_ERR_HI
 // supported side, and the momentum table.  `emit` receives each table and
 // returns where it will live on the device.
 struct HostTables {
-  std::vector<float2> plan[5][3];  // which = 0 row, 1 column, 2 alternative row
+  std::vector<float2> plan[5][4];  // which = 0 row, 1 column, 2 alternative row, 3 third row
   std::vector<float2> twn[5];
   std::vector<double> beta;
 };
@@ -157,7 +166,7 @@ const HostTables& host_tables() {
   static const HostTables T = [] {
     HostTables h;
     for (int i = 0; i < 5; ++i) {
-      for (int which = 0; which < 3; ++which) {
+      for (int which = 0; which < 4; ++which) {
         const int cnt = pwf::plan_twiddles(kSizes[i], which, nullptr);
         h.plan[i][which].assign(std::max(cnt, 1), make_float2(0.f, 0.f));
         pwf::plan_twiddles(kSizes[i], which, h.plan[i][which].data());
@@ -205,6 +214,7 @@ pwf_status context_for_current(Context** out) {
       PWF_TRY(put(h.plan[i][0], &c.tw[i]));
       PWF_TRY(put(h.plan[i][1], &c.twc[i]));
       PWF_TRY(put(h.plan[i][2], &c.twa[i]));
+      PWF_TRY(put(h.plan[i][3], &c.twa2[i]));
       PWF_TRY(put(h.twn[i], &c.twn[i]));
     }
     PWF_TRY(put(h.beta, &c.beta));
@@ -494,6 +504,20 @@ Batch group(const pwf_problem* probs, int n) {
   return b;
 }
 
+// A batch of several grid shapes is launched one sweep at a time over all its
+// classes (merged kernels) when merge mode is on, every side is one the merged
+// kernels hold and there are at most kMaxMerged classes.  Each class keeps its
+// own row plans and tile widths, so the results are those of per-class
+// launches; a class whose plan or width the merged kernels do not hold gets a
+// launch of its own in that sweep (the autotuner, tuning such a batch,
+// chooses among the plans and widths the merged kernels hold).
+bool batch_merged(const Batch& B) {
+  if (!g_merge_mode || B.classes.size() <= 1 || (int)B.classes.size() > pwf::kMaxMerged) return false;
+  for (const Class& c : B.classes)
+    if (pwf::multi_col_width(c.nx) == 0 || pwf::multi_col_width(c.ny) == 0) return false;
+  return true;
+}
+
 struct Launcher {
   Context& ctx;
   char* ws;
@@ -501,6 +525,11 @@ struct Launcher {
   const Batch& B;
   hipStream_t st;
   double corr_tol = 0.0;
+  bool merged = false;   // batch_merged(B): one launch per sweep over the classes
+  int width_of(int ny, int op) const { return col_width(ny, op); }
+  int plan_of(int nx, int op) const {
+    return row_plan(nx, op == pwf::ROW_PSI_UPDATE_CORR ? (int)pwf::ROW_PSI_UPDATE : op);
+  }
   Inst* dev_desc() const { return (Inst*)(ws + L.desc); }
   int32_t* status() const { return (int32_t*)(ws + L.status); }
 
@@ -511,6 +540,7 @@ struct Launcher {
     S.beta = ctx.beta;
     S.tw_row = ctx.tw[size_index(c.nx)];
     S.tw_alt = ctx.twa[size_index(c.nx)];
+    S.tw_alt2 = ctx.twa2[size_index(c.nx)];
     S.twn_row = ctx.twn[size_index(c.nx)];
     S.twn_col = ctx.twn[size_index(c.ny)];
     S.tw_col = ctx.twc[size_index(c.ny)];
@@ -522,19 +552,70 @@ struct Launcher {
   pwf_status row(int op, int iter = 0) const {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
-      const bool alt = row_alt(c.nx, op == pwf::ROW_PSI_UPDATE_CORR ? (int)pwf::ROW_PSI_UPDATE : op);
-      S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx, alt);
-      PWF_HIP(pwf::launch_row(c.nx, op, alt, S.blocks_per_inst * c.count, S, st));
+      const int plan = plan_of(c.nx, op);
+      S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx, plan);
+      PWF_HIP(pwf::launch_row(c.nx, op, plan, S.blocks_per_inst * c.count, S, st));
     }
     return PWF_OK;
   }
   pwf_status col(int op, int iter = 0) const {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
-      const int width = col_width(c.ny, op);
+      const int width = width_of(c.ny, op);
       S.blocks_per_inst = (pwf::col_op_half(op) ? c.nx / 2 : c.nx) / width;
       PWF_HIP(pwf::launch_col(c.ny, width, op, S.blocks_per_inst * c.count, S, st));
     }
+    return PWF_OK;
+  }
+  // One launch over the classes whose row plan (tile width) the merged
+  // kernels hold, and one launch per class for the others.
+  pwf_status row_merged(int op, int iter) const {
+    pwf::MultiSweep M;
+    std::memset(&M, 0, sizeof(M));
+    int total = 0, m = 0;
+    for (const Class& c : B.classes) {
+      const int plan = plan_of(c.nx, op);
+      Sweep S = sweep(c, iter);
+      S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx, plan);
+      if (!pwf::multi_row_supported(c.nx, plan) || m == pwf::kMaxMerged) {
+        PWF_HIP(pwf::launch_row(c.nx, op, plan, S.blocks_per_inst * c.count, S, st));
+        continue;
+      }
+      M.s[m] = S;
+      M.first[m] = total;
+      M.side[m] = c.nx;
+      M.plan[m] = plan;
+      total += S.blocks_per_inst * c.count;
+      ++m;
+    }
+    if (m == 0) return PWF_OK;
+    M.first[m] = total;
+    M.nc = m;
+    PWF_HIP(pwf::launch_row_multi(op, total, M, st));
+    return PWF_OK;
+  }
+  pwf_status col_merged(int op, int iter) const {
+    pwf::MultiSweep M;
+    std::memset(&M, 0, sizeof(M));
+    int total = 0, m = 0;
+    for (const Class& c : B.classes) {
+      const int width = width_of(c.ny, op);
+      Sweep S = sweep(c, iter);
+      S.blocks_per_inst = (pwf::col_op_half(op) ? c.nx / 2 : c.nx) / width;
+      if (width != pwf::multi_col_width(c.ny) || m == pwf::kMaxMerged) {
+        PWF_HIP(pwf::launch_col(c.ny, width, op, S.blocks_per_inst * c.count, S, st));
+        continue;
+      }
+      M.s[m] = S;
+      M.first[m] = total;
+      M.side[m] = c.ny;
+      total += S.blocks_per_inst * c.count;
+      ++m;
+    }
+    if (m == 0) return PWF_OK;
+    M.first[m] = total;
+    M.nc = m;
+    PWF_HIP(pwf::launch_col_multi(op, total, M, st));
     return PWF_OK;
   }
 };
@@ -597,6 +678,12 @@ size_t pwf_workspace_size(const pwf_problem* problems, int32_t n) {
 void pwf_set_graph_mode(int32_t on) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_graph_mode = on != 0;
+}
+
+void pwf_set_merged_launch(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_merge_mode = on != 0 ? 1 : 0;
+  ++g_tune_gen;   // cached graphs hold the other launch structure
 }
 
 }  // extern "C"
@@ -921,7 +1008,7 @@ struct JointCfg {
 pwf_status joint_step(const Launcher& K, const pwf_problem* probs, int n, const JointCfg& jc) {
   const pwf_problem& p = probs[0];
   const size_t m = (size_t)p.geom.nx * p.geom.ny;
-  const int count = p.geom.ny / pwf::row_rows_per_block(p.geom.nx, row_alt(p.geom.nx, pwf::ROW_MUL_T));
+  const int count = p.geom.ny / pwf::row_rows_per_block(p.geom.nx, row_plan(p.geom.nx, pwf::ROW_MUL_T));
   float2* t = (float2*)p.diffuser;
   PWF_HIP(pwf::launch_joint_update((float*)(K.ws + K.L.u1max), n, count, (size_t)p.geom.ny,
                                    (const float2*)(K.ws + K.L.u1[0]), field_bytes(p) / sizeof(float2), m, t,
@@ -961,6 +1048,26 @@ pwf_status solve_sequence(const Launcher& K, const pwf_problem* probs, int n, st
   };
   const int nc = (int)K.B.classes.size();
   if (nc <= 1 || jc.on) return iterate(K);
+  if (K.merged) {
+    // One launch per sweep over every size class (a sweep whose row plan or
+    // tile width the merged kernels do not hold is launched per class).
+    for (int k = 0; k < iters; ++k) {
+      PWF_TRY(K.row_merged(s0, k));
+      PWF_TRY(K.col_merged(pwf::COL_CHIRP1, k));
+      PWF_TRY(K.row_merged(pwf::ROW_MUL_T, k));
+      PWF_TRY(K.col_merged(pwf::COL_CHIRP2, k));
+      PWF_TRY(K.row_merged(pwf::ROW_INTENSITY, k));
+      PWF_TRY(K.col_merged(pwf::COL_BLUR_LOSS, k));
+      PWF_TRY(K.row_merged(pwf::ROW_BACKBLUR, k));
+      PWF_TRY(K.col_merged(pwf::COL_CHIRP2_CONJ, k));
+      PWF_TRY(K.row_merged(pwf::ROW_MUL_CONJ_T, k));
+      PWF_TRY(K.col_merged(pwf::COL_CHIRP1_CONJ, k));
+      PWF_TRY(K.row_merged(pwf::ROW_GRAD, k));
+      PWF_TRY(K.col_merged(pwf::COL_NESTEROV, k));
+    }
+    PWF_TRY(K.row(pwf::ROW_IFFT_OUT, iters));
+    return PWF_OK;
+  }
   // The size classes of an uneven batch are independent problems: their
   // iterations run on parallel streams (classes dealt round-robin), forked
   // from and joined back into K.st with events, so that a small class's short
@@ -1009,6 +1116,7 @@ pwf_status solve_impl(const pwf_problem* problems, int32_t n, const float* const
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   const Batch B = group(problems, n);
+  const bool merged = !jc.on && batch_merged(B);
   std::vector<Inst> desc(n);
   for (int s = 0; s < n; ++s) {
     const int i = B.order[s];
@@ -1032,7 +1140,7 @@ pwf_status solve_impl(const pwf_problem* problems, int32_t n, const float* const
     if (corr_mode) {
       I.corr_partial = (double*)(ws + L.corr[i]);
       I.n_corr_partials = problems[i].geom.ny /
-                          pwf::row_rows_per_block(problems[i].geom.nx, row_alt(problems[i].geom.nx, pwf::ROW_PSI_UPDATE));
+                          pwf::row_rows_per_block(problems[i].geom.nx, row_plan(problems[i].geom.nx, pwf::ROW_PSI_UPDATE));
       I.stop_iter = (int32_t*)(ws + L.stop) + i;
     }
   }
@@ -1059,6 +1167,7 @@ pwf_status solve_impl(const pwf_problem* problems, int32_t n, const float* const
   auto enqueue = [&](hipStream_t s) -> pwf_status {
     Launcher K{*ctx, ws, L, B, s};
     K.corr_tol = corr_tol;
+    K.merged = merged;
     if (corr_mode) PWF_HIP(pwf::launch_fill_zero(ws + L.stop, align_up(sizeof(int32_t) * n), s));
     std::vector<Inst> tmp = desc;
     PWF_TRY(launch_maxt2(problems, n, B, tmp, ws, L, s));
@@ -1083,6 +1192,7 @@ pwf_status solve_impl(const pwf_problem* problems, int32_t n, const float* const
   key.dims.push_back(corr_mode ? 1 : 0);
   key.dims.push_back(g_tune_gen);
   key.dims.push_back(jc.on ? 1 : 0);
+  key.dims.push_back(merged ? 1 : 0);
   for (double d : {corr_tol, jc.eta_t}) {
     int64_t bits;
     std::memcpy(&bits, &d, sizeof(bits));
@@ -1236,7 +1346,7 @@ pwf_status pwf_set_row_plan(int32_t n, int32_t sweep, int32_t plan) {
   const int i = size_index(n);
   if (i < 0) return PWF_ERR_SIZE;
   const int op = row_op_of_sweep(sweep);
-  if (op < 0 || plan < -1 || plan > 1) return PWF_ERR_ARG;
+  if (op < 0 || plan < -1 || plan >= pwf::row_plan_count_n(n)) return PWF_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_mu);
   g_row_plan[i][op] = plan;
   ++g_tune_gen;
@@ -1247,7 +1357,7 @@ int32_t pwf_row_plan(int32_t n, int32_t sweep) {
   const int op = row_op_of_sweep(sweep);
   if (size_index(n) < 0 || op < 0) return -1;
   std::lock_guard<std::mutex> lk(g_mu);
-  return row_alt(n, op) ? 1 : 0;
+  return row_plan(n, op);
 }
 
 pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, void* workspace,
@@ -1285,6 +1395,7 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
   PWF_HIP(hipEventCreate(&e0));
   PWF_HIP(hipEventCreate(&e1));
   pwf_status result = PWF_OK;
+  const bool merged = batch_merged(B);
   for (const Class& c : B.classes) {
     Batch one;
     one.order = B.order;
@@ -1308,9 +1419,10 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
       if (sweep & 1) {
         const int op = col_op_of_sweep(sweep);
         const int cands[2] = {pwf::col_default_width(c.ny), pwf::col_alt_width(c.ny)};
-        int best_w = col_width(c.ny, op);
+        int best_w = merged ? pwf::multi_col_width(c.ny) : col_width(c.ny, op);
         for (int w : cands) {
           if (c.nx % w) continue;
+          if (merged && w != pwf::multi_col_width(c.ny)) continue;
           g_col_width[cidx][op] = w;
           result = timed([&]() { return K.col(op); }, &ms);
           if (result != PWF_OK) break;
@@ -1322,8 +1434,10 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
         g_col_width[cidx][op] = best_w;
       } else {
         const int op = row_op_of_sweep(sweep);
-        int best_plan = row_alt(c.nx, op) ? 1 : 0;
-        for (int plan = 0; plan <= 1; ++plan) {
+        int best_plan = row_plan(c.nx, op);
+        if (merged && !pwf::multi_row_supported(c.nx, best_plan)) best_plan = c.nx == 512 ? 0 : 1;
+        for (int plan = 0; plan < pwf::row_plan_count_n(c.nx); ++plan) {
+          if (merged && !pwf::multi_row_supported(c.nx, plan)) continue;
           g_row_plan[ridx][op] = plan;
           result = timed([&]() { return K.row(op); }, &ms);
           if (result != PWF_OK) break;
@@ -1341,6 +1455,136 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   return result;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ persistent tuning cache
+//
+// One line per (architecture, class mix, grid side):
+//   <arch> <mix> <side> c <w S1> <w S3> <w S5> <w S7> <w S9> <w S11> r <p S0> <p S2> ... <p S10>
+// mix lists the batch's grid shapes and instance counts, e.g. 512x512*24+1024x1024*32.
+namespace {
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a(prop.gcnArchName);
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+std::string class_mix(const Batch& B) {
+  std::string m;
+  for (const Class& c : B.classes) {
+    if (!m.empty()) m += '+';
+    m += std::to_string(c.nx) + 'x' + std::to_string(c.ny) + '*' + std::to_string(c.count);
+  }
+  return m;
+}
+
+std::vector<int> batch_sides(const Batch& B) {
+  std::vector<int> sides;
+  for (const Class& c : B.classes)
+    for (int sd : {c.nx, c.ny})
+      if (std::find(sides.begin(), sides.end(), sd) == sides.end()) sides.push_back(sd);
+  std::sort(sides.begin(), sides.end());
+  return sides;
+}
+
+std::string tuning_line(const std::string& arch, const std::string& mix, int side) {
+  std::string l = arch + ' ' + mix + ' ' + std::to_string(side) + " c";
+  for (int sw = 1; sw < 12; sw += 2) l += ' ' + std::to_string(col_width(side, col_op_of_sweep(sw)));
+  l += " r";
+  for (int sw = 0; sw < 12; sw += 2) l += ' ' + std::to_string(row_plan(side, row_op_of_sweep(sw)));
+  return l;
+}
+
+// Apply the line's settings when it matches arch and mix; returns its side, or 0.
+int apply_tuning_line(const std::string& line, const std::string& arch, const std::string& mix) {
+  std::istringstream in(line);
+  std::string a, m, c, r;
+  int side = 0;
+  int w[6], pl[6];
+  if (!(in >> a >> m >> side >> c) || a != arch || m != mix || c != "c") return 0;
+  for (int& v : w)
+    if (!(in >> v)) return 0;
+  if (!(in >> r) || r != "r") return 0;
+  for (int& v : pl)
+    if (!(in >> v)) return 0;
+  const int i = size_index(side);
+  if (i < 0) return 0;
+  for (int k = 0; k < 6; ++k) {
+    if (!pwf::col_width_supported(side, w[k]) || pl[k] < 0 || pl[k] >= pwf::row_plan_count_n(side)) return 0;
+  }
+  for (int k = 0; k < 6; ++k) {
+    g_col_width[i][col_op_of_sweep(2 * k + 1)] = w[k];
+    g_row_plan[i][row_op_of_sweep(2 * k)] = pl[k];
+  }
+  return side;
+}
+
+}  // namespace
+
+extern "C" {
+
+pwf_status pwf_autotune_cached(const pwf_problem* problems, int32_t n, int32_t reps, const char* cache_path,
+                               int32_t force, int32_t* tuned, void* workspace, size_t workspace_bytes,
+                               void* stream) {
+  PWF_TRY(validate_batch(problems, n));
+  if (!cache_path || reps < 1) return PWF_ERR_ARG;
+  const Batch B = group(problems, n);
+  const std::vector<int> sides = batch_sides(B);
+  const std::string mix = class_mix(B);
+  std::vector<std::string> lines;
+  {
+    std::ifstream in(cache_path);
+    for (std::string l; std::getline(in, l);)
+      if (!l.empty()) lines.push_back(l);
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const std::string arch = device_arch();
+    std::vector<int> found;
+    for (const std::string& l : lines) {
+      std::istringstream in(l);
+      std::string a, m;
+      int side = 0;
+      if (in >> a >> m >> side && a == arch && m == mix && size_index(side) >= 0 &&
+          std::find(sides.begin(), sides.end(), side) != sides.end())
+        found.push_back(side);
+    }
+    bool all = !force;
+    for (int sd : sides) all = all && std::find(found.begin(), found.end(), sd) != found.end();
+    if (all) {
+      for (const std::string& l : lines) apply_tuning_line(l, arch, mix);
+      ++g_tune_gen;
+      if (tuned) *tuned = 0;
+      return PWF_OK;
+    }
+  }
+  PWF_TRY(pwf_autotune(problems, n, reps, workspace, workspace_bytes, stream));
+  std::lock_guard<std::mutex> lk(g_mu);
+  const std::string arch = device_arch();
+  std::vector<std::string> keep;
+  for (const std::string& l : lines) {
+    std::istringstream in(l);
+    std::string a, m;
+    if (in >> a >> m && a == arch && m == mix) continue;   // replaced below
+    keep.push_back(l);
+  }
+  for (int sd : sides) keep.push_back(tuning_line(arch, mix, sd));
+  const std::string tmp = std::string(cache_path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) return PWF_ERR_ARG;
+    for (const std::string& l : keep) out << l << '\n';
+    if (!out) return PWF_ERR_ARG;
+  }
+  if (std::rename(tmp.c_str(), cache_path) != 0) return PWF_ERR_ARG;
+  if (tuned) *tuned = 1;
+  return PWF_OK;
 }
 
 pwf_status pwf_solve_plain(const pwf_problem* problem, const float* y, void* psi_out, int32_t iters,
@@ -1846,6 +2090,7 @@ pwf_status scratch_for_current(ScratchDevice** out) {
       PWF_TRY(put(h.plan[i][0], &d.tables.tw[i]));
       PWF_TRY(put(h.plan[i][1], &d.tables.twc[i]));
       PWF_TRY(put(h.plan[i][2], &d.tables.twa[i]));
+      PWF_TRY(put(h.plan[i][3], &d.tables.twa2[i]));
       PWF_TRY(put(h.twn[i], &d.tables.twn[i]));
     }
     PWF_HIP(hipEventCreateWithFlags(&d.copied, hipEventDisableTiming));
@@ -1911,6 +2156,10 @@ void pwf_finalize(void) {
       t = nullptr;
     }
     for (float2*& t : c.twa) {
+      if (t) hipFree(t);
+      t = nullptr;
+    }
+    for (float2*& t : c.twa2) {
       if (t) hipFree(t);
       t = nullptr;
     }

@@ -180,6 +180,12 @@ template <> struct RowCfg<2048> { using Plan = FftPlan<2048, 32, 8, 8>;  static 
 template <int N> struct RowCfgAlt : RowCfg<N> {};
 template <> struct RowCfgAlt<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  RW = 4; };
 template <> struct RowCfgAlt<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, RW = 2; };
+// A third plan on the large sides: the alternative plan's radices in the other
+// order (small radix first), searched by the autotuner.
+template <int N> struct RowCfgAlt2 : RowCfg<N> {};
+template <> struct RowCfgAlt2<1024> { using Plan = FftPlan<1024, 4, 16, 16>; static constexpr int T = 64,  RW = 4; };
+template <> struct RowCfgAlt2<2048> { using Plan = FftPlan<2048, 8, 16, 16>; static constexpr int T = 128, RW = 2; };
+template <int N> constexpr int row_plan_count() { return (N == 1024 || N == 2048) ? 3 : 2; }
 
 // Column sweeps: T lanes per column and W adjacent columns per workgroup
 // (lane index = t * W + w, so the W columns of one row are one coalesced
@@ -189,7 +195,7 @@ template <> struct ColCfg<128>  { using Plan = FftPlan<128, 16, 8>;      static 
 template <> struct ColCfg<256>  { using Plan = FftPlan<256, 16, 16>;     static constexpr int T = 16,  WA = 16, WB = 32; };
 template <> struct ColCfg<512>  { using Plan = FftPlan<512, 16, 8, 4>;   static constexpr int T = 32,  WA = 16, WB = 8; };
 template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  WA = 8,  WB = 4; };
-template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, WA = 4,  WB = 2; };
+template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, WA = 4,  WB = 8; };
 
 // Arguments common to every sweep launch.
 struct Sweep {
@@ -199,11 +205,24 @@ struct Sweep {
   const double* beta;     // momentum table (Algorithm S1), indexed by k0 + iter
   const float2* tw_row;   // twiddles of the row plan (forward, then reversed plan)
   const float2* tw_alt;   // twiddles of the alternative row plan (forward, then reversed plan)
+  const float2* tw_alt2;  // twiddles of the third row plan (forward, then reversed plan)
   const float2* twn_row;  // w_nx^m, m = 0..nx-1
   const float2* twn_col;  // w_ny^m, m = 0..ny-1
   const float2* tw_col;   // twiddles of the column plan (forward, then reversed plan)
   int32_t* status;        // bit 0: non-finite loss seen
   double corr_tol;        // stopping correlation threshold (used when corr_partial is set)
+};
+
+// One launch over several size classes: class c owns the logical blocks
+// [first[c], first[c + 1]) and runs the sweep body of its side and plan (row
+// sweeps) or side (column sweeps) with its own Sweep arguments.
+constexpr int kMaxMerged = 4;
+struct MultiSweep {
+  Sweep s[kMaxMerged];
+  int32_t first[kMaxMerged + 1];
+  int32_t side[kMaxMerged];
+  int32_t plan[kMaxMerged];
+  int32_t nc;
 };
 
 // True when the instance has met the correlation stop: its sweeps are skipped.

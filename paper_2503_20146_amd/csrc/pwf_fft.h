@@ -33,6 +33,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 __host__ __device__ constexpr int bitrev(int x, int bits) {
   int r = 0;

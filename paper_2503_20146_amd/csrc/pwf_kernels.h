@@ -25,9 +25,9 @@ enum RowOp {
   ROW_PSI_UPDATE_CORR, // S0 with the stopping rule's sums (runs with the plan of ROW_PSI_UPDATE)
 };
 
-// Row sweeps of the iteration (S0, S2, S4, S6, S8, S10) are compiled with both
-// plans of their side and the plan is chosen at run time (pwf_set_row_plan,
-// pwf_autotune).  Default (what the autotuner picks on the 180 x 1024^2
+// Row sweeps of the iteration (S0, S2, S4, S6, S8, S10) are compiled with every
+// plan of their side (two, three at 1024 and 2048) and the plan is chosen at
+// run time (pwf_set_row_plan, pwf_autotune).  Default (what the autotuner picks on the 180 x 1024^2
 // workload): the alternative plan (RowCfgAlt) for every tunable sweep at 1024,
 // for the update, intensity and gradient sweeps at 2048, for the update sweep
 // elsewhere.  Other row sweeps always use RowCfg.
@@ -77,13 +77,23 @@ enum PlainOp {
 };
 
 bool row_alt_default_n(int n, int op);
-int row_rows_per_block(int n, bool alt);
+int row_plan_count_n(int n);
+int row_rows_per_block(int n, int plan);
 int col_default_width(int n);
 int col_alt_width(int n);
 bool col_width_supported(int n, int w);
-hipError_t launch_row(int nx, int op, bool alt, int nblocks, const Sweep& S, hipStream_t st);
+hipError_t launch_row(int nx, int op, int plan, int nblocks, const Sweep& S, hipStream_t st);
 hipError_t launch_col(int ny, int width, int op, int nblocks, const Sweep& S, hipStream_t st);
 hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st);
+
+// Merged launches over size classes (pwf_sweeps_multi.hip).  A class can join a
+// merged row sweep when multi_row_supported(nx, plan) and a merged column sweep
+// when multi_col_width(ny) > 0 (the tile width the merged kernel uses); ops are
+// the twelve sweeps of the iteration.
+bool multi_row_supported(int nx, int plan);
+int multi_col_width(int ny);
+hipError_t launch_row_multi(int op, int nblocks, const MultiSweep& M, hipStream_t st);
+hipError_t launch_col_multi(int op, int nblocks, const MultiSweep& M, hipStream_t st);
 
 hipError_t launch_plain_rows(int nx, int dir, const float2* src, float2* dst, int ny, const float2* tw,
                              hipStream_t st);
@@ -137,9 +147,9 @@ hipError_t launch_joint_update(float* u1max, int n, int count, size_t max_stride
 int maxabs2_blocks();
 hipError_t launch_maxabs2(const float2* t, size_t m, float* partial, float* out, hipStream_t st);
 
-// Number of float2 twiddles of the N-point row (which = 0) or column (which =
-// 1) plan, forward and reversed; fills `out` when it is not null.  Returns -1
-// for unsupported N.
+// Number of float2 twiddles of the N-point row (which = 0), column (1),
+// alternative row (2) or third row (3) plan, forward and reversed; fills
+// `out` when it is not null.  Returns -1 for unsupported N.
 int plan_twiddles(int n, int which, float2* out);
 
 }  // namespace pwf

@@ -209,14 +209,14 @@ hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st) {
 // ------------------------------------------------------------------ host dispatch
 
 #define PWF_DECLARE_SIDE(N)                                                                              \
-  template <int M> hipError_t launch_row_n(int op, bool alt, int nblocks, const Sweep& S, hipStream_t st); \
+  template <int M> hipError_t launch_row_n(int op, int plan, int nblocks, const Sweep& S, hipStream_t st); \
   template <int M> hipError_t launch_col_n(int w, int op, int nblocks, const Sweep& S, hipStream_t st); \
   template <int M> hipError_t plain_rows_n(int dir, const float2* src, float2* dst, int ny,             \
                                            const float2* tw, hipStream_t st);                          \
   template <int M> hipError_t plain_cols_n(int dir, float2* a, int nx, const float2* tw, int planes,   \
                                            size_t plane_stride, hipStream_t st);                       \
   template <int M> int plan_twiddles_n(int which, float2* out);                                       \
-  extern template hipError_t launch_row_n<N>(int, bool, int, const Sweep&, hipStream_t);               \
+  extern template hipError_t launch_row_n<N>(int, int, int, const Sweep&, hipStream_t);                \
   extern template hipError_t launch_col_n<N>(int, int, int, const Sweep&, hipStream_t);                \
   extern template hipError_t plain_rows_n<N>(int, const float2*, float2*, int, const float2*, hipStream_t); \
   extern template hipError_t plain_cols_n<N>(int, float2*, int, const float2*, int, size_t, hipStream_t); \
@@ -239,13 +239,28 @@ bool row_alt_default_n(int n, int op) {
   }
 }
 
-int row_rows_per_block(int n, bool alt) {
+int row_plan_count_n(int n) {
   switch (n) {
-    case 128: return alt ? RowCfgAlt<128>::RW : RowCfg<128>::RW;
-    case 256: return alt ? RowCfgAlt<256>::RW : RowCfg<256>::RW;
-    case 512: return alt ? RowCfgAlt<512>::RW : RowCfg<512>::RW;
-    case 1024: return alt ? RowCfgAlt<1024>::RW : RowCfg<1024>::RW;
-    case 2048: return alt ? RowCfgAlt<2048>::RW : RowCfg<2048>::RW;
+    case 128: return row_plan_count<128>();
+    case 256: return row_plan_count<256>();
+    case 512: return row_plan_count<512>();
+    case 1024: return row_plan_count<1024>();
+    case 2048: return row_plan_count<2048>();
+    default: return 0;
+  }
+}
+
+template <int N> int rows_per_block_of(int plan) {
+  return plan == 2 ? RowCfgAlt2<N>::RW : plan == 1 ? RowCfgAlt<N>::RW : RowCfg<N>::RW;
+}
+
+int row_rows_per_block(int n, int plan) {
+  switch (n) {
+    case 128: return rows_per_block_of<128>(plan);
+    case 256: return rows_per_block_of<256>(plan);
+    case 512: return rows_per_block_of<512>(plan);
+    case 1024: return rows_per_block_of<1024>(plan);
+    case 2048: return rows_per_block_of<2048>(plan);
     default: return 0;
   }
 }
@@ -283,13 +298,13 @@ int col_alt_width(int n) {
   }
 }
 
-hipError_t launch_row(int nx, int op, bool alt, int nblocks, const Sweep& S, hipStream_t st) {
+hipError_t launch_row(int nx, int op, int plan, int nblocks, const Sweep& S, hipStream_t st) {
   switch (nx) {
-    case 128: return launch_row_n<128>(op, alt, nblocks, S, st);
-    case 256: return launch_row_n<256>(op, alt, nblocks, S, st);
-    case 512: return launch_row_n<512>(op, alt, nblocks, S, st);
-    case 1024: return launch_row_n<1024>(op, alt, nblocks, S, st);
-    case 2048: return launch_row_n<2048>(op, alt, nblocks, S, st);
+    case 128: return launch_row_n<128>(op, plan, nblocks, S, st);
+    case 256: return launch_row_n<256>(op, plan, nblocks, S, st);
+    case 512: return launch_row_n<512>(op, plan, nblocks, S, st);
+    case 1024: return launch_row_n<1024>(op, plan, nblocks, S, st);
+    case 2048: return launch_row_n<2048>(op, plan, nblocks, S, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -134,22 +134,34 @@ template <int NX, int OP> constexpr int row_min_waves() {
   return (OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR) ? 3 : OP == ROW_GRAD ? (NX >= 2048 ? 2 : 3) : 4;
 }
 
-template <int NX, bool ALT>
-using RowCfgSel = typename std::conditional<ALT, RowCfgAlt<NX>, RowCfg<NX>>::type;
+template <int NX, int PLAN>
+using RowCfgSel = typename std::conditional<PLAN == 2, RowCfgAlt2<NX>,
+                                            typename std::conditional<PLAN == 1, RowCfgAlt<NX>, RowCfg<NX>>::type>::type;
 
-template <int NX, bool ALT> constexpr int row_threads() { return RowCfgSel<NX, ALT>::T * RowCfgSel<NX, ALT>::RW; }
+template <int NX, int PLAN> constexpr int row_threads() { return RowCfgSel<NX, PLAN>::T * RowCfgSel<NX, PLAN>::RW; }
 
-template <int NX, int OP, bool ALT>
-__global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, OP>())) row_sweep(Sweep S) {
-  using C = RowCfgSel<NX, ALT>;
+// LDS a row sweep needs: the exchange buffer and the staged twiddles.  The
+// update sweep stages half of w_N^m: the 4 KB saved let a fourth workgroup of
+// the 16x16x4 plan fit in a CU's LDS (its registers allow it).
+template <int NX, int OP, int PLAN>
+struct RowLds {
+  using C = RowCfgSel<NX, PLAN>;
+  using TS = TwSel<typename C::Plan, OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR>;
+  static constexpr int kExchange = C::RW * lds_len(NX);
+  static constexpr int kTwiddles = TS::kLds;
+};
+
+// Row sweep `OP` on logical block b (instance b / blocks_per_inst) with the
+// caller's LDS (RowLds sizes).
+template <int NX, int OP, int PLAN>
+__device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, float2* twl) {
+  using C = RowCfgSel<NX, PLAN>;
   using Plan = typename C::Plan;
   constexpr int T = C::T, RW = C::RW, E = NX / T;
   constexpr int R1 = Plan::radix[0], RL = Plan::radix[Plan::NPASS - 1];
   constexpr int M1 = NX / R1, ML = NX / RL;
   constexpr bool IN_FREQ = RowOpTraits<OP>::kInFreq, OUT_FREQ = RowOpTraits<OP>::kOutFreq;
-  __shared__ float2 lds[RW * lds_len(NX)];
 
-  const int b = xcd_contiguous<false>(blockIdx.x, gridDim.x);
   const int inst = b / S.blocks_per_inst;
   const int blk = b - inst * S.blocks_per_inst;
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
@@ -157,17 +169,14 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   const int t = threadIdx.x % T, rw = threadIdx.x / T;
   const int row = blk * RW + rw;
   const LdsView lv{lds + rw * lds_len(NX), 1};
-  // The update sweep stages half of w_N^m: the 4 KB saved let a fourth
-  // workgroup of the 16x16x4 plan fit in a CU's LDS (its registers allow it).
-  using TS = TwSel<Plan, OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR>;
-  __shared__ float2 twl[TS::kLds];
-  const float2* twg = ALT ? S.tw_alt : S.tw_row;
+  using TS = typename RowLds<NX, OP, PLAN>::TS;
+  const float2* twg = PLAN == 2 ? S.tw_alt2 : PLAN == 1 ? S.tw_alt : S.tw_row;
   const auto tw = TS::forward(twl, twg);
   const auto twr = TS::inverse(twl, twg);
   const uint32_t rbase = (uint32_t)row * NX;
   // Twiddles to LDS; the first pass needs none, and the barrier after its
   // LDS exchange orders these writes before the first use.
-  TwStage<TS::kLds, row_threads<NX, ALT>()> tws;
+  TwStage<TS::kLds, row_threads<NX, PLAN>()> tws;
   if constexpr (TS::kMode != 0) tws.load(TS::staged_from(twg, S.twn_row));
   auto load_twiddles = [&]() {
     if constexpr (TS::kMode != 0) tws.store(twl);
@@ -421,6 +430,13 @@ __global__ void __launch_bounds__((row_threads<NX, ALT>()), (row_min_waves<NX, O
   }
 }
 
+template <int NX, int OP, int PLAN>
+__global__ void __launch_bounds__((row_threads<NX, PLAN>()), (row_min_waves<NX, OP>())) row_sweep(Sweep S) {
+  __shared__ float2 lds[RowLds<NX, OP, PLAN>::kExchange];
+  __shared__ float2 twl[RowLds<NX, OP, PLAN>::kTwiddles];
+  row_body<NX, OP, PLAN>(S, xcd_contiguous<false>(blockIdx.x, gridDim.x), lds, twl);
+}
+
 // ------------------------------------------------------------------ column sweeps
 
 // Column tile of the j-th workgroup of an instance with B tiles of W columns.
@@ -481,21 +497,27 @@ template <int NY, int W, int OP> constexpr int col_min_waves() {
          : (OP == COL_NESTEROV || OP == COL_DIRECTION) && !(NY == 256 && W == 16) ? 3 : 2;
 }
 
+// LDS a column sweep needs: the exchange buffer and the staged twiddles (at
+// 2048 points the half table still leaves room for two 4-column tiles per CU).
+template <int NY, int W>
+struct ColLds {
+  using TS = TwSel<typename ColCfg<NY>::Plan, false, true>;
+  static constexpr int kExchange = W * lds_len(NY);
+  static constexpr int kTwiddles = TS::kLds;
+};
+
+// Column sweep `OP` on logical block b (instance b / blocks_per_inst) with the
+// caller's LDS (ColLds sizes).
 template <int NY, int W, int OP>
-__global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>())) col_sweep(Sweep S) {
+__device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, float2* twl) {
   using C = ColCfg<NY>;
   using Plan = typename C::Plan;
   constexpr int T = C::T, E = NY / T;
   constexpr int R1 = Plan::radix[0], RL = Plan::radix[Plan::NPASS - 1];
   constexpr int M1 = NY / R1, ML = NY / RL;
   constexpr int NT = T * W;
-  __shared__ float2 lds[W * lds_len(NY)];
   __shared__ double red[(NT + 63) / 64];
 
-  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous range of tiles so that tiles sharing 128-byte lines meet in
-  // the same L2.
-  const int b = xcd_contiguous<true>(blockIdx.x, gridDim.x);
   const int inst = b / S.blocks_per_inst;
   const int tile = col_tile_of<W>(b - inst * S.blocks_per_inst, S.blocks_per_inst);
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
@@ -518,9 +540,7 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
   const int s = tile * W + w;
   const uint32_t o_ld = (uint32_t)(t * nx + s);  // element (t, s); row r adds r nx
   const LdsView lv{lds + w, W};
-  // at 2048 points the half table still leaves room for two 4-column tiles per CU
-  using TS = TwSel<Plan, false, true>;
-  __shared__ float2 twl[TS::kLds];
+  using TS = typename ColLds<NY, W>::TS;
   const auto tw = TS::forward(twl, S.tw_col);
   const auto twr = TS::inverse(twl, S.tw_col);
 
@@ -744,6 +764,16 @@ __global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>()
   }
 }
 
+template <int NY, int W, int OP>
+__global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>())) col_sweep(Sweep S) {
+  __shared__ float2 lds[ColLds<NY, W>::kExchange];
+  __shared__ float2 twl[ColLds<NY, W>::kTwiddles];
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of tiles so that tiles sharing 128-byte lines meet in
+  // the same L2.
+  col_body<NY, W, OP>(S, xcd_contiguous<true>(blockIdx.x, gridDim.x), lds, twl);
+}
+
 // ------------------------------------------------------------------ plain path kernels
 
 // Out-of-place FFT of every row (natural order in and out).
@@ -823,20 +853,29 @@ plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw, size_t plane_st
   }
 }
 
-template <int N, int OP, bool ALT>
+template <int N, int OP, int PLAN>
 hipError_t launch_row_one(int nblocks, const Sweep& S, hipStream_t st) {
-  hipLaunchKernelGGL((row_sweep<N, OP, ALT>), dim3(nblocks), dim3(row_threads<N, ALT>()), 0, st, S);
+  hipLaunchKernelGGL((row_sweep<N, OP, PLAN>), dim3(nblocks), dim3(row_threads<N, PLAN>()), 0, st, S);
   return hipGetLastError();
 }
 
-// Row sweep `op` with the alternative plan when `alt` (tunable sweeps only;
-// the others always run with their default plan).
+// Row sweep `op` with radix plan `plan` (tunable sweeps only; the others
+// always run with their default plan).
+template <int N, int OP>
+hipError_t launch_row_plan(int plan, int nblocks, const Sweep& S, hipStream_t st) {
+  if (plan == 1) return launch_row_one<N, OP, 1>(nblocks, S, st);
+  if constexpr (row_plan_count<N>() > 2) {
+    if (plan == 2) return launch_row_one<N, OP, 2>(nblocks, S, st);
+  }
+  if (plan == 0) return launch_row_one<N, OP, 0>(nblocks, S, st);
+  return hipErrorInvalidValue;
+}
+
 template <int N>
-hipError_t launch_row_n(int op, bool alt, int nblocks, const Sweep& S, hipStream_t st) {
+hipError_t launch_row_n(int op, int plan, int nblocks, const Sweep& S, hipStream_t st) {
   switch (op) {
-#define PWF_TUNABLE(o) \
-  case o: return alt ? launch_row_one<N, o, true>(nblocks, S, st) : launch_row_one<N, o, false>(nblocks, S, st);
-#define PWF_FIXED(o) case o: return launch_row_one<N, o, row_alt_default<N>(o)>(nblocks, S, st);
+#define PWF_TUNABLE(o) case o: return launch_row_plan<N, o>(plan, nblocks, S, st);
+#define PWF_FIXED(o) case o: return launch_row_one<N, o, row_alt_default<N>(o) ? 1 : 0>(nblocks, S, st);
     PWF_TUNABLE(ROW_PSI_UPDATE) PWF_TUNABLE(ROW_PSI_UPDATE_CORR) PWF_TUNABLE(ROW_MUL_T) PWF_TUNABLE(ROW_MUL_CONJ_T) PWF_TUNABLE(ROW_INTENSITY)
     PWF_TUNABLE(ROW_BACKBLUR) PWF_TUNABLE(ROW_GRAD)
     PWF_FIXED(ROW_START) PWF_FIXED(ROW_FORWARD_OUT) PWF_FIXED(ROW_REAL_FFT) PWF_FIXED(ROW_CPLX_FFT)
@@ -901,7 +940,8 @@ static void fill_twiddles(float2* out) {
 }
 
 // Twiddle tables of an N-point plan followed by those of its reversed plan:
-// which = 0 for the row plan, 1 for the column plan, 2 for the alternative row plan.
+// which = 0 for the row plan, 1 for the column plan, 2 for the alternative row
+// plan, 3 for the third row plan.
 template <int N>
 int plan_twiddles_n(int which, float2* out) {
   auto emit = [&](auto tag) {
@@ -914,8 +954,10 @@ int plan_twiddles_n(int which, float2* out) {
     }
     return Plan::tw_total() + RPlan::tw_total();
   };
-  return which == 0 ? emit(typename RowCfg<N>::Plan{})
-                    : which == 1 ? emit(typename ColCfg<N>::Plan{}) : emit(typename RowCfgAlt<N>::Plan{});
+  return which == 0   ? emit(typename RowCfg<N>::Plan{})
+         : which == 1 ? emit(typename ColCfg<N>::Plan{})
+         : which == 2 ? emit(typename RowCfgAlt<N>::Plan{})
+                      : emit(typename RowCfgAlt2<N>::Plan{});
 }
 
 }  // namespace pwf

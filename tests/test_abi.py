@@ -72,15 +72,19 @@ def test_tuning_settings(lib):
     assert [lib.pwf_row_plan(2048, s) for s in range(0, 12, 2)] == [1, 0, 1, 0, 0, 1]
     assert lib.pwf_row_plan(1024, 1) == -1 and lib.pwf_row_plan(100, 0) == -1
     assert lib.pwf_set_row_plan(1024, 3, 0) == -1      # S3 is a column sweep
-    assert lib.pwf_set_row_plan(1024, 2, 2) == -1
+    assert lib.pwf_set_row_plan(1024, 2, 3) == -1
+    assert lib.pwf_set_row_plan(512, 2, 2) == -1        # two plans below 1024
     assert lib.pwf_set_row_plan(96, 2, 1) == -2
     try:
         assert lib.pwf_set_row_plan(1024, 2, 0) == 0
         assert lib.pwf_row_plan(1024, 2) == 0
         assert lib.pwf_set_row_plan(2048, 2, 1) == 0
         assert lib.pwf_row_plan(2048, 2) == 1
+        assert lib.pwf_set_row_plan(1024, 4, 2) == 0
+        assert lib.pwf_row_plan(1024, 4) == 2
     finally:
         lib.pwf_set_row_plan(1024, 2, -1)
+        lib.pwf_set_row_plan(1024, 4, -1)
         lib.pwf_set_row_plan(2048, 2, -1)
     assert lib.pwf_row_plan(1024, 2) == 1 and lib.pwf_row_plan(2048, 2) == 0
 

@@ -226,10 +226,10 @@ def test_solve_parity_workload1_100_iterations():
     assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
-@pytest.mark.parametrize("plan", [0, 1])
+@pytest.mark.parametrize("plan", [0, 1, 2])
 def test_row_plans_match_oracle(plan):
-    """Every tunable row sweep forced onto one radix plan (32x32 or 16x16x4 at
-    1024; the autotuner may pick either per sweep): forward, gradient and 30
+    """Every tunable row sweep forced onto one radix plan (32x32, 16x16x4 or 4x16x16 at
+    1024; the autotuner may pick any per sweep): forward, gradient and 30
     iterations against the oracle, and the graph vs eager solve agree."""
     from paper_2503_20146_amd import set_graph_mode, set_row_plan
     dev = device()
@@ -261,7 +261,70 @@ def test_row_plans_match_oracle(plan):
     assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
-ALT_TILE = {128: 16, 256: 32, 512: 8, 1024: 4, 2048: 2}   # the second compiled width per side
+@pytest.mark.parametrize("plan", [0, 1, 2])
+def test_row_plans_2048_match_oracle(plan):
+    """Every tunable row sweep at 2048 forced onto one radix plan (32x8x8, 16x16x8 or
+    8x16x16): forward and 6 iterations against the oracle."""
+    from paper_2503_20146_amd import set_row_plan
+    dev = device()
+    inp, geo, prob, y = instance(3, n=2048, instance=56)
+    say(f"row plan {plan} at 2048^2")
+    for s in range(0, 12, 2):
+        set_row_plan(2048, s, plan)
+    try:
+        batch = _pwf([gpu_problem(geo, inp["t"], dev)])
+        psi0 = (0.5 * inp["psi_true"]).astype(np.complex64)
+        f = batch.forward([to_dev(psi0, dev)])[0].cpu().numpy()
+        out, hist = batch.solve([to_dev(y, dev)], 6)
+    finally:
+        for s in range(0, 12, 2):
+            set_row_plan(2048, s, -1)
+    f_ref, _, _ = O.physical_model(psi0.astype(np.complex128), prob)
+    assert rel(f, f_ref) <= FWD_TOL
+    psi_ref, hist_ref, _ = O.pwf(y, prob, 6)
+    assert np.sqrt(np.mean(np.abs(out[0].cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL
+    assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """pwf_autotune_cached: the first call times and writes the batch's sides; a second call
+    on the same class mix reads them back without timing; force times again; another
+    class mix gets entries of its own beside the first."""
+    from paper_2503_20146_amd import _lib, set_column_tile, set_row_plan
+    dev = device()
+    lib = _lib.load()
+    say("autotune cache round trip")
+    inps = [instance(0, instance=i) for i in range(2)] + [instance(3, n=256, instance=1)]
+    mixed = _pwf([gpu_problem(x[1], x[0]["t"], dev) for x in inps])
+    path = tmp_path / "tuning.txt"
+
+    def state():
+        return ([lib.pwf_column_tile(n, s) for n in (128, 256) for s in range(1, 12, 2)],
+                [lib.pwf_row_plan(n, s) for n in (128, 256) for s in range(0, 12, 2)])
+
+    def reset():
+        for n in (128, 256):
+            set_column_tile(n, 0)
+            for s in range(0, 12, 2):
+                set_row_plan(n, s, -1)
+    try:
+        assert mixed.autotune(2, path) is True
+        tuned = state()
+        lines = path.read_text().splitlines()
+        assert len(lines) == 2 and all("128x128*2+256x256*1" in ln for ln in lines)
+        reset()
+        assert mixed.autotune(2, path) is False
+        assert state() == tuned
+        assert mixed.autotune(2, path, force=True) is True
+        assert len(path.read_text().splitlines()) == 2
+        alone = _pwf([gpu_problem(inps[0][1], inps[0][0]["t"], dev)])
+        assert alone.autotune(2, path) is True
+        assert len(path.read_text().splitlines()) == 3
+    finally:
+        reset()
+
+
+ALT_TILE = {128: 16, 256: 32, 512: 8, 1024: 4, 2048: 8}   # the second compiled width per side
 
 
 @pytest.mark.parametrize("side", [128, 256, 512, 1024, 2048])

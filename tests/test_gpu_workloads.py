@@ -116,6 +116,49 @@ def test_uneven_roi_batch_64_instances():
         assert np.all(np.abs(hist[i].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref)), i
 
 
+def test_uneven_merged_launch_equals_per_class():
+    """One launch per sweep over the 512^2, 1024^2 and 2048^2 classes equals the classes
+    launched separately on parallel streams, bit for bit, eagerly and in graph replays
+    (with eager work and synchronisations between the replays)."""
+    import torch
+    from paper_2503_20146_amd import PWF, set_graph_mode, set_merged_launch
+    dev = device()
+    say("merged vs per-class launches: 2 x 512^2 + 2 x 1024^2 + 1 x 2048^2")
+    specs = S.roi_batch_specs()
+    pick = [0, 1, 24, 25, 56]
+    probs, ys = [], []
+    for i in pick:
+        side, sigma = specs[i]
+        inp = S.instance_inputs(3, side, instance=i, sigma_px=sigma)
+        probs.append(gpu_problem(inp["geometry"], inp["t"], dev))
+        ys.append(to_dev(S.poisson_intensity(np.clip(1.0 + 0.1 * inp["psi_true"].imag, 0, None), inp["seed_key"]),
+                         dev))
+    batch = PWF(probs)
+    try:
+        set_merged_launch(False)
+        ref, href = batch.solve(ys, 8)
+        ref = [r.clone() for r in ref]
+        set_merged_launch(True)
+        assert batch.lib.pwf_version() >= 10100
+        set_graph_mode(False)
+        eager, he = batch.solve(ys, 8)
+        set_graph_mode(True)
+        for i in range(len(pick)):
+            assert torch.equal(eager[i], ref[i]), i
+            assert torch.equal(he[i], href[i]), i
+        for _ in range(3):
+            g, hg = batch.solve(ys, 8)
+            torch.cuda.synchronize()
+            _ = batch.forward(g)
+            torch.cuda.synchronize()
+            for i in range(len(pick)):
+                assert torch.equal(g[i], ref[i]), i
+                assert torch.equal(hg[i], href[i]), i
+    finally:
+        set_graph_mode(True)
+        set_merged_launch(False)
+
+
 def test_uneven_roi_2048_instance_100_iterations():
     """The first 2048^2 ROI instance (instance 56, its own sigma) for 100 iterations
     against the oracle; the batch test above shows its batched solve equals this one."""
