@@ -95,17 +95,33 @@ def autotune(batch) -> dict:
             "row_plans_S0_S2_S4_S6_S8_S10": {n: [lib.pwf_row_plan(n, s) for s in range(0, 12, 2)] for n in sides}}
 
 
-def _read_counter_csv(path: str, counter: str):
-    """Per-kernel mean of `counter` over dispatches from a rocprofv3 counter_collection.csv,
-    and the largest single dispatch of a copy or fill kernel (the calibration launch)."""
+def _counter_rows(path: str, counter: str):
+    """(kernel name, dispatch id, value) of `counter` from rocprofv3 output: a
+    counter_collection.csv (--output-format csv) or the rocpd SQLite database it writes by
+    default (its counters_collection view)."""
+    if path.endswith(".db"):
+        import sqlite3
+        con = sqlite3.connect(f"file:{path}?mode=ro", uri=True)
+        try:
+            yield from con.execute("select kernel_name, dispatch_id, value from counters_collection "
+                                   "where counter_name = ?", (counter,))
+        finally:
+            con.close()
+        return
     import csv
-    sums = {}
     with open(path) as fh:
         for row in csv.DictReader(fh):
-            if row.get("Counter_Name") != counter:
-                continue
-            key = (row["Kernel_Name"], row.get("Dispatch_Id"))
-            sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+            if row.get("Counter_Name") == counter:
+                yield row["Kernel_Name"], row.get("Dispatch_Id"), float(row["Counter_Value"])
+
+
+def _read_counter_csv(path: str, counter: str):
+    """Per-kernel mean of `counter` over dispatches, and the largest single dispatch of a copy
+    or fill kernel (the calibration launch)."""
+    sums = {}
+    for name, disp, val in _counter_rows(path, counter):
+        key = (name, disp)
+        sums[key] = sums.get(key, 0.0) + float(val)
     per_kernel = {}
     calib = 0.0
     for (name, _), val in sums.items():
@@ -470,8 +486,9 @@ def main() -> int:
                     help="skip the joint-diffuser, calibration and tomography measurements")
     ap.add_argument("--sweep-only", default=None,
                     help="after setup, only launch sweep K (0..11) or 'all' plus a 1 GiB copy (counter runs)")
-    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs of a --sweep-only all run "
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH", "WRITE"),
+                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output (counter_collection.csv or "
+                         "the rocpd .db) of a --sweep-only all run "
                          "into profiles/traffic_counters.json and exit")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--retune", action="store_true",
