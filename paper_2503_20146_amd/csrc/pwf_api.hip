@@ -26,7 +26,7 @@ using pwf::Sweep;
 
 namespace {
 
-constexpr int kVersion = 10100;        // 1.1.0
+constexpr int kVersion = 10200;        // 1.2.0
 constexpr int kBetaCap = 1 << 16;      // iterations covered by the momentum table
 constexpr size_t kAlign = 256;
 constexpr int kSizes[] = {128, 256, 512, 1024, 2048};
@@ -294,8 +294,20 @@ pwf_status validate_batch(const pwf_problem* probs, int32_t n) {
 // ------------------------------------------------------------------ workspace layout
 
 size_t field_bytes(const pwf_problem& p) { return align_up((size_t)p.geom.nx * p.geom.ny * sizeof(float2)); }
-// loss partials: one per column tile of the residual sweep
-int n_partials(const pwf_problem& p) { return p.geom.nx / 2 / col_width(p.geom.ny, pwf::COL_BLUR_LOSS); }
+// Workgroups of a column sweep per instance: one per tile of `width` columns
+// (nx/2 columns in half form), times the two halves of a split transform.
+int col_blocks(int nx, int ny, int op, int width) {
+  return (pwf::col_op_half(op) ? nx / 2 : nx) / width * (pwf::col_split_n(ny) ? 2 : 1);
+}
+// loss partials: one per workgroup of the residual sweep
+int n_partials(const pwf_problem& p) {
+  return col_blocks(p.geom.nx, p.geom.ny, pwf::COL_BLUR_LOSS, col_width(p.geom.ny, pwf::COL_BLUR_LOSS));
+}
+// room for per-workgroup partials of a column sweep at the narrowest compiled tile
+int max_partials(const pwf_problem& p) {
+  const int narrow = std::min(pwf::col_default_width(p.geom.ny), pwf::col_alt_width(p.geom.ny));
+  return col_blocks(p.geom.nx, p.geom.ny, pwf::COL_CHIRP1, narrow);
+}
 size_t table_bytes(const pwf_problem& p) {
   return align_up((size_t)(p.geom.nx + p.geom.ny) * (2 * sizeof(float2) + 2 * sizeof(float)));
 }
@@ -326,9 +338,8 @@ Layout make_layout(const pwf_problem* probs, int n, bool joint = false) {
   L.partials = off;
   for (int i = 0; i < n; ++i) {
     L.part[i] = off;
-    // room for the narrowest compiled column tile and the plain path's partials
-    const int narrow = std::min(pwf::col_default_width(probs[i].geom.ny), pwf::col_alt_width(probs[i].geom.ny));
-    off += align_up(sizeof(double) * std::max(probs[i].geom.nx / narrow, pwf::plain_elementwise_blocks()));
+    // room for the loss partials at any compiled column tile and the plain path's partials
+    off += align_up(sizeof(double) * std::max(max_partials(probs[i]), pwf::plain_elementwise_blocks()));
   }
   L.tables.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -389,8 +400,7 @@ Layout make_loss_grad_layout(const pwf_problem* probs, int n) {
   L.partials = off;
   for (int i = 0; i < n; ++i) {
     L.part[i] = off;
-    const int narrow = std::min(pwf::col_default_width(probs[i].geom.ny), pwf::col_alt_width(probs[i].geom.ny));
-    off += align_up(sizeof(double) * (probs[i].geom.nx / narrow));
+    off += align_up(sizeof(double) * max_partials(probs[i]));
   }
   L.tables.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -542,8 +552,13 @@ struct Launcher {
     S.tw_alt = ctx.twa[size_index(c.nx)];
     S.tw_alt2 = ctx.twa2[size_index(c.nx)];
     S.twn_row = ctx.twn[size_index(c.nx)];
-    S.twn_col = ctx.twn[size_index(c.ny)];
-    S.tw_col = ctx.twc[size_index(c.ny)];
+    // a split column transform runs ny/2-point transforms (pwf_device.h, col_split)
+    const bool split = pwf::col_split_n(c.ny);
+    const int nf = split ? c.ny / 2 : c.ny;
+    S.twn_col = ctx.twn[size_index(nf)];
+    S.tw_col = ctx.twc[size_index(nf)];
+    S.twn_pair = ctx.twn[size_index(c.ny)];
+    S.pair_half = split ? c.ny / 2 : 0;
     S.status = status();
     S.blocks_per_inst = 0;
     S.corr_tol = corr_tol;
@@ -562,7 +577,7 @@ struct Launcher {
     for (const Class& c : B.classes) {
       Sweep S = sweep(c, iter);
       const int width = width_of(c.ny, op);
-      S.blocks_per_inst = (pwf::col_op_half(op) ? c.nx / 2 : c.nx) / width;
+      S.blocks_per_inst = col_blocks(c.nx, c.ny, op, width);
       PWF_HIP(pwf::launch_col(c.ny, width, op, S.blocks_per_inst * c.count, S, st));
     }
     return PWF_OK;
@@ -577,7 +592,7 @@ struct Launcher {
       const int plan = plan_of(c.nx, op);
       Sweep S = sweep(c, iter);
       S.blocks_per_inst = c.ny / pwf::row_rows_per_block(c.nx, plan);
-      if (!pwf::multi_row_supported(c.nx, plan) || m == pwf::kMaxMerged) {
+      if (!pwf::multi_row_supported(c.nx, c.ny, plan) || m == pwf::kMaxMerged) {
         PWF_HIP(pwf::launch_row(c.nx, op, plan, S.blocks_per_inst * c.count, S, st));
         continue;
       }
@@ -601,7 +616,7 @@ struct Launcher {
     for (const Class& c : B.classes) {
       const int width = width_of(c.ny, op);
       Sweep S = sweep(c, iter);
-      S.blocks_per_inst = (pwf::col_op_half(op) ? c.nx / 2 : c.nx) / width;
+      S.blocks_per_inst = col_blocks(c.nx, c.ny, op, width);
       if (width != pwf::multi_col_width(c.ny) || m == pwf::kMaxMerged) {
         PWF_HIP(pwf::launch_col(c.ny, width, op, S.blocks_per_inst * c.count, S, st));
         continue;
@@ -1435,9 +1450,9 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
       } else {
         const int op = row_op_of_sweep(sweep);
         int best_plan = row_plan(c.nx, op);
-        if (merged && !pwf::multi_row_supported(c.nx, best_plan)) best_plan = c.nx == 512 ? 0 : 1;
+        if (merged && !pwf::multi_row_supported(c.nx, c.ny, best_plan)) best_plan = c.nx == 512 ? 0 : 1;
         for (int plan = 0; plan < pwf::row_plan_count_n(c.nx); ++plan) {
-          if (merged && !pwf::multi_row_supported(c.nx, plan)) continue;
+          if (merged && !pwf::multi_row_supported(c.nx, c.ny, plan)) continue;
           g_row_plan[ridx][op] = plan;
           result = timed([&]() { return K.row(op); }, &ms);
           if (result != PWF_OK) break;
@@ -1466,13 +1481,15 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
 // mix lists the batch's grid shapes and instance counts, e.g. 512x512*24+1024x1024*32.
 namespace {
 
+// Architecture of the current device and the library version: a cached
+// schedule was timed on these kernels, so another version re-times it.
 std::string device_arch() {
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
   std::string a(prop.gcnArchName);
   const size_t colon = a.find(':');
-  return colon == std::string::npos ? a : a.substr(0, colon);
+  return (colon == std::string::npos ? a : a.substr(0, colon)) + "/v" + std::to_string(kVersion);
 }
 
 std::string class_mix(const Batch& B) {

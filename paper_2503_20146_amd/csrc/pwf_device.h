@@ -197,6 +197,27 @@ template <> struct ColCfg<512>  { using Plan = FftPlan<512, 16, 8, 4>;   static 
 template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  WA = 8,  WB = 4; };
 template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, WA = 4,  WB = 8; };
 
+// Radix-2 split of the long column transforms in the sweeps.  A 2048-point
+// column needs 16 KB of LDS, so a tile of 8 columns (64-byte row segments)
+// would run alone on its CU, and 4-column tiles read 32-byte segments.  The
+// sweeps therefore take the first radix-2 stage of the y transform out of the
+// column sweeps (decimation in frequency):
+//   forward: a[n] = x[n] + x[n + H],  b[n] = (x[n] - x[n + H]) w^n,  H = ny/2,
+//            then X[2j] = FFT_H(a)[j] and X[2j + 1] = FFT_H(b)[j];
+//   inverse: x[n] = A[n] + w^-n B[n],  x[n + H] = A[n] - w^-n B[n], with A, B
+//            the inverse H-point transforms of the even and odd ky,
+// w = exp(-2 pi i / ny).  Row sweeps handle rows n and n + H together and
+// apply these butterflies as they read and write W; a column sweep's
+// workgroup runs one H-point half (rows p H .. p H + H - 1, ky = 2 j + p), so
+// at 2048 it has the shape of a 1024-point sweep: 8-column tiles, two
+// workgroups per CU.  The spectra kept between iterations (Psi^, Z^, Y^) are
+// stored in the same order: row p H + j holds ky = 2 j + p.
+template <int NY> constexpr bool col_split() { return NY >= 2048; }
+constexpr bool col_split_n(int ny) { return ny >= 2048; }
+template <int NY> constexpr int col_fft_len() { return col_split<NY>() ? NY / 2 : NY; }
+// Column configuration of the sweeps on side NY (transform length and tile widths).
+template <int NY> using ColSweepCfg = ColCfg<col_fft_len<NY>()>;
+
 // Arguments common to every sweep launch.
 struct Sweep {
   const Inst* inst;       // device array of descriptors
@@ -207,8 +228,10 @@ struct Sweep {
   const float2* tw_alt;   // twiddles of the alternative row plan (forward, then reversed plan)
   const float2* tw_alt2;  // twiddles of the third row plan (forward, then reversed plan)
   const float2* twn_row;  // w_nx^m, m = 0..nx-1
-  const float2* twn_col;  // w_ny^m, m = 0..ny-1
+  const float2* twn_col;  // w_L^m, m = 0..L-1, L = the column sweeps' transform length
   const float2* tw_col;   // twiddles of the column plan (forward, then reversed plan)
+  const float2* twn_pair; // w_ny^m, m = 0..ny-1: twiddles of the split's butterflies (row sweeps)
+  int32_t pair_half;      // H = ny/2 when the column transform is split (col_split), else 0
   int32_t* status;        // bit 0: non-finite loss seen
   double corr_tol;        // stopping correlation threshold (used when corr_partial is set)
 };

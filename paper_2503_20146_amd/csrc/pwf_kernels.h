@@ -87,10 +87,10 @@ hipError_t launch_col(int ny, int width, int op, int nblocks, const Sweep& S, hi
 hipError_t launch_build_tables(const Inst* insts, int n, hipStream_t st);
 
 // Merged launches over size classes (pwf_sweeps_multi.hip).  A class can join a
-// merged row sweep when multi_row_supported(nx, plan) and a merged column sweep
+// merged row sweep when multi_row_supported(nx, ny, plan) and a merged column sweep
 // when multi_col_width(ny) > 0 (the tile width the merged kernel uses); ops are
 // the twelve sweeps of the iteration.
-bool multi_row_supported(int nx, int plan);
+bool multi_row_supported(int nx, int ny, int plan);
 int multi_col_width(int ny);
 hipError_t launch_row_multi(int op, int nblocks, const MultiSweep& M, hipStream_t st);
 hipError_t launch_col_multi(int op, int nblocks, const MultiSweep& M, hipStream_t st);

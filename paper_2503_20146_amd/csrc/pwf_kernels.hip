@@ -267,33 +267,33 @@ int row_rows_per_block(int n, int plan) {
 
 int col_default_width(int n) {
   switch (n) {
-    case 128: return ColCfg<128>::WA;
-    case 256: return ColCfg<256>::WA;
-    case 512: return ColCfg<512>::WA;
-    case 1024: return ColCfg<1024>::WA;
-    case 2048: return ColCfg<2048>::WA;
+    case 128: return ColSweepCfg<128>::WA;
+    case 256: return ColSweepCfg<256>::WA;
+    case 512: return ColSweepCfg<512>::WA;
+    case 1024: return ColSweepCfg<1024>::WA;
+    case 2048: return ColSweepCfg<2048>::WA;
     default: return 0;
   }
 }
 
 bool col_width_supported(int n, int w) {
   switch (n) {
-    case 128: return w == ColCfg<128>::WA || w == ColCfg<128>::WB;
-    case 256: return w == ColCfg<256>::WA || w == ColCfg<256>::WB;
-    case 512: return w == ColCfg<512>::WA || w == ColCfg<512>::WB;
-    case 1024: return w == ColCfg<1024>::WA || w == ColCfg<1024>::WB;
-    case 2048: return w == ColCfg<2048>::WA || w == ColCfg<2048>::WB;
+    case 128: return w == ColSweepCfg<128>::WA || w == ColSweepCfg<128>::WB;
+    case 256: return w == ColSweepCfg<256>::WA || w == ColSweepCfg<256>::WB;
+    case 512: return w == ColSweepCfg<512>::WA || w == ColSweepCfg<512>::WB;
+    case 1024: return w == ColSweepCfg<1024>::WA || w == ColSweepCfg<1024>::WB;
+    case 2048: return w == ColSweepCfg<2048>::WA || w == ColSweepCfg<2048>::WB;
     default: return false;
   }
 }
 
 int col_alt_width(int n) {
   switch (n) {
-    case 128: return ColCfg<128>::WB;
-    case 256: return ColCfg<256>::WB;
-    case 512: return ColCfg<512>::WB;
-    case 1024: return ColCfg<1024>::WB;
-    case 2048: return ColCfg<2048>::WB;
+    case 128: return ColSweepCfg<128>::WB;
+    case 256: return ColSweepCfg<256>::WB;
+    case 512: return ColSweepCfg<512>::WB;
+    case 1024: return ColSweepCfg<1024>::WB;
+    case 2048: return ColSweepCfg<2048>::WB;
     default: return 0;
   }
 }

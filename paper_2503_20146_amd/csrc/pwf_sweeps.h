@@ -83,6 +83,43 @@ __device__ __forceinline__ float2 cexp_f(float2 p) {
                      a * __uint_as_float(__float_as_uint(s1) ^ flip_s));
 }
 
+// Butterflies of the column transform's radix-2 split (col_split) in the row
+// sweeps.  The two rows n and n + H of a pair sit PD lanes apart in one wave
+// (pb = 1 for row n + H) and hold the same x positions, so each value meets
+// its partner through one cross-lane move: at PD = 32, v_permlane32_swap of
+// two copies (the upper half of the wave then holds the lower half's values
+// and vice versa), else a lane shuffle.  w = w_ny^n.
+template <int PD>
+__device__ __forceinline__ float pair_partner(float a, int pb) {
+  if constexpr (PD == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(a), false, false);
+    return __uint_as_float(pb ? r[0] : r[1]);
+  } else {
+    return __shfl_xor(a, PD, 64);
+  }
+}
+template <int PD>
+__device__ __forceinline__ float2 pair_partner(float2 a, int pb) {
+  return make_float2(pair_partner<PD>(a.x, pb), pair_partner<PD>(a.y, pb));
+}
+// Reading W after a column sweep: the lane of row n (pb = 0) holds A[n], its
+// partner (pb = 1) B[n]; returns x[n] = A + w^-n B, or x[n + H] = A - w^-n B.
+template <int PD>
+__device__ __forceinline__ float2 split_inverse(float2 mine, float2 w, int pb) {
+  const float2 other = pair_partner<PD>(mine, pb);
+  const float2 a = pb ? other : mine;
+  const float2 wb = cmulc(pb ? mine : other, w);
+  return pb ? make_float2(a.x - wb.x, a.y - wb.y) : make_float2(a.x + wb.x, a.y + wb.y);
+}
+// Writing W for a column sweep: the lane of row n holds X[n], its partner
+// X[n + H]; returns a[n] = X[n] + X[n + H], or b[n] = (X[n] - X[n + H]) w^n.
+template <int PD>
+__device__ __forceinline__ float2 split_forward(float2 mine, float2 w, int pb) {
+  const float2 other = pair_partner<PD>(mine, pb);
+  return pb ? cmul(make_float2(other.x - mine.x, other.y - mine.y), w)
+            : make_float2(mine.x + other.x, mine.y + other.y);
+}
+
 // Twiddles staged in LDS.  Every load of the table is issued ahead of the
 // sweep's own loads and held in registers, and the LDS writes come after those
 // loads are issued: the table's latency then hides under the data's instead of
@@ -153,7 +190,7 @@ struct RowLds {
 
 // Row sweep `OP` on logical block b (instance b / blocks_per_inst) with the
 // caller's LDS (RowLds sizes).
-template <int NX, int OP, int PLAN>
+template <int NX, int OP, int PLAN, bool PAIR>
 __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, float2* twl) {
   using C = RowCfgSel<NX, PLAN>;
   using Plan = typename C::Plan;
@@ -166,8 +203,27 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
   const int blk = b - inst * S.blocks_per_inst;
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
   if (instance_stopped(I)) return;  // uniform over the workgroup
-  const int t = threadIdx.x % T, rw = threadIdx.x / T;
-  const int row = blk * RW + rw;
+  // Rows of the workgroup: RW consecutive rows, or, with the column transform
+  // split (PAIR, pair_half = H = ny/2), RW/2 pairs (n, n + H) whose two rows
+  // sit PD lanes apart in one wave (lane t of row n + H is PD lanes after lane
+  // t of row n) for the split's butterflies.
+  static_assert(RW % 2 == 0, "row pairs");
+  constexpr int PD = T < 32 ? T : 32;
+  int t, rw, row, pb = 0, prow = 0;
+  if constexpr (PAIR) {
+    const int H = S.pair_half;
+    const int u = (int)threadIdx.x % (2 * T);
+    pb = (u / PD) & 1;
+    t = (u / (2 * PD)) * PD + u % PD;
+    rw = 2 * ((int)threadIdx.x / (2 * T)) + pb;
+    prow = blk * (RW / 2) + (int)threadIdx.x / (2 * T);
+    row = prow + pb * H;
+  } else {
+    t = (int)threadIdx.x % T;
+    rw = (int)threadIdx.x / T;
+    row = blk * RW + rw;
+  }
+  const float2 wp = PAIR ? gld(S.twn_pair, (uint32_t)prow) : make_float2(1.f, 0.f);
   const LdsView lv{lds + rw * lds_len(NX), 1};
   using TS = typename RowLds<NX, OP, PLAN>::TS;
   const float2* twg = PLAN == 2 ? S.tw_alt2 : PLAN == 1 ? S.tw_alt : S.tw_row;
@@ -202,7 +258,22 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
           constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
           const int kx = t + T * c + r * ML;
           const int kk = kx <= NX / 2 ? kx : NX - kx;
-          float2 a = gld(I.W, rh + (uint32_t)(kk == NX / 2 ? 0 : kk));
+          v[c * RL + r] = gld(I.W, rh + (uint32_t)(kk == NX / 2 ? 0 : kk));
+        });
+      });
+      // the split's butterflies act on the stored values (the packed column
+      // included), before they are unpacked
+      if constexpr (PAIR) {
+        static_for<0, E>([&](auto ee) {
+          constexpr int e = decltype(ee)::value;
+          v[e] = split_inverse<PD>(v[e], wp, pb);
+        });
+      }
+      static_for<0, E / RL>([&](auto cc) {
+        static_for<0, RL>([&](auto rr) {
+          constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
+          const int kx = t + T * c + r * ML;
+          float2 a = v[c * RL + r];
           if (kx > NX / 2) a.y = -a.y;
           else if (kx == 0) a.y = 0.f;
           else if (kx == NX / 2) a = make_float2(s_ny * a.y, 0.f);
@@ -227,6 +298,15 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
           side[c * R1 + q] = gld(sp, rbase + t + T * c + q * M1);
         });
       });
+    }
+    if constexpr (!(OP == ROW_BACKBLUR || OP == ROW_FORWARD_OUT)) {
+      // (issued after the side loads, whose latency then overlaps the wait)
+      if constexpr (PAIR) {
+        static_for<0, E>([&](auto ee) {
+          constexpr int e = decltype(ee)::value;
+          v[e] = split_inverse<PD>(v[e], wp, pb);
+        });
+      }
     }
     fft_inverse<Plan, T>(v, t, twr, lv);
   } else if constexpr (OP == ROW_REAL_FFT) {
@@ -361,20 +441,36 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
     fft_forward<Plan, T>(v, t, tw, lv);
     if constexpr (OP == ROW_INTENSITY || OP == ROW_REAL_FFT) {
       // spectrum of a real row in half form (see col_op_half); lane 0 holds
-      // kx = 0 in v[0] and kx = nx/2 in v[RL/2]
+      // kx = 0 in v[0] and kx = nx/2 in v[RL/2].  Element (c, r) has kx < nx/2
+      // exactly when r < RL/2 (t + T c < nx/RL), so only those are stored.
+      static_assert(RL % 2 == 0, "half form");
       const uint32_t rh = opaque(rbase);
+      const float s_ny = OP == ROW_INTENSITY ? gldf(I.ix, NX / 2) : 1.f;
+      float2 packed = make_float2(v[0].x, s_ny * v[RL / 2].x);
+      if constexpr (PAIR) {
+        packed = split_forward<PD>(packed, wp, pb);
+        static_for<0, E / RL>([&](auto cc) {
+          static_for<0, RL / 2>([&](auto rr) {
+            constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
+            v[c * RL + r] = split_forward<PD>(v[c * RL + r], wp, pb);
+          });
+        });
+      }
       static_for<0, E / RL>([&](auto cc) {
-        static_for<0, RL>([&](auto rr) {
+        static_for<0, RL / 2>([&](auto rr) {
           constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
           const int kx = t + T * c + r * ML;
-          if (kx > 0 && kx < NX / 2) gst(I.W, rh + (uint32_t)kx, v[c * RL + r]);
+          if (kx > 0) gst(I.W, rh + (uint32_t)kx, v[c * RL + r]);
         });
       });
-      if (t == 0) {
-        const float s_ny = OP == ROW_INTENSITY ? gldf(I.ix, NX / 2) : 1.f;
-        gst(I.W, rh, make_float2(v[0].x, s_ny * v[RL / 2].x));
-      }
+      if (t == 0) gst(I.W, rh, packed);
     } else {
+      if constexpr (PAIR) {
+        static_for<0, E>([&](auto ee) {
+          constexpr int e = decltype(ee)::value;
+          v[e] = split_forward<PD>(v[e], wp, pb);
+        });
+      }
       const uint32_t rb_st = opaque(rbase);
       static_for<0, E / RL>([&](auto cc) {
         static_for<0, RL>([&](auto rr) {
@@ -430,11 +526,11 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
   }
 }
 
-template <int NX, int OP, int PLAN>
+template <int NX, int OP, int PLAN, bool PAIR>
 __global__ void __launch_bounds__((row_threads<NX, PLAN>()), (row_min_waves<NX, OP>())) row_sweep(Sweep S) {
   __shared__ float2 lds[RowLds<NX, OP, PLAN>::kExchange];
   __shared__ float2 twl[RowLds<NX, OP, PLAN>::kTwiddles];
-  row_body<NX, OP, PLAN>(S, xcd_contiguous<false>(blockIdx.x, gridDim.x), lds, twl);
+  row_body<NX, OP, PLAN, PAIR>(S, xcd_contiguous<false>(blockIdx.x, gridDim.x), lds, twl);
 }
 
 // ------------------------------------------------------------------ column sweeps
@@ -493,42 +589,56 @@ __device__ __noinline__ float2 transfer_direct(double chirp_rev, double s_coef, 
 // the others, which need fewer registers than that anyway (a 4-wave bound,
 // 128 registers, makes the chirp sweeps spill).
 template <int NY, int W, int OP> constexpr int col_min_waves() {
-  return OP == COL_NESTEROV && (NY == 512 || (NY > 512 && ColCfg<NY>::T * W == 512)) ? 4
-         : (OP == COL_NESTEROV || OP == COL_DIRECTION) && !(NY == 256 && W == 16) ? 3 : 2;
+  constexpr int NF = col_fft_len<NY>();
+  return OP == COL_NESTEROV && (NF == 512 || (NF > 512 && ColCfg<NF>::T * W == 512)) ? 4
+         : (OP == COL_NESTEROV || OP == COL_DIRECTION) && !(NF == 256 && W == 16) ? 3 : 2;
 }
 
-// LDS a column sweep needs: the exchange buffer and the staged twiddles (at
-// 2048 points the half table still leaves room for two 4-column tiles per CU).
+// LDS a column sweep needs: the exchange buffer and the staged twiddles of
+// its transform (NY points, or NY/2 when split).
 template <int NY, int W>
 struct ColLds {
-  using TS = TwSel<typename ColCfg<NY>::Plan, false, true>;
-  static constexpr int kExchange = W * lds_len(NY);
+  static constexpr int NF = col_fft_len<NY>();
+  using TS = TwSel<typename ColCfg<NF>::Plan, false, true>;
+  static constexpr int kExchange = W * lds_len(NF);
   static constexpr int kTwiddles = TS::kLds;
 };
 
 // Column sweep `OP` on logical block b (instance b / blocks_per_inst) with the
 // caller's LDS (ColLds sizes).
+// With the transform split (col_split), logical blocks [0, B/2) of an
+// instance run the even-ky half (rows 0 .. NY/2 - 1) and [B/2, B) the odd
+// half, over the same tiles; elements are addressed by their position j in
+// the half-column (row part NY/2 + j) and the frequency is ky = 2 j + part.
 template <int NY, int W, int OP>
 __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, float2* twl) {
-  using C = ColCfg<NY>;
+  constexpr bool SPLIT = col_split<NY>();
+  constexpr int NF = col_fft_len<NY>();
+  using C = ColCfg<NF>;
   using Plan = typename C::Plan;
-  constexpr int T = C::T, E = NY / T;
+  constexpr int T = C::T, E = NF / T;
   constexpr int R1 = Plan::radix[0], RL = Plan::radix[Plan::NPASS - 1];
-  constexpr int M1 = NY / R1, ML = NY / RL;
+  constexpr int M1 = NF / R1, ML = NF / RL;
   constexpr int NT = T * W;
   __shared__ double red[(NT + 63) / 64];
 
   const int inst = b / S.blocks_per_inst;
-  const int tile = col_tile_of<W>(b - inst * S.blocks_per_inst, S.blocks_per_inst);
+  const int jb = b - inst * S.blocks_per_inst;
+  const int ntile = SPLIT ? S.blocks_per_inst / 2 : S.blocks_per_inst;
+  const int part = SPLIT && jb >= ntile ? 1 : 0;
+  const int tile = col_tile_of<W>(jb - part * ntile, ntile);
   const Inst I = S.inst[inst];  // by value: the fields stay in registers
   if (instance_stopped(I)) return;  // uniform over the workgroup
+  // frequency of position j, and the position of -ky within the half
+  auto ky_of = [&](int j) { return SPLIT ? 2 * j + part : j; };
+  auto mirror_pos = [&](int j) { return SPLIT && part ? NF - 1 - j : (NF - j) & (NF - 1); };
   // x-spectra in half form (col_op_half) use columns 0 .. nx/2 - 1 only
   constexpr bool HALF = col_op_half(OP);
   const int nx = I.nx;
   if constexpr (OP == COL_CHIRP1) {
     // Stopping rule (Methods, "Reconstruction procedure"): |<x_k, x_k-1>| /
     // (|x_k| |x_k-1|) above the threshold, from the FP64 partials of S0.
-    if (I.corr_partial && S.iter > 0 && tile == 0 && threadIdx.x == 0) {
+    if (I.corr_partial && S.iter > 0 && tile == 0 && part == 0 && threadIdx.x == 0) {
       double a[4] = {0.0, 0.0, 0.0, 0.0};
       for (int i = 0; i < I.n_corr_partials; ++i)
         for (int j = 0; j < 4; ++j) a[j] += I.corr_partial[4 * i + j];
@@ -538,7 +648,7 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
   }
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int s = tile * W + w;
-  const uint32_t o_ld = (uint32_t)(t * nx + s);  // element (t, s); row r adds r nx
+  const uint32_t o_ld = (uint32_t)((part * NF + t) * nx + s);  // element (t, s) of the half; position j adds (j - t) nx
   const LdsView lv{lds + w, W};
   using TS = typename ColLds<NY, W>::TS;
   const auto tw = TS::forward(twl, S.tw_col);
@@ -558,7 +668,7 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
   if constexpr (TS::kMode != 0) tws.store(twl);
   fft_forward<Plan, T>(v, t, tw, lv);
 
-  // Fourier-domain step; element e = c*RL + r holds ky = t + T c + r ML.
+  // Fourier-domain step; element e = c*RL + r holds position j = t + T c + r ML.
   const int kx = HALF ? s : kx_of_col(s, nx);
   const float fx = freq_of(kx, nx);
   double acc = 0.0;
@@ -596,10 +706,10 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
     auto load_state = [&](auto bb, int slot) {
       static_for<0, NA>([&](auto uu) {
         constexpr int u = decltype(uu)::value, e = decltype(bb)::value * NA + u;
-        const int ky = t + T * (e / RL) + (e % RL) * ML;
-        zk[e] = gld(z_cur, o_a + (uint32_t)((ky - t) * nx));
-        zp[slot][u] = gld(z_old, o_a + (uint32_t)((ky - t) * nx));
-        gb[slot][u] = gldf(I.gy, ky);
+        const int j = t + T * (e / RL) + (e % RL) * ML;
+        zk[e] = gld(z_cur, o_a + (uint32_t)((j - t) * nx));
+        zp[slot][u] = gld(z_old, o_a + (uint32_t)((j - t) * nx));
+        gb[slot][u] = gldf(I.gy, ky_of(j));
       });
     };
     load_state(std::integral_constant<int, 0>{}, 0);
@@ -609,16 +719,16 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
       __builtin_amdgcn_sched_barrier(0);
       static_for<0, NA>([&](auto uu) {
         constexpr int u = decltype(uu)::value, e = b * NA + u;
-        const int ky = t + T * (e / RL) + (e % RL) * ML;
+        const int j = t + T * (e / RL) + (e % RL) * ML;
         const float2 z0 = zk[e], z1 = zp[b & 1][u];
         const float2 ps = make_float2(z0.x + bp * (z0.x - z1.x), z0.y + bp * (z0.y - z1.y));
-        const float P = pinv_of(I, fx, freq_of(ky, NY));
+        const float P = pinv_of(I, fx, freq_of(ky_of(j), NY));
         // G = F{s Re g} + i F{Im g} with s = kGradReScale: the Hermitian split
         // with Re g unscaled gives a = (1/s + P)/2, c = (1/s - P)/2
         const float a = 0.5f * (kGradReUnscale + P), c = 0.5f * (kGradReUnscale - P);
         const float g2 = gxv + (1.f - gxv) * gb[b & 1][u];  // 1 - STFx STFy without cancellation
         const float r1 = g2 * I.alpha_c1, r2 = g2 * I.alpha_c2;
-        lv.at(ky) = make_float2(c * v[e].x + r2 * ps.x, c * v[e].y + r2 * ps.y);
+        lv.at(j) = make_float2(c * v[e].x + r2 * ps.x, c * v[e].y + r2 * ps.y);
         // Psi - eta (a G + g2 c1 Psi); the mirror's share follows the exchange
         v[e] = make_float2(ps.x - I.eta * (a * v[e].x + r1 * ps.x), ps.y - I.eta * (a * v[e].y + r1 * ps.y));
       });
@@ -628,12 +738,12 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
     const uint32_t o_up = opaque(o_ld);
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      const int ky = t + T * (e / RL) + (e % RL) * ML;
+      const int j = t + T * (e / RL) + (e % RL) * ML;
       const int kl = (int)opaque((uint32_t)t) + T * (e / RL) + (e % RL) * ML;
-      const float2 hm = lm.at((NY - kl) & (NY - 1));
+      const float2 hm = lm.at(mirror_pos(kl));
       const float2 z = make_float2(v[e].x - I.eta * hm.x, v[e].y + I.eta * hm.y);  // - eta conj(h(-k))
       const float2 pn = make_float2(z.x + bf * (z.x - zk[e].x), z.y + bf * (z.y - zk[e].y));
-      gst(z_old, o_up + (uint32_t)((ky - t) * nx), z);  // Z_{k+1}; this lane read Z_{k-1} here above
+      gst(z_old, o_up + (uint32_t)((j - t) * nx), z);  // Z_{k+1}; this lane read Z_{k-1} here above
       v[e] = cscale(pn, I.inv_m);
     });
     __syncthreads();
@@ -649,9 +759,9 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
     __syncthreads();
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      const int ky = t + T * (e / RL) + (e % RL) * ML;
-      const float2 gm = lm.at((NY - ky) & (NY - 1));
-      const float P = pinv_of(I, fx, freq_of(ky, NY));
+      const int j = t + T * (e / RL) + (e % RL) * ML;
+      const float2 gm = lm.at(mirror_pos(j));
+      const float P = pinv_of(I, fx, freq_of(ky_of(j), NY));
       const float a = 0.5f * (kGradReUnscale + P), b = 0.5f * (kGradReUnscale - P);
       // G = F{s Re g} + i F{Im g} (s = kGradReScale):
       // (1/s+P)/2 G + (1/s-P)/2 conj(G(-k)) = F{Re g} + i P F{Im g}
@@ -660,17 +770,17 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
     __syncthreads();
     static_for<0, E>([&](auto ee) {  // Psi to LDS: each lane needs Psi(k) and Psi(-k)
       constexpr int e = decltype(ee)::value;
-      const int ky = t + T * (e / RL) + (e % RL) * ML;
-      lv.at(ky) = gld(I.psi_hat, o_ld + (uint32_t)((ky - t) * nx));
+      const int j = t + T * (e / RL) + (e % RL) * ML;
+      lv.at(j) = gld(I.psi_hat, o_ld + (uint32_t)((j - t) * nx));
     });
     __syncthreads();
     const float gxv = gldf(I.gx, kx);
     static_for<0, E>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      const int ky = t + T * (e / RL) + (e % RL) * ML;
-      const float2 pk = lv.at(ky);
-      const float2 pm = lm.at((NY - ky) & (NY - 1));
-      const float g2 = gxv + (1.f - gxv) * gldf(I.gy, ky);   // 1 - STFx STFy without cancellation
+      const int j = t + T * (e / RL) + (e % RL) * ML;
+      const float2 pk = lv.at(j);
+      const float2 pm = lm.at(mirror_pos(j));
+      const float g2 = gxv + (1.f - gxv) * gldf(I.gy, ky_of(j));   // 1 - STFx STFy without cancellation
       // Re(a) F{Re psi} + i Im(a) F{Im psi} = c1 Psi + c2 conj(Psi(-k))
       const float2 reg = make_float2(I.alpha_c1 * pk.x + I.alpha_c2 * pm.x, I.alpha_c1 * pk.y - I.alpha_c2 * pm.y);
       v[e] = cscale(make_float2(v[e].x + g2 * reg.x, v[e].y + g2 * reg.y), I.inv_m);
@@ -695,7 +805,7 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
       if (I.series && I.cross) {
         static_for<0, E>([&](auto ee) {
           constexpr int e = decltype(ee)::value;
-          const int ky = t + T * (e / RL) + (e % RL) * ML;
+          const int ky = ky_of(t + T * (e / RL) + (e % RL) * ML);
           float2 q = transfer_sep(qx, gld(qy, ky), fx, freq_of(ky, NY), I.s_coef_f, two_pi_a);
           if (CONJ) q = cconj(q);
           v[e] = cmul(v[e], q);
@@ -703,7 +813,7 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
       } else if (I.series) {
         static_for<0, E>([&](auto ee) {
           constexpr int e = decltype(ee)::value;
-          const int ky = t + T * (e / RL) + (e % RL) * ML;
+          const int ky = ky_of(t + T * (e / RL) + (e % RL) * ML);
           float2 q = cmul(qx, gld(qy, ky));
           if (CONJ) q = cconj(q);
           v[e] = cmul(v[e], q);
@@ -712,7 +822,7 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
         const double a = L1 ? I.chirp1_rev : I.chirp2_rev;
         static_for<0, E>([&](auto ee) {  // rare path: one out-of-line FP64 call per element
           constexpr int e = decltype(ee)::value;
-          const int ky = t + T * (e / RL) + (e % RL) * ML;
+          const int ky = ky_of(t + T * (e / RL) + (e % RL) * ML);
           float2 q = transfer_direct(a, I.s_coef, fx, freq_of(ky, NY));
           if (CONJ) q = cconj(q);
           v[e] = cscale(cmul(v[e], q), I.inv_m);
@@ -721,20 +831,22 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
     } else {
       static_for<0, E>([&](auto ee) {
         constexpr int e = decltype(ee)::value;
-        const int ky = t + T * (e / RL) + (e % RL) * ML;
+        const int j = t + T * (e / RL) + (e % RL) * ML;
+        const int ky = ky_of(j);
+        const uint32_t o_e = (uint32_t)((part * NF + j) * nx + s);  // this element's place in the spectra
         if constexpr (OP == COL_BLUR) {
           v[e] = cscale(v[e], ixv * gldf(I.iy, ky) * I.inv_m);
         } else if constexpr (OP == COL_BLUR_LOSS) {
           const float h = ixv * gldf(I.iy, ky);
-          const float2 yh = gld(I.y_hat, (uint32_t)(ky * nx + s));
+          const float2 yh = gld(I.y_hat, o_e);
           const float2 rr = make_float2(h * v[e].x - yh.x, h * v[e].y - yh.y);
           acc += wgt * ((double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y);
           v[e] = cscale(rr, h * I.inv_m);
         } else if constexpr (OP == COL_SPEC_YHAT) {
-          gst(I.y_hat, (uint32_t)(ky * nx + s), v[e]);
+          gst(I.y_hat, o_e, v[e]);
         } else if constexpr (OP == COL_SPEC_PSIHAT) {
-          gst(I.psi_hat, (uint32_t)(ky * nx + s), v[e]);
-          if (I.z_hat) gst(I.z_hat, (uint32_t)(ky * nx + s), v[e]);  // Z_{-1} = Z_0 = Psi_0
+          gst(I.psi_hat, o_e, v[e]);
+          if (I.z_hat) gst(I.z_hat, o_e, v[e]);  // Z_{-1} = Z_0 = Psi_0
         }
       });
     }
@@ -759,13 +871,13 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
     if (threadIdx.x == 0) {
       double sum = 0.0;
       for (int i = 0; i < NT / 64; ++i) sum += red[i];
-      I.loss_partial[tile] = sum;
+      I.loss_partial[part * ntile + tile] = sum;
     }
   }
 }
 
 template <int NY, int W, int OP>
-__global__ void __launch_bounds__(ColCfg<NY>::T * W, (col_min_waves<NY, W, OP>())) col_sweep(Sweep S) {
+__global__ void __launch_bounds__(ColSweepCfg<NY>::T * W, (col_min_waves<NY, W, OP>())) col_sweep(Sweep S) {
   __shared__ float2 lds[ColLds<NY, W>::kExchange];
   __shared__ float2 twl[ColLds<NY, W>::kTwiddles];
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -853,29 +965,29 @@ plain_fft_cols(float2* __restrict__ a, int nx, const float2* tw, size_t plane_st
   }
 }
 
-template <int N, int OP, int PLAN>
+template <int N, int OP, int PLAN, bool PAIR>
 hipError_t launch_row_one(int nblocks, const Sweep& S, hipStream_t st) {
-  hipLaunchKernelGGL((row_sweep<N, OP, PLAN>), dim3(nblocks), dim3(row_threads<N, PLAN>()), 0, st, S);
+  hipLaunchKernelGGL((row_sweep<N, OP, PLAN, PAIR>), dim3(nblocks), dim3(row_threads<N, PLAN>()), 0, st, S);
   return hipGetLastError();
 }
 
 // Row sweep `op` with radix plan `plan` (tunable sweeps only; the others
 // always run with their default plan).
-template <int N, int OP>
+template <int N, int OP, bool PAIR>
 hipError_t launch_row_plan(int plan, int nblocks, const Sweep& S, hipStream_t st) {
-  if (plan == 1) return launch_row_one<N, OP, 1>(nblocks, S, st);
+  if (plan == 1) return launch_row_one<N, OP, 1, PAIR>(nblocks, S, st);
   if constexpr (row_plan_count<N>() > 2) {
-    if (plan == 2) return launch_row_one<N, OP, 2>(nblocks, S, st);
+    if (plan == 2) return launch_row_one<N, OP, 2, PAIR>(nblocks, S, st);
   }
-  if (plan == 0) return launch_row_one<N, OP, 0>(nblocks, S, st);
+  if (plan == 0) return launch_row_one<N, OP, 0, PAIR>(nblocks, S, st);
   return hipErrorInvalidValue;
 }
 
-template <int N>
-hipError_t launch_row_n(int op, int plan, int nblocks, const Sweep& S, hipStream_t st) {
+template <int N, bool PAIR>
+hipError_t launch_row_np(int op, int plan, int nblocks, const Sweep& S, hipStream_t st) {
   switch (op) {
-#define PWF_TUNABLE(o) case o: return launch_row_plan<N, o>(plan, nblocks, S, st);
-#define PWF_FIXED(o) case o: return launch_row_one<N, o, row_alt_default<N>(o) ? 1 : 0>(nblocks, S, st);
+#define PWF_TUNABLE(o) case o: return launch_row_plan<N, o, PAIR>(plan, nblocks, S, st);
+#define PWF_FIXED(o) case o: return launch_row_one<N, o, row_alt_default<N>(o) ? 1 : 0, PAIR>(nblocks, S, st);
     PWF_TUNABLE(ROW_PSI_UPDATE) PWF_TUNABLE(ROW_PSI_UPDATE_CORR) PWF_TUNABLE(ROW_MUL_T) PWF_TUNABLE(ROW_MUL_CONJ_T) PWF_TUNABLE(ROW_INTENSITY)
     PWF_TUNABLE(ROW_BACKBLUR) PWF_TUNABLE(ROW_GRAD)
     PWF_FIXED(ROW_START) PWF_FIXED(ROW_FORWARD_OUT) PWF_FIXED(ROW_REAL_FFT) PWF_FIXED(ROW_CPLX_FFT)
@@ -886,9 +998,17 @@ hipError_t launch_row_n(int op, int plan, int nblocks, const Sweep& S, hipStream
   }
 }
 
+// Row sweep on side N; rows are paired (PAIR) when the launch's column
+// transform is split (Sweep::pair_half > 0).
+template <int N>
+hipError_t launch_row_n(int op, int plan, int nblocks, const Sweep& S, hipStream_t st) {
+  return S.pair_half > 0 ? launch_row_np<N, true>(op, plan, nblocks, S, st)
+                         : launch_row_np<N, false>(op, plan, nblocks, S, st);
+}
+
 template <int N, int W>
 hipError_t launch_col_nw(int op, int nblocks, const Sweep& S, hipStream_t st) {
-  using C = ColCfg<N>;
+  using C = ColSweepCfg<N>;
   const dim3 grid(nblocks), block(C::T * W);
   switch (op) {
 #define PWF_CASE(o) case o: hipLaunchKernelGGL((col_sweep<N, W, o>), grid, block, 0, st, S); break;
@@ -903,8 +1023,9 @@ hipError_t launch_col_nw(int op, int nblocks, const Sweep& S, hipStream_t st) {
 
 template <int N>
 hipError_t launch_col_n(int width, int op, int nblocks, const Sweep& S, hipStream_t st) {
-  if (width == ColCfg<N>::WA) return launch_col_nw<N, ColCfg<N>::WA>(op, nblocks, S, st);
-  if (width == ColCfg<N>::WB) return launch_col_nw<N, ColCfg<N>::WB>(op, nblocks, S, st);
+  using C = ColSweepCfg<N>;
+  if (width == C::WA) return launch_col_nw<N, C::WA>(op, nblocks, S, st);
+  if (width == C::WB) return launch_col_nw<N, C::WB>(op, nblocks, S, st);
   return hipErrorInvalidValue;
 }
 

@@ -54,7 +54,7 @@ def test_status_strings(lib):
 
 def test_tuning_settings(lib):
     """Tile widths and row plans: defaults, settable values, errors (host-only calls)."""
-    assert lib.pwf_column_tile(1024, 1) == 8 and lib.pwf_column_tile(2048, 11) == 4
+    assert lib.pwf_column_tile(1024, 1) == 8 and lib.pwf_column_tile(2048, 11) == 8
     assert lib.pwf_column_tile(100, 1) == 0 and lib.pwf_column_tile(1024, 2) == 0
     assert lib.pwf_set_column_tile(1024, -1, 3) == -1
     assert lib.pwf_set_column_tile(1024, 4, 4) == -1     # S4 is a row sweep
