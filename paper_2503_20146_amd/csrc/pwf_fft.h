@@ -253,21 +253,29 @@ struct TwPass {
 
 // TwTable: one table of w_N^m (m = 0..N-1) for every pass of both
 // directions: w_{LR}^{qk} = w_N^{qk N/(LR)}, and qk N/(LR) < N.
-// HALF keeps only m < N/2 and uses w_N^(m + N/2) = -w_N^m (a sign flip of both
-// parts), which halves the staged table at the cost of a few integer ops per
-// twiddle.
-template <int N, bool HALF = false>
+// DIV = 2 keeps only m < N/2 and uses w_N^(m + N/2) = -w_N^m (a sign flip of
+// both parts); DIV = 4 keeps m < N/4 and uses w_N^(m + a N/4) = (-i)^a w_N^m
+// (a swap of the parts and sign flips).  Both cut the staged table at the
+// cost of a few integer ops per twiddle; the rotations are exact.
+template <int N, int DIV = 1>
 struct TwTable {
+  static_assert(DIV == 1 || DIV == 2 || DIV == 4, "table fraction");
   const float2* tab;
   template <class Plan, int P, int q>
   __device__ __forceinline__ float2 get(int k) const {
     const int i = q * (N / (Plan::stride_before(P) * Plan::radix[P])) * k;
-    if constexpr (!HALF) {
+    if constexpr (DIV == 1) {
       return tab[i];
-    } else {
+    } else if constexpr (DIV == 2) {
       const float2 w = tab[i & (N / 2 - 1)];
       const uint32_t sg = (uint32_t)(i & (N / 2)) << (31 - ilog2(N / 2));
       return make_float2(__uint_as_float(__float_as_uint(w.x) ^ sg), __uint_as_float(__float_as_uint(w.y) ^ sg));
+    } else {
+      const float2 w = tab[i & (N / 4 - 1)];
+      const int a = (i >> ilog2(N / 4)) & 3;   // quarter turns: (-i)^a
+      const float x = (a & 1) ? w.y : w.x, y = (a & 1) ? w.x : w.y;
+      const uint32_t sx = (uint32_t)(a & 2) << 30, sy = (uint32_t)((a ^ (a >> 1)) & 1) << 31;
+      return make_float2(__uint_as_float(__float_as_uint(x) ^ sx), __uint_as_float(__float_as_uint(y) ^ sy));
     }
   }
 };
@@ -396,18 +404,18 @@ struct TwLayout {
 // Where a sweep kernel reads its twiddles from.  Mode 1: the per-pass tables
 // of a palindromic plan staged in LDS (conflict-free reads; the inverse shares
 // them).  Mode 2: the single table w_N^m staged in LDS (N entries, fewer than
-// the per-pass tables of both directions).  HALF: stage the half table in
-// mode 2 (see TwTable).  Mode 0: per-pass tables read from global memory.
-// Above 1024 points the full table (16 KB at 2048) would leave room for only
-// one workgroup per CU beside the exchange buffer: kernels that pass
-// STAGE_LARGE stage the half table there, the others use mode 0.
-template <class Plan, bool HALF = false, bool STAGE_LARGE = false>
+// the per-pass tables of both directions), or the fraction 1/DIV of it (see
+// TwTable).  Mode 0: per-pass tables read from global memory.  Above 1024
+// points the full table (16 KB at 2048) would leave room for only one
+// workgroup per CU beside the exchange buffer: kernels that pass STAGE_LARGE
+// stage at least the half table there, the others use mode 0.
+template <class Plan, int DIV = 1, bool STAGE_LARGE = false>
 struct TwSel {
   static constexpr int N = Plan::kN;
-  static constexpr bool kHalf = HALF || N > 1024;
+  static constexpr int kDiv = N > 1024 && DIV < 2 ? 2 : DIV;
   static constexpr int kMode = N > 1024 ? (STAGE_LARGE ? 2 : 0) : (TwLayout<Plan>::kSelfReverse ? 1 : 2);
-  static constexpr int kLds = kMode == 1 ? TwLayout<Plan>::kUsed : kMode == 2 ? (kHalf ? N / 2 : N) : 1;
-  using View = typename std::conditional<kMode == 2, TwTable<N, kHalf>, TwPass>::type;
+  static constexpr int kLds = kMode == 1 ? TwLayout<Plan>::kUsed : kMode == 2 ? N / kDiv : 1;
+  using View = typename std::conditional<kMode == 2, TwTable<N, kDiv>, TwPass>::type;
   // pass: per-pass tables in global memory (forward, then reversed plan);
   // full: w_N^m in global memory; lds: the staged copy.
   __device__ static const float2* staged_from(const float2* pass, const float2* full) {

@@ -177,13 +177,25 @@ using RowCfgSel = typename std::conditional<PLAN == 2, RowCfgAlt2<NX>,
 
 template <int NX, int PLAN> constexpr int row_threads() { return RowCfgSel<NX, PLAN>::T * RowCfgSel<NX, PLAN>::RW; }
 
-// LDS a row sweep needs: the exchange buffer and the staged twiddles.  The
-// update sweep stages half of w_N^m: the 4 KB saved let a fourth workgroup of
-// the 16x16x4 plan fit in a CU's LDS (its registers allow it).
+// LDS a row sweep needs: the exchange buffer and the staged twiddles, a
+// fraction 1/row_tw_div of w_N^m (TwTable).  The update sweep stages half of
+// it up to 1024: the 4 KB saved let a fourth workgroup of the 16x16x4 plan fit
+// in a CU's LDS (its registers allow it; the other sweeps at 1024 gained
+// nothing from a quarter table).  At 2048, beside the two rows' 33 KB exchange
+// buffer, the half table (8 KB) leaves room for three workgroups per CU and
+// the quarter table (4 KB) for four; the quarter's rotations cost registers,
+// and the x t, intensity and gradient sweeps run as fast or faster with the
+// half table (x t spills with the quarter).  Reading the per-pass tables from
+// global memory instead cost the 2048 row sweeps 20% (23.1 against 18.7 ms
+// per iteration of 180 projections).
+template <int NX, int OP> constexpr int row_tw_div() {
+  if constexpr (NX > 1024) return (OP == ROW_MUL_T || OP == ROW_INTENSITY || OP == ROW_GRAD) ? 2 : 4;
+  else return (OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR) ? 2 : 1;
+}
 template <int NX, int OP, int PLAN>
 struct RowLds {
   using C = RowCfgSel<NX, PLAN>;
-  using TS = TwSel<typename C::Plan, OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR>;
+  using TS = TwSel<typename C::Plan, row_tw_div<NX, OP>(), true>;
   static constexpr int kExchange = C::RW * lds_len(NX);
   static constexpr int kTwiddles = TS::kLds;
 };
@@ -599,7 +611,7 @@ template <int NY, int W, int OP> constexpr int col_min_waves() {
 template <int NY, int W>
 struct ColLds {
   static constexpr int NF = col_fft_len<NY>();
-  using TS = TwSel<typename ColCfg<NF>::Plan, false, true>;
+  using TS = TwSel<typename ColCfg<NF>::Plan, 1, true>;
   static constexpr int kExchange = W * lds_len(NF);
   static constexpr int kTwiddles = TS::kLds;
 };
