@@ -213,6 +213,15 @@ template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static 
 // workgroups per CU.  The spectra kept between iterations (Psi^, Z^, Y^) are
 // stored in the same order: row p H + j holds ky = 2 j + p.
 template <int NY> constexpr bool col_split() { return NY >= 2048; }
+// Stored row of W, x and v for position j of half p of a split transform (row
+// p ny/2 + j): the halves are interleaved in blocks of kSplitBlock rows, so
+// that the two rows of a row sweep's pair lie kSplitBlock rows apart (the
+// workgroups in flight read and write one region, not two ny/2 rows apart)
+// while a column sweep still reads runs of kSplitBlock consecutive rows.
+constexpr int kSplitBlock = 8;
+__host__ __device__ constexpr int split_row(int j, int p) {
+  return ((j & ~(kSplitBlock - 1)) << 1) + p * kSplitBlock + (j & (kSplitBlock - 1));
+}
 constexpr bool col_split_n(int ny) { return ny >= 2048; }
 template <int NY> constexpr int col_fft_len() { return col_split<NY>() ? NY / 2 : NY; }
 // Column configuration of the sweeps on side NY (transform length and tile widths).

@@ -85,39 +85,61 @@ __device__ __forceinline__ float2 cexp_f(float2 p) {
 
 // Butterflies of the column transform's radix-2 split (col_split) in the row
 // sweeps.  The two rows n and n + H of a pair sit PD lanes apart in one wave
-// (pb = 1 for row n + H) and hold the same x positions, so each value meets
-// its partner through one cross-lane move: at PD = 32, v_permlane32_swap of
-// two copies (the upper half of the wave then holds the lower half's values
-// and vice versa), else a lane shuffle.  w = w_ny^n.
-template <int PD>
-__device__ __forceinline__ float pair_partner(float a, int pb) {
-  if constexpr (PD == 32) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(a), false, false);
-    return __uint_as_float(pb ? r[0] : r[1]);
+// (pb = 1 for row n + H) and hold the same x positions.  w = w_ny^n.
+//   reading W after a column sweep: row n holds A[n], row n + H holds B[n];
+//     x[n] = A + w^-n B, x[n + H] = A - w^-n B;
+//   writing W for a column sweep: rows n, n + H hold X[n], X[n + H];
+//     a[n] = X[n] + X[n + H] (row n), b[n] = (X[n] - X[n + H]) w^n (row n + H).
+// At PD = 32 two elements go at once: v_permlane32_swap of the registers of
+// elements e1, e2 leaves the lower half-wave with both rows' values of e1 and
+// the upper half with those of e2; each lane computes both outputs of its
+// element and a second swap returns them to their rows.  Other PD (sides
+// below 64 points per lane group) exchange each value with a lane shuffle.
+__device__ __forceinline__ void lane_swap32(float& p, float& q) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(p), __float_as_uint(q), false, false);
+  p = __uint_as_float(r[0]);
+  q = __uint_as_float(r[1]);
+}
+template <bool FWD>
+__device__ __forceinline__ void split_butterfly(float2& a, float2& b, float2 w) {
+  if constexpr (FWD) {
+    const float2 d = make_float2(a.x - b.x, a.y - b.y);
+    a = make_float2(a.x + b.x, a.y + b.y);
+    b = cmul(d, w);
   } else {
-    return __shfl_xor(a, PD, 64);
+    const float2 wb = cmulc(b, w);
+    b = make_float2(a.x - wb.x, a.y - wb.y);
+    a = make_float2(a.x + wb.x, a.y + wb.y);
   }
 }
-template <int PD>
-__device__ __forceinline__ float2 pair_partner(float2 a, int pb) {
-  return make_float2(pair_partner<PD>(a.x, pb), pair_partner<PD>(a.y, pb));
+// elements p, q of this lane (PD = 32): both replaced by this row's outputs
+template <bool FWD>
+__device__ __forceinline__ void split_two(float2& p, float2& q, float2 w) {
+  lane_swap32(p.x, q.x);
+  lane_swap32(p.y, q.y);
+  split_butterfly<FWD>(p, q, w);   // (row n, row n + H) values of one element
+  lane_swap32(p.x, q.x);
+  lane_swap32(p.y, q.y);
 }
-// Reading W after a column sweep: the lane of row n (pb = 0) holds A[n], its
-// partner (pb = 1) B[n]; returns x[n] = A + w^-n B, or x[n + H] = A - w^-n B.
-template <int PD>
-__device__ __forceinline__ float2 split_inverse(float2 mine, float2 w, int pb) {
-  const float2 other = pair_partner<PD>(mine, pb);
-  const float2 a = pb ? other : mine;
-  const float2 wb = cmulc(pb ? mine : other, w);
-  return pb ? make_float2(a.x - wb.x, a.y - wb.y) : make_float2(a.x + wb.x, a.y + wb.y);
+// one element of this lane (any PD): replaced by this row's output
+template <bool FWD, int PD>
+__device__ __forceinline__ void split_one(float2& v, float2 w, int pb) {
+  const float2 o = make_float2(__shfl_xor(v.x, PD, 64), __shfl_xor(v.y, PD, 64));
+  float2 a = pb ? o : v, b = pb ? v : o;
+  split_butterfly<FWD>(a, b, w);
+  v = pb ? b : a;
 }
-// Writing W for a column sweep: the lane of row n holds X[n], its partner
-// X[n + H]; returns a[n] = X[n] + X[n + H], or b[n] = (X[n] - X[n + H]) w^n.
-template <int PD>
-__device__ __forceinline__ float2 split_forward(float2 mine, float2 w, int pb) {
-  const float2 other = pair_partner<PD>(mine, pb);
-  return pb ? cmul(make_float2(other.x - mine.x, other.y - mine.y), w)
-            : make_float2(mine.x + other.x, mine.y + other.y);
+// The elements v[IDX(i)], i < COUNT, of this lane.
+template <bool FWD, int PD, int COUNT, class F, int E>
+__device__ __forceinline__ void split_elements(float2 (&v)[E], float2 w, int pb, F idx) {
+  if constexpr (PD == 32 && COUNT % 2 == 0) {
+    static_for<0, COUNT / 2>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      split_two<FWD>(v[idx(std::integral_constant<int, 2 * i>{})], v[idx(std::integral_constant<int, 2 * i + 1>{})], w);
+    });
+  } else {
+    static_for<0, COUNT>([&](auto ii) { split_one<FWD, PD>(v[idx(ii)], w, pb); });
+  }
 }
 
 // Twiddles staged in LDS.  Every load of the table is issued ahead of the
@@ -218,10 +240,15 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
   // Rows of the workgroup: RW consecutive rows, or, with the column transform
   // split (PAIR, pair_half = H = ny/2), RW/2 pairs (n, n + H) whose two rows
   // sit PD lanes apart in one wave (lane t of row n + H is PD lanes after lane
-  // t of row n) for the split's butterflies.
+  // t of row n) for the split's butterflies.  The workspace fields that only
+  // the row sweeps and the split halves address (W, x, v) store the two rows
+  // of a pair close together (split_row), so that a workgroup reads and
+  // writes one region instead of two ny/2 rows apart (that cost the 2048 row
+  // sweeps 7%); `mrow` is the stored row, `row` the row of the caller's
+  // fields (t, y, psi, outputs) and of u1.
   static_assert(RW % 2 == 0, "row pairs");
   constexpr int PD = T < 32 ? T : 32;
-  int t, rw, row, pb = 0, prow = 0;
+  int t, rw, row, mrow, pb = 0, prow = 0;
   if constexpr (PAIR) {
     const int H = S.pair_half;
     const int u = (int)threadIdx.x % (2 * T);
@@ -230,10 +257,12 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
     rw = 2 * ((int)threadIdx.x / (2 * T)) + pb;
     prow = blk * (RW / 2) + (int)threadIdx.x / (2 * T);
     row = prow + pb * H;
+    mrow = split_row(prow, pb);
   } else {
     t = (int)threadIdx.x % T;
     rw = (int)threadIdx.x / T;
     row = blk * RW + rw;
+    mrow = row;
   }
   const float2 wp = PAIR ? gld(S.twn_pair, (uint32_t)prow) : make_float2(1.f, 0.f);
   const LdsView lv{lds + rw * lds_len(NX), 1};
@@ -241,7 +270,8 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
   const float2* twg = PLAN == 2 ? S.tw_alt2 : PLAN == 1 ? S.tw_alt : S.tw_row;
   const auto tw = TS::forward(twl, twg);
   const auto twr = TS::inverse(twl, twg);
-  const uint32_t rbase = (uint32_t)row * NX;
+  const uint32_t rbase = (uint32_t)row * NX;   // caller fields, u1
+  const uint32_t wbase = (uint32_t)mrow * NX;  // W, x, v
   // Twiddles to LDS; the first pass needs none, and the barrier after its
   // LDS exchange orders these writes before the first use.
   TwStage<TS::kLds, row_threads<NX, PLAN>()> tws;
@@ -263,7 +293,7 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
       // half-form x-spectrum (see col_op_half): kx > nx/2 from conj at nx - kx,
       // kx = 0 and nx/2 from the packed position 0 (after the residual sweep's
       // second IOTF, kx = nx/2 still lacks its second x factor)
-      const uint32_t rh = rbase;
+      const uint32_t rh = wbase;
       const float s_ny = OP == ROW_BACKBLUR ? gldf(I.ix, NX / 2) : 1.f;
       static_for<0, E / RL>([&](auto cc) {
         static_for<0, RL>([&](auto rr) {
@@ -275,12 +305,7 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
       });
       // the split's butterflies act on the stored values (the packed column
       // included), before they are unpacked
-      if constexpr (PAIR) {
-        static_for<0, E>([&](auto ee) {
-          constexpr int e = decltype(ee)::value;
-          v[e] = split_inverse<PD>(v[e], wp, pb);
-        });
-      }
+      if constexpr (PAIR) split_elements<false, PD, E>(v, wp, pb, [](auto i) { return decltype(i)::value; });
       static_for<0, E / RL>([&](auto cc) {
         static_for<0, RL>([&](auto rr) {
           constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
@@ -296,29 +321,25 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
       static_for<0, E / RL>([&](auto cc) {
         static_for<0, RL>([&](auto rr) {
           constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
-          v[c * RL + r] = gld(I.W, rbase + col_of_kx(t + T * c + r * ML, NX));
+          v[c * RL + r] = gld(I.W, wbase + col_of_kx(t + T * c + r * ML, NX));
         });
       });
     }
     load_twiddles();
     if constexpr (SIDE) {
-      const float2* __restrict__ sp = (OP == ROW_MUL_T || OP == ROW_MUL_CONJ_T) ? I.t
-                                     : (OP == ROW_BACKBLUR ? I.v : I.x);
+      constexpr bool T_SIDE = OP == ROW_MUL_T || OP == ROW_MUL_CONJ_T;
+      const float2* __restrict__ sp = T_SIDE ? I.t : (OP == ROW_BACKBLUR ? I.v : I.x);
+      const uint32_t sb = T_SIDE ? rbase : wbase;
       static_for<0, E / R1>([&](auto cc) {
         static_for<0, R1>([&](auto qq) {
           constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-          side[c * R1 + q] = gld(sp, rbase + t + T * c + q * M1);
+          side[c * R1 + q] = gld(sp, sb + t + T * c + q * M1);
         });
       });
     }
     if constexpr (!(OP == ROW_BACKBLUR || OP == ROW_FORWARD_OUT)) {
       // (issued after the side loads, whose latency then overlaps the wait)
-      if constexpr (PAIR) {
-        static_for<0, E>([&](auto ee) {
-          constexpr int e = decltype(ee)::value;
-          v[e] = split_inverse<PD>(v[e], wp, pb);
-        });
-      }
+      if constexpr (PAIR) split_elements<false, PD, E>(v, wp, pb, [](auto i) { return decltype(i)::value; });
     }
     fft_inverse<Plan, T>(v, t, twr, lv);
   } else if constexpr (OP == ROW_REAL_FFT) {
@@ -344,12 +365,15 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
   float inv_maxt2 = 0.f;
   float u1max = 0.f;  // joint diffuser mode (S2): max |u1|^2 over this lane's elements
   if constexpr (OP == ROW_GRAD) inv_maxt2 = I.grad_mul > 0.f ? I.grad_mul : 1.0f / *I.maxt2;
-  // stopping correlation of exp(psi) with the previous iterate (FP64 sums)
+  // stopping correlation of exp(psi) with the previous iterate (FP64 sums):
+  // only the S0 variant for the stopping rule (solves with a threshold attach
+  // the partials and launch that variant)
   constexpr bool PSI = OP == ROW_PSI_UPDATE || OP == ROW_PSI_UPDATE_CORR;
-  const bool corr = PSI && I.corr_partial != nullptr;
+  const bool corr = OP == ROW_PSI_UPDATE_CORR && I.corr_partial != nullptr;
   const bool corr_sum = corr && S.iter > 0;
   double c_re = 0.0, c_im = 0.0, n_new = 0.0, n_old = 0.0;
   const uint32_t rb_rs = opaque(rbase);
+  const uint32_t wb_rs = PAIR ? opaque(wbase) : rb_rs;
   if constexpr (OP == ROW_MUL_CONJ_T) {
     if (I.u1) {
       // Joint diffuser mode: u1 <- conj(u1) a2 with a2 = this back-propagated
@@ -390,7 +414,7 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
     constexpr int b = decltype(bb)::value;
     static_for<0, NBX>([&](auto uu) {
       constexpr int u = decltype(uu)::value, e = b * NBX + u;
-      xb[XB ? b & 1 : 0][u] = gld(I.x, rb_rs + t + T * (e / R1) + (e % R1) * M1);
+      xb[XB ? b & 1 : 0][u] = gld(I.x, wb_rs + t + T * (e / R1) + (e % R1) * M1);
     });
   };
   if constexpr (XB) {
@@ -400,7 +424,8 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
       constexpr int e = c * R1 + q;
-      const uint32_t idx = rb_rs + t + T * c + q * M1;
+      const uint32_t idx = rb_rs + t + T * c + q * M1;   // caller fields, u1
+      const uint32_t midx = PAIR ? wb_rs + t + T * c + q * M1 : idx;  // x, v
       if constexpr (PSI) {
         if constexpr (XB) {
           if (corr_sum && e % NBX == 0 && e / NBX + 1 < E / NBX) load_x(std::integral_constant<int, e / NBX + 1>{});
@@ -408,17 +433,17 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
         if (corr) gst(I.out, idx, v[e]);  // psi of this iterate, kept in case the stop fires
         const float2 xn = cexp_f(v[e]);
         if (corr_sum) {
-          const float2 xo = XB ? xb[XB ? (e / NBX) & 1 : 0][e % NBX] : gld(I.x, idx);
+          const float2 xo = XB ? xb[XB ? (e / NBX) & 1 : 0][e % NBX] : gld(I.x, midx);
           c_re += (double)xn.x * xo.x + (double)xn.y * xo.y;
           c_im += (double)xn.x * xo.y - (double)xn.y * xo.x;
           n_new += (double)xn.x * xn.x + (double)xn.y * xn.y;
           n_old += (double)xo.x * xo.x + (double)xo.y * xo.y;
         }
         v[e] = xn;
-        if (I.x) gst(I.x, idx, v[e]);
+        if (I.x) gst(I.x, midx, v[e]);
       } else if constexpr (OP == ROW_START) {
         v[e] = cexp_f(v[e]);
-        if (I.x) gst(I.x, idx, v[e]);
+        if (I.x) gst(I.x, midx, v[e]);
       } else if constexpr (OP == ROW_MUL_T) {
         if (I.u1) {  // joint diffuser mode: keep u1 for the diffuser gradient of S8
           gst(I.u1, idx, v[e]);
@@ -428,13 +453,13 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
       } else if constexpr (OP == ROW_MUL_CONJ_T) {
         v[e] = cmulc(v[e], side[e]);
       } else if constexpr (OP == ROW_INTENSITY) {
-        if (I.v) gst(I.v, idx, v[e]);
+        if (I.v) gst(I.v, midx, v[e]);
         v[e] = make_float2(v[e].x * v[e].x + v[e].y * v[e].y, 0.f);
       } else if constexpr (OP == ROW_BACKBLUR) {
         const float h = v[e].x;
         v[e] = make_float2(side[e].x * h, side[e].y * h);
       } else if constexpr (OP == ROW_GRAD) {
-        const float2 xs = SIDE ? side[SIDE ? e : 0] : gld(I.x, idx);
+        const float2 xs = SIDE ? side[SIDE ? e : 0] : gld(I.x, midx);
         v[e] = cscale(cmulc(v[e], xs), inv_maxt2);
         if (I.g_out) gst(I.g_out, idx, v[e]);
         v[e].x *= kGradReScale;  // the direction sweeps undo this (see kGradReScale)
@@ -456,16 +481,15 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
       // kx = 0 in v[0] and kx = nx/2 in v[RL/2].  Element (c, r) has kx < nx/2
       // exactly when r < RL/2 (t + T c < nx/RL), so only those are stored.
       static_assert(RL % 2 == 0, "half form");
-      const uint32_t rh = opaque(rbase);
+      const uint32_t rh = opaque(wbase);
       const float s_ny = OP == ROW_INTENSITY ? gldf(I.ix, NX / 2) : 1.f;
       float2 packed = make_float2(v[0].x, s_ny * v[RL / 2].x);
       if constexpr (PAIR) {
-        packed = split_forward<PD>(packed, wp, pb);
-        static_for<0, E / RL>([&](auto cc) {
-          static_for<0, RL / 2>([&](auto rr) {
-            constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
-            v[c * RL + r] = split_forward<PD>(v[c * RL + r], wp, pb);
-          });
+        split_one<true, PD>(packed, wp, pb);
+        // the stored elements (c, r < RL/2), i -> c = i / (RL/2), r = i % (RL/2)
+        split_elements<true, PD, E / 2>(v, wp, pb, [](auto i) {
+          constexpr int k = decltype(i)::value;
+          return (k / (RL / 2)) * RL + k % (RL / 2);
         });
       }
       static_for<0, E / RL>([&](auto cc) {
@@ -477,13 +501,8 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
       });
       if (t == 0) gst(I.W, rh, packed);
     } else {
-      if constexpr (PAIR) {
-        static_for<0, E>([&](auto ee) {
-          constexpr int e = decltype(ee)::value;
-          v[e] = split_forward<PD>(v[e], wp, pb);
-        });
-      }
-      const uint32_t rb_st = opaque(rbase);
+      if constexpr (PAIR) split_elements<true, PD, E>(v, wp, pb, [](auto i) { return decltype(i)::value; });
+      const uint32_t rb_st = opaque(wbase);
       static_for<0, E / RL>([&](auto cc) {
         static_for<0, RL>([&](auto rr) {
           constexpr int c = decltype(cc)::value, r = decltype(rr)::value;
@@ -660,7 +679,13 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
   }
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int s = tile * W + w;
+  // spectra: row part NF + j; W (split): stored row split_row(j, part), which
+  // for the positions t + T c + q M1 of a lane (T, M1 multiples of the block)
+  // is split_row(t, part) + 2 (T c + q M1)
   const uint32_t o_ld = (uint32_t)((part * NF + t) * nx + s);  // element (t, s) of the half; position j adds (j - t) nx
+  constexpr int WS = SPLIT ? 2 : 1;  // W row stride of consecutive positions
+  static_assert(!SPLIT || (T % kSplitBlock == 0 && M1 % kSplitBlock == 0), "split row blocks");
+  const uint32_t o_w = SPLIT ? (uint32_t)(split_row(t, part) * nx + s) : o_ld;
   const LdsView lv{lds + w, W};
   using TS = typename ColLds<NY, W>::TS;
   const auto tw = TS::forward(twl, S.tw_col);
@@ -672,7 +697,7 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
       constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-      v[c * R1 + q] = gld(I.W, o_ld + (uint32_t)((T * c + q * M1) * nx));
+      v[c * R1 + q] = gld(I.W, o_w + (uint32_t)((T * c + q * M1) * WS * nx));
     });
   });
   // Twiddles to LDS; the first pass needs none, and the barrier after its
@@ -866,11 +891,11 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
 
   if constexpr (ColOpTraits<OP>::kInverse) {
     fft_inverse<Plan, T>(v, t, twr, lv);
-    const uint32_t o_st = opaque(o_ld);
+    const uint32_t o_st = opaque(o_w);
     static_for<0, E / R1>([&](auto cc) {
       static_for<0, R1>([&](auto qq) {
         constexpr int c = decltype(cc)::value, q = decltype(qq)::value;
-        gst(I.W, o_st + (uint32_t)((T * c + q * M1) * nx), v[c * R1 + q]);
+        gst(I.W, o_st + (uint32_t)((T * c + q * M1) * WS * nx), v[c * R1 + q]);
       });
     });
   }
