@@ -494,7 +494,7 @@ def main() -> int:
     ap.add_argument("--retune", action="store_true",
                     help="time every tile width and row plan again and rewrite the tuning cache's entries")
     ap.add_argument("--tuning-cache", default=None, help="tuning cache file (default: the package's)")
-    ap.add_argument("--iters-2048", type=int, default=10,
+    ap.add_argument("--iters-2048", type=int, default=50,
                     help="iterations of the timed 720 x 2048^2 solve (extras)")
     ap.add_argument("--workload", choices=["720x2048", "uneven"], default=None,
                     help="only run this secondary workload and print its record (profiling runs)")
@@ -551,7 +551,7 @@ def main() -> int:
             torch.cuda.synchronize()
             del src, dst
         # every compiled column-tile width in turn unless one is fixed
-        for w in ([args.col_tile] if args.col_tile else [8, 4]):
+        for w in ([args.col_tile] if args.col_tile else [16, 8]):
             _l.load().pwf_set_column_tile(1024, -1, w)
             for sw in sweeps:
                 batch.bench_sweep(sw, args.sweep_reps)

@@ -133,9 +133,9 @@ typedef struct {
  * The frequency layout is row-major [r][s]: column kx of the 2-D DFT sits at
  * s = 2 kx for 0 < kx < nx/2, at s = 2 (nx - kx) + 1 for nx/2 < kx < nx, at
  * s = 0 for kx = 0 and at s = 1 for kx = nx/2, so that kx and -kx are
- * neighbours.  Row r holds ky = r for ny < 2048; for ny = 2048 the column
+ * neighbours.  Row r holds ky = r for ny < 512; for ny >= 512 the column
  * transform is split into its even and odd frequencies (one radix-2 stage in
- * the row sweeps, two 1024-point halves in the column sweeps), and row
+ * the row sweeps, two ny/2-point halves in the column sweeps), and row
  * r = p ny/2 + j holds ky = 2 j + p (p = 0, 1). */
 typedef struct {
   void* psi;
@@ -281,9 +281,9 @@ pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep
 /* Tile width (columns per workgroup) of the column sweep S`sweep` of the
  * iteration (sweep = 1, 3, 5, 7, 9 or 11; -1: every column sweep, including
  * those of pwf_forward / pwf_gradient) for grid side n.  Two widths are
- * compiled per side (128: 32/16, 256: 16/32, 512: 16/8, 1024: 8/4,
- * 2048: 8/4, over one 1024-row half of the split column transform; see the
- * state layout above); 0 restores the default.  PWF_ERR_SIZE / PWF_ERR_ARG for an
+ * compiled per side (128: 32/16, 256: 16/32, and over one half of the split
+ * column transform of the larger sides (see the state layout above) 512:
+ * 16/32, 1024: 16/8, 2048: 8/4); 0 restores the default.  PWF_ERR_SIZE / PWF_ERR_ARG for an
  * unsupported side, sweep or width.  Process-wide; applies to calls issued
  * afterwards. */
 pwf_status pwf_set_column_tile(int32_t n, int32_t sweep, int32_t width);
@@ -314,7 +314,7 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
 
 /* Autotuner with a persistent cache: a text file at cache_path (host path,
  * created when missing) keyed by the device's architecture with the library
- * version (e.g. "gfx950/v10200": entries timed on other kernels are not
+ * version (e.g. "gfx950/v10300": entries timed on other kernels are not
  * reused), the batch's class mix (its grid shapes and instance counts) and
  * the grid side, holding
  * that side's column-tile widths (S1..S11) and row plans (S0..S10).  When

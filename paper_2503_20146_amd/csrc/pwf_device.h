@@ -197,22 +197,27 @@ template <> struct ColCfg<512>  { using Plan = FftPlan<512, 16, 8, 4>;   static 
 template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  WA = 8,  WB = 4; };
 template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, WA = 4,  WB = 8; };
 
-// Radix-2 split of the long column transforms in the sweeps.  A 2048-point
-// column needs 16 KB of LDS, so a tile of 8 columns (64-byte row segments)
-// would run alone on its CU, and 4-column tiles read 32-byte segments.  The
-// sweeps therefore take the first radix-2 stage of the y transform out of the
-// column sweeps (decimation in frequency):
+// Radix-2 split of the column transforms of the sweeps on sides of 512 and
+// more.  A 2048-point column needs 16 KB of LDS, so a tile of 8 columns
+// (64-byte row segments) would run alone on its CU, and 4-column tiles read
+// 32-byte segments; at 1024 and 512 points the halves admit twice the tile
+// width at the same LDS and registers (16 columns, 128-byte row segments, in
+// place of 8 at 1024; 16 or 32 in place of 16 or 8 at 512: the column sweeps
+// gain 4-9%).  The sweeps therefore take the first radix-2
+// stage of the y transform out of the column sweeps (decimation in
+// frequency):
 //   forward: a[n] = x[n] + x[n + H],  b[n] = (x[n] - x[n + H]) w^n,  H = ny/2,
 //            then X[2j] = FFT_H(a)[j] and X[2j + 1] = FFT_H(b)[j];
 //   inverse: x[n] = A[n] + w^-n B[n],  x[n + H] = A[n] - w^-n B[n], with A, B
 //            the inverse H-point transforms of the even and odd ky,
 // w = exp(-2 pi i / ny).  Row sweeps handle rows n and n + H together and
 // apply these butterflies as they read and write W; a column sweep's
-// workgroup runs one H-point half (rows p H .. p H + H - 1, ky = 2 j + p), so
-// at 2048 it has the shape of a 1024-point sweep: 8-column tiles, two
-// workgroups per CU.  The spectra kept between iterations (Psi^, Z^, Y^) are
-// stored in the same order: row p H + j holds ky = 2 j + p.
-template <int NY> constexpr bool col_split() { return NY >= 2048; }
+// workgroup runs one H-point half (ky = 2 j + p for position j of half p).
+// The spectra kept between iterations (Psi^, Z^, Y^) store half p's position
+// j at row p H + j.
+template <int NY> constexpr bool col_split() { return NY >= 512; }
+constexpr bool col_split_n(int ny) { return ny >= 512; }
+
 // Stored row of W, x and v for position j of half p of a split transform (row
 // p ny/2 + j): the halves are interleaved in blocks of kSplitBlock rows, so
 // that the two rows of a row sweep's pair lie kSplitBlock rows apart (the
@@ -222,7 +227,6 @@ constexpr int kSplitBlock = 8;
 __host__ __device__ constexpr int split_row(int j, int p) {
   return ((j & ~(kSplitBlock - 1)) << 1) + p * kSplitBlock + (j & (kSplitBlock - 1));
 }
-constexpr bool col_split_n(int ny) { return ny >= 2048; }
 template <int NY> constexpr int col_fft_len() { return col_split<NY>() ? NY / 2 : NY; }
 // Column configuration of the sweeps on side NY (transform length and tile widths).
 template <int NY> using ColSweepCfg = ColCfg<col_fft_len<NY>()>;

@@ -1,12 +1,12 @@
 // Sweeps of the iteration launched once over several size classes of an
 // uneven batch.  Every class keeps its own descriptors and launch arguments;
 // each workgroup finds its class from the block offsets and runs that side's
-// sweep body.  Row bodies: 256 threads and a 33.8 KB exchange buffer on every
-// side (512: 32 x 8 rows; 1024 and 2048: the 64- and 128-lane plans, 4 and 2
-// rows); column bodies: 512 threads and a 67.6 KB exchange buffer (512: 16
-// columns, 1024: 8, 2048: 8 columns of one half of the split transform).  The
-// LDS pools below are the largest each body needs, so every class runs at the
-// occupancy of its own kernel or close to it.
+// sweep body.  Row bodies: 256 threads on every side (512: 32 x 8 rows; 1024
+// and 2048: the 64- and 128-lane plans, 4 and 2 rows), rows paired for the
+// split column transforms of these sides; column bodies: 512 threads (one
+// half of the split transform: 256, 512 and 1024 points, 32, 16 and 8
+// columns).  The LDS pools below are the largest each body needs, so every
+// class runs at the occupancy of its own kernel or close to it.
 #include "pwf_sweeps.h"
 
 namespace pwf {
@@ -40,19 +40,21 @@ __global__ void __launch_bounds__(256, (multi_row_waves<OP>())) row_sweep_multi(
   int c = 0;
   while (c + 1 < M.nc && b >= M.first[c + 1]) ++c;
   const int lb = b - M.first[c];
-  // (a 2048-point side comes with its split column transform: paired rows)
+  // (the merged sides all come with split column transforms: paired rows)
   const int key = M.side[c] * 4 + M.plan[c];
-  if (key == 512 * 4 + 0) row_body<512, OP, 0, false>(M.s[c], lb, lds, twl);
-  else if (key == 1024 * 4 + 1) row_body<1024, OP, 1, false>(M.s[c], lb, lds, twl);
-  else if (key == 1024 * 4 + 2) row_body<1024, OP, 2, false>(M.s[c], lb, lds, twl);
+  if (key == 512 * 4 + 0) row_body<512, OP, 0, true>(M.s[c], lb, lds, twl);
+  else if (key == 1024 * 4 + 1) row_body<1024, OP, 1, true>(M.s[c], lb, lds, twl);
+  else if (key == 1024 * 4 + 2) row_body<1024, OP, 2, true>(M.s[c], lb, lds, twl);
   else if (key == 2048 * 4 + 1) row_body<2048, OP, 1, true>(M.s[c], lb, lds, twl);
   else if (key == 2048 * 4 + 2) row_body<2048, OP, 2, true>(M.s[c], lb, lds, twl);
 }
 
-constexpr int kMultiColExchange = cmax(cmax(ColLds<512, 16>::kExchange, ColLds<1024, 8>::kExchange),
-                                       ColLds<2048, 8>::kExchange);
-constexpr int kMultiColTwiddles = cmax(cmax(ColLds<512, 16>::kTwiddles, ColLds<1024, 8>::kTwiddles),
-                                       ColLds<2048, 8>::kTwiddles);
+// column tile of the merged kernel's body on side N: 512 threads
+template <int N> constexpr int multi_w() { return 512 / ColSweepCfg<N>::T; }
+constexpr int kMultiColExchange = cmax(cmax(ColLds<512, multi_w<512>()>::kExchange, ColLds<1024, multi_w<1024>()>::kExchange),
+                                       ColLds<2048, multi_w<2048>()>::kExchange);
+constexpr int kMultiColTwiddles = cmax(cmax(ColLds<512, multi_w<512>()>::kTwiddles, ColLds<1024, multi_w<1024>()>::kTwiddles),
+                                       ColLds<2048, multi_w<2048>()>::kTwiddles);
 
 template <int OP>
 __global__ void __launch_bounds__(512, 4) col_sweep_multi(MultiSweep M) {
@@ -63,9 +65,9 @@ __global__ void __launch_bounds__(512, 4) col_sweep_multi(MultiSweep M) {
   while (c + 1 < M.nc && b >= M.first[c + 1]) ++c;
   const int lb = b - M.first[c];
   switch (M.side[c]) {
-    case 512: col_body<512, 16, OP>(M.s[c], lb, lds, twl); break;
-    case 1024: col_body<1024, 8, OP>(M.s[c], lb, lds, twl); break;
-    case 2048: col_body<2048, 8, OP>(M.s[c], lb, lds, twl); break;
+    case 512: col_body<512, multi_w<512>(), OP>(M.s[c], lb, lds, twl); break;
+    case 1024: col_body<1024, multi_w<1024>(), OP>(M.s[c], lb, lds, twl); break;
+    case 2048: col_body<2048, multi_w<2048>(), OP>(M.s[c], lb, lds, twl); break;
     default: break;
   }
 }
@@ -73,12 +75,14 @@ __global__ void __launch_bounds__(512, 4) col_sweep_multi(MultiSweep M) {
 }  // namespace
 
 bool multi_row_supported(int nx, int ny, int plan) {
-  // rows are paired exactly when the side is 2048 (square grids of the merged sides)
-  if ((nx == 2048) != col_split_n(ny)) return false;
+  // the merged row bodies pair their rows: classes whose column transform is split
+  if (!col_split_n(ny)) return false;
   return (nx == 512 && plan == 0) || ((nx == 1024 || nx == 2048) && (plan == 1 || plan == 2));
 }
 
-int multi_col_width(int ny) { return ny == 512 ? 16 : ny == 1024 ? 8 : ny == 2048 ? 8 : 0; }
+int multi_col_width(int ny) {
+  return ny == 512 ? multi_w<512>() : ny == 1024 ? multi_w<1024>() : ny == 2048 ? multi_w<2048>() : 0;
+}
 
 hipError_t launch_row_multi(int op, int nblocks, const MultiSweep& M, hipStream_t st) {
   const dim3 grid(nblocks), block(256);

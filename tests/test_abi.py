@@ -54,19 +54,21 @@ def test_status_strings(lib):
 
 def test_tuning_settings(lib):
     """Tile widths and row plans: defaults, settable values, errors (host-only calls)."""
-    assert lib.pwf_column_tile(1024, 1) == 8 and lib.pwf_column_tile(2048, 11) == 8
+    # defaults: 16 columns at 1024 and 8 at 2048 (one half of the split column transform)
+    assert lib.pwf_column_tile(1024, 1) == 16 and lib.pwf_column_tile(2048, 11) == 8
     assert lib.pwf_column_tile(100, 1) == 0 and lib.pwf_column_tile(1024, 2) == 0
     assert lib.pwf_set_column_tile(1024, -1, 3) == -1
-    assert lib.pwf_set_column_tile(1024, 4, 4) == -1     # S4 is a row sweep
-    assert lib.pwf_set_column_tile(100, -1, 4) == -2
+    assert lib.pwf_set_column_tile(1024, -1, 4) == -1    # not compiled at 1024 (16 and 8 are)
+    assert lib.pwf_set_column_tile(1024, 4, 8) == -1     # S4 is a row sweep
+    assert lib.pwf_set_column_tile(100, -1, 8) == -2
     try:
-        assert lib.pwf_set_column_tile(1024, 11, 4) == 0
-        assert lib.pwf_column_tile(1024, 11) == 4 and lib.pwf_column_tile(1024, 1) == 8
-        assert lib.pwf_set_column_tile(1024, -1, 4) == 0
-        assert all(lib.pwf_column_tile(1024, s) == 4 for s in range(1, 12, 2))
+        assert lib.pwf_set_column_tile(1024, 11, 8) == 0
+        assert lib.pwf_column_tile(1024, 11) == 8 and lib.pwf_column_tile(1024, 1) == 16
+        assert lib.pwf_set_column_tile(1024, -1, 8) == 0
+        assert all(lib.pwf_column_tile(1024, s) == 8 for s in range(1, 12, 2))
     finally:
         lib.pwf_set_column_tile(1024, -1, 0)
-    assert lib.pwf_column_tile(1024, 11) == 8
+    assert lib.pwf_column_tile(1024, 11) == 16
     # built-in plans at 1024: every tunable row sweep on the alternative plan
     assert [lib.pwf_row_plan(1024, s) for s in range(0, 12, 2)] == [1, 1, 1, 1, 1, 1]
     assert [lib.pwf_row_plan(2048, s) for s in range(0, 12, 2)] == [1, 0, 1, 0, 0, 1]
