@@ -367,10 +367,13 @@ def test_plain_path_parity():
     assert np.all(np.abs(hist.cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
-def test_step_matches_solve_and_oracle_state():
+@pytest.mark.parametrize("n", [128, 512])
+def test_step_matches_solve_and_oracle_state(n):
+    """pwf_state / pwf_step against pwf_solve and the oracle; at 512 the state's
+    spectra are in the split column layout (even and odd ky halves)."""
     dev = device()
-    inp, geo, prob, y = instance(0)
-    say("step x 7 vs solve 7")
+    inp, geo, prob, y = instance(0, n=n)
+    say(f"step x 7 vs solve 7 at {n}^2")
     batch = _pwf([gpu_problem(geo, inp["t"], dev)])
     yd = to_dev(y, dev)
     states = batch.init_states([yd])
@@ -484,6 +487,32 @@ def test_mixed_sizes_in_one_batch():
         assert torch.equal(out[i], one[0])
         psi_ref, _, _ = O.pwf(refs[i][1], refs[i][0], 10)
         assert np.sqrt(np.mean(np.abs(out[i].cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL
+
+
+@pytest.mark.parametrize("ny,nx", [(512, 256), (1024, 128)])
+def test_solve_nonsquare_split_matches_oracle(ny, nx):
+    """Split column transform (ny >= 512) with rows shorter than 64 lanes per
+    pair (the split's butterflies then exchange values by lane shuffle): 10
+    iterations against the oracle, and batched with a square instance equal
+    to alone."""
+    import torch
+    dev = device()
+    say(f"solve {ny}x{nx}, split columns, 10 iterations")
+    rng = np.random.default_rng(ny + 3 * nx)
+    geo = S.Geometry(ny=ny, nx=nx, sigma_x_px=1.1, sigma_y_px=0.9)
+    t = S.diffuser(rng, ny, nx)
+    psi_true = S.phase_object(rng, ny, nx, 4.0, 2.0)
+    prob = O.make_problem(t, geo)
+    f, _, _ = O.physical_model(psi_true, prob)
+    y = S.poisson_intensity(f, (11, ny, nx))
+    p = gpu_problem(geo, t, dev)
+    out, hist = _pwf([p]).solve([to_dev(y, dev)], 10)
+    psi_ref, hist_ref, _ = O.pwf(y, prob, 10)
+    assert np.sqrt(np.mean(np.abs(out[0].cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL
+    assert np.all(np.abs(hist[0].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
+    inp2, geo2, _, y2 = instance(0, n=512)
+    both, _ = _pwf([gpu_problem(geo2, inp2["t"], dev), p]).solve([to_dev(y2, dev), to_dev(y, dev)], 10)
+    assert torch.equal(both[1], out[0])
 
 
 def test_graph_replay_equals_eager():
