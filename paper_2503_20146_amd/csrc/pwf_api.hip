@@ -643,9 +643,22 @@ pwf_status check_ws(const pwf_problem* probs, int n, void* ws, size_t ws_bytes, 
 }
 
 // max|t|^2 for every distinct diffuser; sets inst.maxt2.
+// (the distinct diffusers in launches of up to kMaxabs2Batch: a batch of
+// distinct ROIs would otherwise queue two small launches per instance)
 pwf_status launch_maxt2(const pwf_problem* probs, int n, const Batch& B, std::vector<Inst>& desc, char* ws,
                         const Layout& L, hipStream_t st) {
   std::vector<const void*> seen;
+  pwf::Maxabs2Batch mb;
+  std::memset(&mb, 0, sizeof(mb));
+  int first = 0;  // slot of mb's first entry
+  auto flush = [&]() -> pwf_status {
+    if (mb.n == 0) return PWF_OK;
+    float* part = (float*)(ws + L.maxt2_part) + (size_t)first * pwf::maxabs2_blocks();
+    PWF_HIP(pwf::launch_maxabs2_batch(mb, part, st));
+    first += mb.n;
+    mb.n = 0;
+    return PWF_OK;
+  };
   for (int s = 0; s < n; ++s) {
     const pwf_problem& p = probs[B.order[s]];
     int slot = -1;
@@ -654,13 +667,15 @@ pwf_status launch_maxt2(const pwf_problem* probs, int n, const Batch& B, std::ve
     if (slot < 0) {
       slot = (int)seen.size();
       seen.push_back(p.diffuser);
-      float* part = (float*)(ws + L.maxt2_part) + (size_t)slot * pwf::maxabs2_blocks();
-      PWF_HIP(pwf::launch_maxabs2((const float2*)p.diffuser, (size_t)p.geom.nx * p.geom.ny, part,
-                                  (float*)(ws + L.maxt2) + slot, st));
+      if (mb.n == pwf::kMaxabs2Batch) PWF_TRY(flush());
+      mb.t[mb.n] = (const float2*)p.diffuser;
+      mb.m[mb.n] = (size_t)p.geom.nx * p.geom.ny;
+      mb.out[mb.n] = (float*)(ws + L.maxt2) + slot;
+      ++mb.n;
     }
     desc[s].maxt2 = (const float*)(ws + L.maxt2) + slot;
   }
-  return PWF_OK;
+  return flush();
 }
 
 }  // namespace

@@ -146,6 +146,16 @@ hipError_t launch_joint_update(float* u1max, int n, int count, size_t max_stride
                                hipStream_t st);
 int maxabs2_blocks();
 hipError_t launch_maxabs2(const float2* t, size_t m, float* partial, float* out, hipStream_t st);
+// max |t|^2 of B.n <= kMaxabs2Batch diffusers in two launches; partial holds
+// maxabs2_blocks() floats per diffuser (diffuser d at d * maxabs2_blocks()).
+constexpr int kMaxabs2Batch = 32;
+struct Maxabs2Batch {
+  const float2* t[kMaxabs2Batch];
+  size_t m[kMaxabs2Batch];
+  float* out[kMaxabs2Batch];
+  int32_t n;
+};
+hipError_t launch_maxabs2_batch(const Maxabs2Batch& B, float* partial, hipStream_t st);
 
 // Number of float2 twiddles of the N-point row (which = 0), column (1),
 // alternative row (2) or third row (3) plan, forward and reversed; fills

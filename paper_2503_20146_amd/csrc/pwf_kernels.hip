@@ -154,6 +154,37 @@ __global__ void maxabs2_final(const float* __restrict__ partial, int np, float* 
   }
 }
 
+// max |t|^2 of up to kMaxabs2Batch diffusers in one launch pair (blockIdx.y =
+// diffuser): the same per-block partials and the same final reduction order
+// as maxabs2_partial / maxabs2_final.
+__global__ void maxabs2_partial_multi(Maxabs2Batch B, float* __restrict__ partial) {
+  const int d = blockIdx.y;
+  const float2* __restrict__ t = B.t[d];
+  const size_t m = B.m[d];
+  float mx = 0.f;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 a = t[i];
+    mx = fmaxf(mx, a.x * a.x + a.y * a.y);
+  }
+  __shared__ float red[16];
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) mx = fmaxf(mx, red[i]);
+    partial[(size_t)d * gridDim.x + blockIdx.x] = fmaxf(mx, red[0]);
+  }
+}
+
+__global__ void maxabs2_final_multi(Maxabs2Batch B, const float* __restrict__ partial, int np) {
+  if (threadIdx.x == 0) {
+    const int d = blockIdx.x;
+    float mx = 0.f;
+    for (int i = 0; i < np; ++i) mx = fmaxf(mx, partial[(size_t)d * np + i]);
+    *B.out[d] = mx;
+  }
+}
+
 // 1-D factors of the separable windows of one instance (FP64 arguments).
 __global__ void build_tables_kernel(const Inst* __restrict__ insts) {
   const Inst I = insts[blockIdx.x];
@@ -500,6 +531,13 @@ hipError_t launch_speckle_sums(const float* img, int nx, int ny, int max_shift, 
                      partial);
   hipLaunchKernelGGL(speckle_sums_final, dim3(1), dim3(128), 0, st, partial, speckle_sum_blocks(),
                      1 + 2 * (kMaxShift + 1), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxabs2_batch(const Maxabs2Batch& B, float* partial, hipStream_t st) {
+  if (B.n < 1 || B.n > kMaxabs2Batch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(maxabs2_partial_multi, dim3(maxabs2_blocks(), B.n), dim3(256), 0, st, B, partial);
+  hipLaunchKernelGGL(maxabs2_final_multi, dim3(B.n), dim3(64), 0, st, B, partial, maxabs2_blocks());
   return hipGetLastError();
 }
 
