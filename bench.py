@@ -47,11 +47,17 @@ SWEEP_SOURCES = ["pwf_device.h", "pwf_fft.h", "pwf_sweeps.h", "pwf_sweeps_1024.h
 
 
 def kernel_source_hash() -> str:
+    """Hash of the code of SWEEP_SOURCES with comments and whitespace removed (a change
+    of comments leaves the kernels, and so the counters, as they were)."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2503_20146_amd", "csrc")
     for f in SWEEP_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -93,8 +93,8 @@ __device__ __forceinline__ float2 cexp_f(float2 p) {
 // At PD = 32 two elements go at once: v_permlane32_swap of the registers of
 // elements e1, e2 leaves the lower half-wave with both rows' values of e1 and
 // the upper half with those of e2; each lane computes both outputs of its
-// element and a second swap returns them to their rows.  Other PD (sides
-// below 64 points per lane group) exchange each value with a lane shuffle.
+// element and a second swap returns them to their rows.  Rows on fewer than
+// 32 lanes (sides 128 and 256) exchange each value with a lane shuffle.
 __device__ __forceinline__ void lane_swap32(float& p, float& q) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(p), __float_as_uint(q), false, false);
   p = __uint_as_float(r[0]);
@@ -142,10 +142,6 @@ __device__ __forceinline__ void split_elements(float2 (&v)[E], float2 w, int pb,
   }
 }
 
-// Twiddles staged in LDS.  Every load of the table is issued ahead of the
-// sweep's own loads and held in registers, and the LDS writes come after those
-// loads are issued: the table's latency then hides under the data's instead of
-// costing one dependent round trip per strided chunk of the table.
 // A copy of v that the compiler cannot see through.  Stores at the end of a
 // sweep take their offsets from such a copy: otherwise the compiler reuses the
 // 64-bit addresses of the matching loads and keeps one register pair per
@@ -155,6 +151,10 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
   return v;
 }
 
+// Twiddles staged in LDS.  Every load of the table is issued ahead of the
+// sweep's own loads and held in registers, and the LDS writes come after those
+// loads are issued: the table's latency then hides under the data's instead of
+// costing one dependent round trip per strided chunk of the table.
 template <int COUNT, int NTHR>
 struct TwStage {
   static constexpr int K = (COUNT + NTHR - 1) / NTHR;
