@@ -633,7 +633,11 @@ struct ColLds {
   using TS = TwSel<typename ColCfg<NF>::Plan, 1, true>;
   static constexpr int kExchange = W * lds_len(NF);
   static constexpr int kTwiddles = TS::kLds;
+  static constexpr int kYTable = NF / 2 + 1;  // chirp sweeps: staged y factors
 };
+constexpr bool col_op_chirp(int op) {
+  return op == COL_CHIRP1 || op == COL_CHIRP1_CONJ || op == COL_CHIRP2 || op == COL_CHIRP2_CONJ;
+}
 
 // Column sweep `OP` on logical block b (instance b / blocks_per_inst) with the
 // caller's LDS (ColLds sizes).
@@ -642,7 +646,7 @@ struct ColLds {
 // half, over the same tiles; elements are addressed by their position j in
 // the half-column (row part NY/2 + j) and the frequency is ky = 2 j + part.
 template <int NY, int W, int OP>
-__device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, float2* twl) {
+__device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, float2* twl, float2* qyl) {
   constexpr bool SPLIT = col_split<NY>();
   constexpr int NF = col_fft_len<NY>();
   using C = ColCfg<NF>;
@@ -693,6 +697,25 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
 
   TwStage<TS::kLds, NT> tws;
   if constexpr (TS::kMode != 0) tws.load(TS::staged_from(S.tw_col, S.twn_col));
+  // The chirp sweeps' y factors staged in LDS like the twiddles, instead of
+  // one global load per element (the 16-column chirp sweeps at 1024: 0.636 ->
+  // 0.591 ms).  The factor depends on fy^2, so positions j and mirror_pos(j)
+  // (ky and -ky) share it: the table (the caller's LDS, ColLds::kYTable
+  // entries) holds positions 0 .. NF/2 (4 KB at 1024 points, which still lets
+  // two workgroups share a CU).
+  constexpr bool YSTAGE = col_op_chirp(OP);
+  constexpr int NQ = YSTAGE ? ColLds<NY, W>::kYTable : 1;
+  constexpr int KQ = (NQ + NT - 1) / NT;
+  float2 qys[YSTAGE ? KQ : 1];
+  if constexpr (YSTAGE) {
+    const float2* __restrict__ qsrc = (OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ) ? I.qy1 : I.qy2;
+    static_for<0, KQ>([&](auto jj) {
+      constexpr int k = decltype(jj)::value;
+      const int j = (int)threadIdx.x + k * NT;
+      // (half 1 uses positions below NF/2 only: its entry NF/2 would be ky = ny + 1)
+      if (j < NQ && !(part == 1 && j == NF / 2)) qys[k] = gld(qsrc, (uint32_t)ky_of(j));
+    });
+  }
   float2 v[E];
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
@@ -700,9 +723,16 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
       v[c * R1 + q] = gld(I.W, o_w + (uint32_t)((T * c + q * M1) * WS * nx));
     });
   });
-  // Twiddles to LDS; the first pass needs none, and the barrier after its
-  // LDS exchange orders these writes before the first use.
+  // Twiddles (and y factors) to LDS; the first pass needs none, and the
+  // barrier after its LDS exchange orders these writes before the first use.
   if constexpr (TS::kMode != 0) tws.store(twl);
+  if constexpr (YSTAGE) {
+    static_for<0, KQ>([&](auto jj) {
+      constexpr int k = decltype(jj)::value;
+      const int j = (int)threadIdx.x + k * NT;
+      if (j < NQ && !(part == 1 && j == NF / 2)) qyl[j] = qys[k];
+    });
+  }
   fft_forward<Plan, T>(v, t, tw, lv);
 
   // Fourier-domain step; element e = c*RL + r holds position j = t + T c + r ML.
@@ -839,19 +869,25 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
       const float2* __restrict__ qy = L1 ? I.qy1 : I.qy2;
       const float two_pi_a = L1 ? I.two_pi_a1 : I.two_pi_a2;
       // the y factors carry the 1/m of the inverse transform
+      // y factor of position j (staged: that of min(j, mirror_pos(j)); else from the table)
+      auto qy_at = [&](int j) {
+        if constexpr (YSTAGE) return qyl[j <= NF / 2 - part ? j : mirror_pos(j)];
+        else return gld(qy, (uint32_t)ky_of(j));
+      };
       if (I.series && I.cross) {
         static_for<0, E>([&](auto ee) {
           constexpr int e = decltype(ee)::value;
-          const int ky = ky_of(t + T * (e / RL) + (e % RL) * ML);
-          float2 q = transfer_sep(qx, gld(qy, ky), fx, freq_of(ky, NY), I.s_coef_f, two_pi_a);
+          const int j = t + T * (e / RL) + (e % RL) * ML;
+          const int ky = ky_of(j);
+          float2 q = transfer_sep(qx, qy_at(j), fx, freq_of(ky, NY), I.s_coef_f, two_pi_a);
           if (CONJ) q = cconj(q);
           v[e] = cmul(v[e], q);
         });
       } else if (I.series) {
         static_for<0, E>([&](auto ee) {
           constexpr int e = decltype(ee)::value;
-          const int ky = ky_of(t + T * (e / RL) + (e % RL) * ML);
-          float2 q = cmul(qx, gld(qy, ky));
+          const int j = t + T * (e / RL) + (e % RL) * ML;
+          float2 q = cmul(qx, qy_at(j));
           if (CONJ) q = cconj(q);
           v[e] = cmul(v[e], q);
         });
@@ -917,10 +953,11 @@ template <int NY, int W, int OP>
 __global__ void __launch_bounds__(ColSweepCfg<NY>::T * W, (col_min_waves<NY, W, OP>())) col_sweep(Sweep S) {
   __shared__ float2 lds[ColLds<NY, W>::kExchange];
   __shared__ float2 twl[ColLds<NY, W>::kTwiddles];
+  __shared__ float2 qyl[col_op_chirp(OP) ? ColLds<NY, W>::kYTable : 1];
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous range of tiles so that tiles sharing 128-byte lines meet in
   // the same L2.
-  col_body<NY, W, OP>(S, xcd_contiguous<true>(blockIdx.x, gridDim.x), lds, twl);
+  col_body<NY, W, OP>(S, xcd_contiguous<true>(blockIdx.x, gridDim.x), lds, twl, qyl);
 }
 
 // ------------------------------------------------------------------ plain path kernels

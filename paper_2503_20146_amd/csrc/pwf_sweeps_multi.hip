@@ -55,19 +55,22 @@ constexpr int kMultiColExchange = cmax(cmax(ColLds<512, multi_w<512>()>::kExchan
                                        ColLds<2048, multi_w<2048>()>::kExchange);
 constexpr int kMultiColTwiddles = cmax(cmax(ColLds<512, multi_w<512>()>::kTwiddles, ColLds<1024, multi_w<1024>()>::kTwiddles),
                                        ColLds<2048, multi_w<2048>()>::kTwiddles);
+constexpr int kMultiYTable = cmax(cmax(ColLds<512, multi_w<512>()>::kYTable, ColLds<1024, multi_w<1024>()>::kYTable),
+                                  ColLds<2048, multi_w<2048>()>::kYTable);
 
 template <int OP>
 __global__ void __launch_bounds__(512, 4) col_sweep_multi(MultiSweep M) {
   __shared__ float2 lds[kMultiColExchange];
   __shared__ float2 twl[kMultiColTwiddles];
+  __shared__ float2 qyl[col_op_chirp(OP) ? kMultiYTable : 1];
   const int b = xcd_contiguous<true>(blockIdx.x, gridDim.x);
   int c = 0;
   while (c + 1 < M.nc && b >= M.first[c + 1]) ++c;
   const int lb = b - M.first[c];
   switch (M.side[c]) {
-    case 512: col_body<512, multi_w<512>(), OP>(M.s[c], lb, lds, twl); break;
-    case 1024: col_body<1024, multi_w<1024>(), OP>(M.s[c], lb, lds, twl); break;
-    case 2048: col_body<2048, multi_w<2048>(), OP>(M.s[c], lb, lds, twl); break;
+    case 512: col_body<512, multi_w<512>(), OP>(M.s[c], lb, lds, twl, qyl); break;
+    case 1024: col_body<1024, multi_w<1024>(), OP>(M.s[c], lb, lds, twl, qyl); break;
+    case 2048: col_body<2048, multi_w<2048>(), OP>(M.s[c], lb, lds, twl, qyl); break;
     default: break;
   }
 }
