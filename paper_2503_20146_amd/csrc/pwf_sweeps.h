@@ -638,6 +638,9 @@ struct ColLds {
 constexpr bool col_op_chirp(int op) {
   return op == COL_CHIRP1 || op == COL_CHIRP1_CONJ || op == COL_CHIRP2 || op == COL_CHIRP2_CONJ;
 }
+// Sweeps that stage their per-ky factor in LDS (ColLds::kYTable entries):
+// the chirp factor, the regulariser window 1 - STF_y (S11), the IOTF (S5).
+constexpr bool col_op_ystage(int op) { return col_op_chirp(op) || op == COL_NESTEROV || op == COL_BLUR_LOSS; }
 
 // Column sweep `OP` on logical block b (instance b / blocks_per_inst) with the
 // caller's LDS (ColLds sizes).
@@ -697,25 +700,32 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
 
   TwStage<TS::kLds, NT> tws;
   if constexpr (TS::kMode != 0) tws.load(TS::staged_from(S.tw_col, S.twn_col));
-  // The chirp sweeps' y factors staged in LDS like the twiddles, instead of
-  // one global load per element (the 16-column chirp sweeps at 1024: 0.636 ->
-  // 0.591 ms).  The factor depends on fy^2, so positions j and mirror_pos(j)
-  // (ky and -ky) share it: the table (the caller's LDS, ColLds::kYTable
-  // entries) holds positions 0 .. NF/2 (4 KB at 1024 points, which still lets
-  // two workgroups share a CU).
-  constexpr bool YSTAGE = col_op_chirp(OP);
+  // The per-ky factor of the Fourier-domain step (chirp y factor; 1 - STF_y
+  // in S11; IOTF_y in S5) staged in LDS like the twiddles, instead of one
+  // global load per element (the 16-column chirp sweeps at 1024: 0.636 ->
+  // 0.591 ms).  The factors depend on fy^2, so positions j and mirror_pos(j)
+  // (ky and -ky) share them: the table (the caller's LDS, ColLds::kYTable
+  // entries; float factors in .x) holds positions 0 .. NF/2 (4 KB at 1024
+  // points, which still lets two workgroups share a CU).
+  constexpr bool YSTAGE = col_op_ystage(OP);
   constexpr int NQ = YSTAGE ? ColLds<NY, W>::kYTable : 1;
   constexpr int KQ = (NQ + NT - 1) / NT;
   float2 qys[YSTAGE ? KQ : 1];
   if constexpr (YSTAGE) {
-    const float2* __restrict__ qsrc = (OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ) ? I.qy1 : I.qy2;
     static_for<0, KQ>([&](auto jj) {
       constexpr int k = decltype(jj)::value;
       const int j = (int)threadIdx.x + k * NT;
       // (half 1 uses positions below NF/2 only: its entry NF/2 would be ky = ny + 1)
-      if (j < NQ && !(part == 1 && j == NF / 2)) qys[k] = gld(qsrc, (uint32_t)ky_of(j));
+      if (j < NQ && !(part == 1 && j == NF / 2)) {
+        const uint32_t ky = (uint32_t)ky_of(j);
+        if constexpr (OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ) qys[k] = gld(I.qy1, ky);
+        else if constexpr (OP == COL_CHIRP2 || OP == COL_CHIRP2_CONJ) qys[k] = gld(I.qy2, ky);
+        else qys[k] = make_float2(gldf(OP == COL_NESTEROV ? I.gy : I.iy, ky), 0.f);
+      }
     });
   }
+  // staged factor of position j: that of min(j, mirror_pos(j))
+  auto ytab = [&](int j) { return qyl[j <= NF / 2 - part ? j : mirror_pos(j)]; };
   float2 v[E];
   static_for<0, E / R1>([&](auto cc) {
     static_for<0, R1>([&](auto qq) {
@@ -776,7 +786,7 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
         const int j = t + T * (e / RL) + (e % RL) * ML;
         zk[e] = gld(z_cur, o_a + (uint32_t)((j - t) * nx));
         zp[slot][u] = gld(z_old, o_a + (uint32_t)((j - t) * nx));
-        gb[slot][u] = gldf(I.gy, ky_of(j));
+        gb[slot][u] = ytab(j).x;
       });
     };
     load_state(std::integral_constant<int, 0>{}, 0);
@@ -866,14 +876,10 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
     constexpr bool CONJ = OP == COL_CHIRP1_CONJ || OP == COL_CHIRP2_CONJ;
     constexpr bool L1 = OP == COL_CHIRP1 || OP == COL_CHIRP1_CONJ;
     if constexpr (CHIRP) {
-      const float2* __restrict__ qy = L1 ? I.qy1 : I.qy2;
       const float two_pi_a = L1 ? I.two_pi_a1 : I.two_pi_a2;
       // the y factors carry the 1/m of the inverse transform
       // y factor of position j (staged: that of min(j, mirror_pos(j)); else from the table)
-      auto qy_at = [&](int j) {
-        if constexpr (YSTAGE) return qyl[j <= NF / 2 - part ? j : mirror_pos(j)];
-        else return gld(qy, (uint32_t)ky_of(j));
-      };
+      auto qy_at = [&](int j) { return ytab(j); };
       if (I.series && I.cross) {
         static_for<0, E>([&](auto ee) {
           constexpr int e = decltype(ee)::value;
@@ -910,7 +916,7 @@ __device__ __forceinline__ void col_body(const Sweep& S, int b, float2* lds, flo
         if constexpr (OP == COL_BLUR) {
           v[e] = cscale(v[e], ixv * gldf(I.iy, ky) * I.inv_m);
         } else if constexpr (OP == COL_BLUR_LOSS) {
-          const float h = ixv * gldf(I.iy, ky);
+          const float h = ixv * ytab(j).x;
           const float2 yh = gld(I.y_hat, o_e);
           const float2 rr = make_float2(h * v[e].x - yh.x, h * v[e].y - yh.y);
           acc += wgt * ((double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y);
@@ -953,7 +959,7 @@ template <int NY, int W, int OP>
 __global__ void __launch_bounds__(ColSweepCfg<NY>::T * W, (col_min_waves<NY, W, OP>())) col_sweep(Sweep S) {
   __shared__ float2 lds[ColLds<NY, W>::kExchange];
   __shared__ float2 twl[ColLds<NY, W>::kTwiddles];
-  __shared__ float2 qyl[col_op_chirp(OP) ? ColLds<NY, W>::kYTable : 1];
+  __shared__ float2 qyl[col_op_ystage(OP) ? ColLds<NY, W>::kYTable : 1];
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous range of tiles so that tiles sharing 128-byte lines meet in
   // the same L2.

@@ -62,7 +62,7 @@ template <int OP>
 __global__ void __launch_bounds__(512, 4) col_sweep_multi(MultiSweep M) {
   __shared__ float2 lds[kMultiColExchange];
   __shared__ float2 twl[kMultiColTwiddles];
-  __shared__ float2 qyl[col_op_chirp(OP) ? kMultiYTable : 1];
+  __shared__ float2 qyl[col_op_ystage(OP) ? kMultiYTable : 1];
   const int b = xcd_contiguous<true>(blockIdx.x, gridDim.x);
   int c = 0;
   while (c + 1 < M.nc && b >= M.first[c + 1]) ++c;
