@@ -291,6 +291,25 @@ def test_correlation_stop_matches_oracle(tol):
     assert np.all(np.abs(hist[0, :k_ref].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
 
 
+# At 512^2 (split column transform; the stopping-rule S0 variant on paired rows)
+# 1 - correlation runs 8.3e-6, 3.8e-6, 2.1e-6, 1.5e-6, 1.2e-6, 9.7e-7, ...: thresholds
+# between neighbours with margins of 1e-7 and more.
+@pytest.mark.parametrize("tol", [1.0 - 3e-6, 1.0 - 1.3e-6])
+def test_correlation_stop_matches_oracle_512(tol):
+    from paper_2503_20146_amd import PWF
+    dev = device()
+    inp, geo, prob, y = instance(0, n=512)
+    say(f"correlation stop {tol} at 512^2")
+    psi_ref, hist_ref, st = O.pwf(y, prob, 60, corr_tol=tol)
+    k_ref = len(hist_ref)
+    batch = PWF([gpu_problem(geo, inp["t"], dev)])
+    out, hist, done = batch.solve([to_dev(y, dev)], 60, corr_tol=tol, return_iters=True)
+    assert 1 <= k_ref < 60
+    assert done[0] == k_ref, (done[0], k_ref)
+    assert _rms(out[0].cpu().numpy(), psi_ref) <= PHASE_TOL
+    assert np.all(np.abs(hist[0, :k_ref].cpu().numpy() - hist_ref) / hist_ref <= loss_history_tolerance(y, hist_ref))
+
+
 def test_correlation_stop_per_instance_in_a_batch():
     """Instances stop independently; stopped ones keep their iterate while others run."""
     import torch
