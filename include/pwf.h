@@ -283,7 +283,7 @@ pwf_status pwf_bench_sweep(const pwf_problem* problems, int32_t n, int32_t sweep
  * those of pwf_forward / pwf_gradient) for grid side n.  Two widths are
  * compiled per side (128: 32/16, 256: 16/32, and over one half of the split
  * column transform of the larger sides (see the state layout above) 512:
- * 16/32, 1024: 16/8, 2048: 8/4); 0 restores the default.  PWF_ERR_SIZE / PWF_ERR_ARG for an
+ * 16/32, 1024: 16/8, 2048: 8/16); 0 restores the default.  PWF_ERR_SIZE / PWF_ERR_ARG for an
  * unsupported side, sweep or width.  Process-wide; applies to calls issued
  * afterwards. */
 pwf_status pwf_set_column_tile(int32_t n, int32_t sweep, int32_t width);
@@ -314,7 +314,7 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
 
 /* Autotuner with a persistent cache: a text file at cache_path (host path,
  * created when missing) keyed by the device's architecture with the library
- * version (e.g. "gfx950/v10300": entries timed on other kernels are not
+ * version (e.g. "gfx950/v10301": entries timed on other kernels are not
  * reused), the batch's class mix (its grid shapes and instance counts) and
  * the grid side, holding
  * that side's column-tile widths (S1..S11) and row plans (S0..S10).  When

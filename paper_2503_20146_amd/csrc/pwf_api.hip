@@ -26,7 +26,7 @@ using pwf::Sweep;
 
 namespace {
 
-constexpr int kVersion = 10300;        // 1.3.0
+constexpr int kVersion = 10301;        // 1.3.1
 constexpr int kBetaCap = 1 << 16;      // iterations covered by the momentum table
 constexpr size_t kAlign = 256;
 constexpr int kSizes[] = {128, 256, 512, 1024, 2048};

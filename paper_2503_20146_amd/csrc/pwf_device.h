@@ -190,11 +190,17 @@ template <int N> constexpr int row_plan_count() { return (N == 1024 || N == 2048
 // Column sweeps: T lanes per column and W adjacent columns per workgroup
 // (lane index = t * W + w, so the W columns of one row are one coalesced
 // segment).  Two tile widths are compiled per side; the launcher picks one.
+// The 1024-point transforms (the halves of 2048-point columns) come in 8 and
+// 16 columns: 16 (147 KB of LDS, one 1024-lane workgroup per CU) covers whole
+// 128-byte lines, which S11 turns into 6% more bandwidth (4.9 against
+// 4.65 TB/s at 180 x 2048^2), while the chirp sweeps keep 8 (4.6 against 3.9:
+// two workgroups per CU overlap one's loads with the other's transform).
+// 4-column tiles (32-byte segments) were slower than 8 everywhere.
 template <int N> struct ColCfg;
 template <> struct ColCfg<128>  { using Plan = FftPlan<128, 16, 8>;      static constexpr int T = 8,   WA = 32, WB = 16; };
 template <> struct ColCfg<256>  { using Plan = FftPlan<256, 16, 16>;     static constexpr int T = 16,  WA = 16, WB = 32; };
 template <> struct ColCfg<512>  { using Plan = FftPlan<512, 16, 8, 4>;   static constexpr int T = 32,  WA = 16, WB = 8; };
-template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  WA = 8,  WB = 4; };
+template <> struct ColCfg<1024> { using Plan = FftPlan<1024, 16, 16, 4>; static constexpr int T = 64,  WA = 8,  WB = 16; };
 template <> struct ColCfg<2048> { using Plan = FftPlan<2048, 16, 16, 8>; static constexpr int T = 128, WA = 4,  WB = 8; };
 
 // Radix-2 split of the column transforms of the sweeps on sides of 512 and

@@ -59,6 +59,7 @@ def test_tuning_settings(lib):
     assert lib.pwf_column_tile(100, 1) == 0 and lib.pwf_column_tile(1024, 2) == 0
     assert lib.pwf_set_column_tile(1024, -1, 3) == -1
     assert lib.pwf_set_column_tile(1024, -1, 4) == -1    # not compiled at 1024 (16 and 8 are)
+    assert lib.pwf_set_column_tile(2048, -1, 4) == -1    # nor at 2048 (8 and 16 are)
     assert lib.pwf_set_column_tile(1024, 4, 8) == -1     # S4 is a row sweep
     assert lib.pwf_set_column_tile(100, -1, 8) == -2
     try:
@@ -66,9 +67,12 @@ def test_tuning_settings(lib):
         assert lib.pwf_column_tile(1024, 11) == 8 and lib.pwf_column_tile(1024, 1) == 16
         assert lib.pwf_set_column_tile(1024, -1, 8) == 0
         assert all(lib.pwf_column_tile(1024, s) == 8 for s in range(1, 12, 2))
+        assert lib.pwf_set_column_tile(2048, 11, 16) == 0
+        assert lib.pwf_column_tile(2048, 11) == 16 and lib.pwf_column_tile(2048, 1) == 8
     finally:
         lib.pwf_set_column_tile(1024, -1, 0)
-    assert lib.pwf_column_tile(1024, 11) == 16
+        lib.pwf_set_column_tile(2048, -1, 0)
+    assert lib.pwf_column_tile(1024, 11) == 16 and lib.pwf_column_tile(2048, 11) == 8
     # built-in plans at 1024: every tunable row sweep on the alternative plan
     assert [lib.pwf_row_plan(1024, s) for s in range(0, 12, 2)] == [1, 1, 1, 1, 1, 1]
     assert [lib.pwf_row_plan(2048, s) for s in range(0, 12, 2)] == [1, 0, 1, 0, 0, 1]

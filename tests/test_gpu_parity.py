@@ -324,7 +324,7 @@ def test_autotune_cache_round_trip(tmp_path):
         reset()
 
 
-ALT_TILE = {128: 16, 256: 32, 512: 32, 1024: 8, 2048: 4}   # the second compiled width per side
+ALT_TILE = {128: 16, 256: 32, 512: 32, 1024: 8, 2048: 16}   # the second compiled width per side
 
 
 @pytest.mark.parametrize("side", [128, 256, 512, 1024, 2048])
