@@ -426,6 +426,31 @@ def uneven_batch(dev, iters: int = 50) -> dict:
     return res
 
 
+def streaming_reference(dev, iter_tbps: float):
+    """Rates of plain streaming kernels (torch's own elementwise kernels over 1 GiB fp32
+    operands, HIP events, 20 launches each) on this GPU: what a kernel that only streams
+    reaches here, beside the published 8 TB/s the roofline fractions are taken against."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, device=dev)
+    c = torch.ones(n, device=dev)
+    b = torch.empty_like(a)
+    out = {}
+    for key, fn, nbytes in (("add_2read_1write_TBps", lambda: torch.add(a, c, out=b), 12 * n),
+                            ("scale_1read_1write_TBps", lambda: torch.mul(a, 2.0, out=b), 8 * n),
+                            ("fill_write_TBps", lambda: b.fill_(2.0), 4 * n),
+                            ("memcpy_d2d_TBps", lambda: b.copy_(a), 8 * n)):
+        fn()
+        torch.cuda.synchronize()
+        sec = time_events(lambda: [fn() for _ in range(20)]) / 20
+        out[key] = round(nbytes / sec / 1e12, 2)
+    del a, b, c
+    torch.cuda.empty_cache()
+    out["iteration_TBps"] = round(iter_tbps, 2)
+    out["iteration_frac_of_add_rate"] = round(iter_tbps / out["add_2read_1write_TBps"], 3)
+    return out
+
+
 def time_events(fn, reps_note=None):
     import torch
     s = torch.cuda.current_stream()
@@ -624,6 +649,10 @@ def main() -> int:
         print(f"[bench] plain {pv:.1f} proj-iter/s", file=sys.stderr, flush=True)
 
     extras = None if args.no_extras else secondary_measurements(batch, ys, out, probs, geo, d_inputs, dev)
+    if extras is not None:
+        iter_tbps = value * ITER_BYTES_PER_PX * geo.nx * geo.ny / 1e12
+        extras["streaming_reference"] = streaming_reference(dev, iter_tbps)
+        print(f"[bench] streaming reference {extras['streaming_reference']}", file=sys.stderr, flush=True)
     del batch, ys, out, hist
     torch.cuda.empty_cache()
     if extras is not None:
