@@ -150,32 +150,86 @@ __global__ void fsc_part_kernel(const float2* __restrict__ src, int part, float2
 }
 
 // Shell sums of Re(G1* G2), |G1|^2, |G2|^2 over kappa = round(|k|) (signed
-// index frequencies of an n^dims grid), kappa <= n/2.  Each workgroup sums its
-// grid-stride share into LDS (FP64 atomics: summation order within a
-// workgroup is not fixed) and writes one row of partials.
-__global__ void __launch_bounds__(256) fsc_shell_kernel(const float2* __restrict__ g1, const float2* __restrict__ g2,
-                                                        int n, int dims, double* __restrict__ partial) {
+// index frequencies of an n^dims grid), kappa <= n/2, in a fixed order (the
+// result is bit-reproducible).  Every wave owns a private histogram of the
+// three sums in LDS and walks its share of the grid in chunks of 64
+// consecutive elements.  A chunk lies in one half of one x row (64 divides
+// n/2), where kappa is monotone in kx, so lanes of equal kappa are contiguous:
+// a segmented suffix sum over the wave (a fixed butterfly order) leaves each
+// segment's total in its first lane, and those lanes, whose kappa differ, add
+// it to the wave's histogram.  The workgroup then adds its waves' histograms
+// in wave order and writes one row of partials.  Four waves per workgroup up
+// to n = 1024 and two at 2048 keep the histograms at 49 KB of LDS.
+constexpr int kFscThreads = 256;
+
+__global__ void __launch_bounds__(kFscThreads) fsc_shell_kernel(const float2* __restrict__ g1,
+                                                                const float2* __restrict__ g2, int n, int dims,
+                                                                double* __restrict__ partial) {
   extern __shared__ double sh[];
   const int nsh = n / 2 + 1;
-  for (int i = threadIdx.x; i < 3 * nsh; i += blockDim.x) sh[i] = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  for (int i = threadIdx.x; i < waves * 3 * nsh; i += blockDim.x) sh[i] = 0.0;
   __syncthreads();
+  double* h = sh + wave * 3 * nsh;
   const size_t m = dims == 3 ? (size_t)n * n * n : (size_t)n * n;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
-    const int kx = (int)(i % n);
-    const int ky = (int)((i / n) % n);
-    const int kz = dims == 3 ? (int)(i / ((size_t)n * n)) : 0;
+  const size_t chunks = m / 64;
+  const size_t stride = (size_t)gridDim.x * waves;
+  const int lg = 31 - __clz(n);  // n is a power of two
+  // shell of this lane's element in chunk c (nsh: outside the last shell)
+  auto shell_of = [&](size_t c) -> int {
+    const size_t e0 = c << 6;
+    const size_t row = e0 >> lg;
+    const int kx = (int)(e0 & (size_t)(n - 1)) + lane;
+    const int ky = (int)(row & (size_t)(n - 1));
+    const int kz = (int)(row >> lg);  // 0 in 2-D
     const float fx = (float)(kx < n / 2 ? kx : kx - n);
     const float fy = (float)(ky < n / 2 ? ky : ky - n);
     const float fz = (float)(kz < n / 2 ? kz : kz - n);
-    const int s = (int)rintf(sqrtf(fx * fx + fy * fy + fz * fz));
-    if (s >= nsh) continue;
-    const float2 a = g1[i], b = g2[i];
-    atomicAdd(&sh[s], (double)a.x * b.x + (double)a.y * b.y);
-    atomicAdd(&sh[nsh + s], (double)a.x * a.x + (double)a.y * a.y);
-    atomicAdd(&sh[2 * nsh + s], (double)b.x * b.x + (double)b.y * b.y);
+    const int k = (int)rintf(sqrtf(fx * fx + fy * fy + fz * fz));
+    return k < nsh ? k : nsh;
+  };
+  auto accumulate = [&](int s, float2 a, float2 b) {
+    double v0 = (double)a.x * b.x + (double)a.y * b.y;
+    double v1 = (double)a.x * a.x + (double)a.y * a.y;
+    double v2 = (double)b.x * b.x + (double)b.y * b.y;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int sd = __shfl_down(s, d, 64);
+      const double u0 = __shfl_down(v0, d, 64);
+      const double u1 = __shfl_down(v1, d, 64);
+      const double u2 = __shfl_down(v2, d, 64);
+      if (lane + d < 64 && sd == s) {
+        v0 += u0;
+        v1 += u1;
+        v2 += u2;
+      }
+    }
+    const int sp = __shfl_up(s, 1, 64);
+    if ((lane == 0 || sp != s) && s < nsh) {
+      h[s] += v0;
+      h[nsh + s] += v1;
+      h[2 * nsh + s] += v2;
+    }
+  };
+  // two chunks per step, both chunks' loads issued before either is reduced
+  // (the chunks are still reduced in the order c, c + stride, c + 2 stride, ...)
+  const float2 zero = make_float2(0.f, 0.f);
+  for (size_t c = (size_t)blockIdx.x * waves + wave; c < chunks; c += 2 * stride) {
+    const size_t c2 = c + stride;
+    const int s1 = shell_of(c);
+    const int s2 = c2 < chunks ? shell_of(c2) : nsh;
+    const size_t i1 = (c << 6) + lane, i2 = (c2 << 6) + lane;
+    const float2 a1 = s1 < nsh ? g1[i1] : zero, b1 = s1 < nsh ? g2[i1] : zero;
+    const float2 a2 = s2 < nsh ? g1[i2] : zero, b2 = s2 < nsh ? g2[i2] : zero;
+    accumulate(s1, a1, b1);
+    if (c2 < chunks) accumulate(s2, a2, b2);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 3 * nsh; i += blockDim.x) partial[(size_t)blockIdx.x * 3 * nsh + i] = sh[i];
+  for (int i = threadIdx.x; i < 3 * nsh; i += blockDim.x) {
+    double t = sh[i];
+    for (int w = 1; w < waves; ++w) t += sh[w * 3 * nsh + i];
+    partial[(size_t)blockIdx.x * 3 * nsh + i] = t;
+  }
 }
 
 __global__ void fsc_final_kernel(const double* __restrict__ partial, int blocks, int len, double* __restrict__ out) {
@@ -186,7 +240,8 @@ __global__ void fsc_final_kernel(const double* __restrict__ partial, int blocks,
   }
 }
 
-int fsc_blocks() { return 1024; }
+// three 49 KB workgroups per CU: one round over the 256 CUs
+int fsc_blocks() { return 768; }
 
 hipError_t launch_fsc_part(const float2* src, int part, float2* dst, size_t m, hipStream_t st) {
   hipLaunchKernelGGL(fsc_part_kernel, dim3(4096), dim3(256), 0, st, src, part, dst, m);
@@ -196,8 +251,9 @@ hipError_t launch_fsc_part(const float2* src, int part, float2* dst, size_t m, h
 hipError_t launch_fsc_shells(const float2* g1, const float2* g2, int n, int dims, double* partial, double* out,
                              hipStream_t st) {
   const int nsh = n / 2 + 1;
-  hipLaunchKernelGGL(fsc_shell_kernel, dim3(fsc_blocks()), dim3(256), sizeof(double) * 3 * nsh, st, g1, g2, n, dims,
-                     partial);
+  const int threads = n > 1024 ? kFscThreads / 2 : kFscThreads;
+  hipLaunchKernelGGL(fsc_shell_kernel, dim3(fsc_blocks()), dim3(threads), sizeof(double) * (threads / 64) * 3 * nsh,
+                     st, g1, g2, n, dims, partial);
   hipLaunchKernelGGL(fsc_final_kernel, dim3((3 * nsh + 255) / 256), dim3(256), 0, st, partial, fsc_blocks(),
                      3 * nsh, out);
   return hipGetLastError();
