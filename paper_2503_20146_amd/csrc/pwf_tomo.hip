@@ -152,16 +152,30 @@ __global__ void fsc_part_kernel(const float2* __restrict__ src, int part, float2
 // Shell sums of Re(G1* G2), |G1|^2, |G2|^2 over kappa = round(|k|) (signed
 // index frequencies of an n^dims grid), kappa <= n/2, in a fixed order (the
 // result is bit-reproducible).  Every wave owns a private histogram of the
-// three sums in LDS and walks its share of the grid in chunks of 64
-// consecutive elements.  A chunk lies in one half of one x row (64 divides
-// n/2), where kappa is monotone in kx, so lanes of equal kappa are contiguous:
-// a segmented suffix sum over the wave (a fixed butterfly order) leaves each
-// segment's total in its first lane, and those lanes, whose kappa differ, add
-// it to the wave's histogram.  The workgroup then adds its waves' histograms
-// in wave order and writes one row of partials.  Four waves per workgroup up
-// to n = 1024 and two at 2048 keep the histograms at 49 KB of LDS.
+// three sums in LDS and walks its share of the grid in chunks of 64 K
+// consecutive elements, K per lane.  A chunk lies in one half of one x row
+// (64 K divides n/2), where kappa is monotone in kx, so equal kappa form runs
+// of consecutive elements:
+//  * each lane sums its own K elements run by run; a run that starts and ends
+//    inside the lane is complete and goes to the histogram at once (no other
+//    lane holds that kappa);
+//  * the lane's first and last runs may continue runs of its neighbours.  A
+//    lane whose K elements are one run passes the sum arriving from the left
+//    on (when kappa matches) plus its own; any other lane starts afresh with
+//    its last run.  That is the map x -> A x + B per lane (A = 1 for a
+//    continuing single-run lane, else 0), composed over the wave by an
+//    inclusive scan in a fixed butterfly order;
+//  * a lane with several runs adds the sum arriving from the left to its first
+//    run and writes that; a lane whose last run the next lane does not
+//    continue writes its scan value.
+// The kappa written by the lanes of one store are distinct, so no two lanes
+// of a wave touch one entry at once, and the stores follow program order.
+// The workgroup then adds its waves' histograms in wave order and writes one
+// row of partials.  Four waves per workgroup up to n = 1024 and two at 2048
+// keep the histograms at 49 KB of LDS.
 constexpr int kFscThreads = 256;
 
+template <int K>
 __global__ void __launch_bounds__(kFscThreads) fsc_shell_kernel(const float2* __restrict__ g1,
                                                                 const float2* __restrict__ g2, int n, int dims,
                                                                 double* __restrict__ partial) {
@@ -172,57 +186,99 @@ __global__ void __launch_bounds__(kFscThreads) fsc_shell_kernel(const float2* __
   __syncthreads();
   double* h = sh + wave * 3 * nsh;
   const size_t m = dims == 3 ? (size_t)n * n * n : (size_t)n * n;
-  const size_t chunks = m / 64;
+  const size_t chunks = m / (64 * K);
   const size_t stride = (size_t)gridDim.x * waves;
   const int lg = 31 - __clz(n);  // n is a power of two
-  // shell of this lane's element in chunk c (nsh: outside the last shell)
-  auto shell_of = [&](size_t c) -> int {
-    const size_t e0 = c << 6;
+  auto put = [&](int k, double x0, double x1, double x2) {
+    if (k < nsh) {
+      h[k] += x0;
+      h[nsh + k] += x1;
+      h[2 * nsh + k] += x2;
+    }
+  };
+  for (size_t c = (size_t)blockIdx.x * waves + wave; c < chunks; c += stride) {
+    const size_t e0 = c * (64 * K) + (size_t)lane * K;  // this lane's first element
     const size_t row = e0 >> lg;
-    const int kx = (int)(e0 & (size_t)(n - 1)) + lane;
+    const int kx0 = (int)(e0 & (size_t)(n - 1));
     const int ky = (int)(row & (size_t)(n - 1));
     const int kz = (int)(row >> lg);  // 0 in 2-D
-    const float fx = (float)(kx < n / 2 ? kx : kx - n);
     const float fy = (float)(ky < n / 2 ? ky : ky - n);
     const float fz = (float)(kz < n / 2 ? kz : kz - n);
-    const int k = (int)rintf(sqrtf(fx * fx + fy * fy + fz * fz));
-    return k < nsh ? k : nsh;
-  };
-  auto accumulate = [&](int s, float2 a, float2 b) {
-    double v0 = (double)a.x * b.x + (double)a.y * b.y;
-    double v1 = (double)a.x * a.x + (double)a.y * a.y;
-    double v2 = (double)b.x * b.x + (double)b.y * b.y;
+    const float r2 = fy * fy + fz * fz;
+    int sk[K];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int sd = __shfl_down(s, d, 64);
-      const double u0 = __shfl_down(v0, d, 64);
-      const double u1 = __shfl_down(v1, d, 64);
-      const double u2 = __shfl_down(v2, d, 64);
-      if (lane + d < 64 && sd == s) {
-        v0 += u0;
-        v1 += u1;
-        v2 += u2;
+    for (int j = 0; j < K; ++j) {
+      const int kx = kx0 + j;
+      const float fx = (float)(kx < n / 2 ? kx : kx - n);
+      const int k = (int)rintf(sqrtf(fx * fx + r2));
+      sk[j] = k < nsh ? k : nsh;  // nsh: outside the last shell
+    }
+    // kappa is monotone over the lane's elements: one inside means an end is
+    float2 a[K], b[K];
+    const bool any_in = sk[0] < nsh || sk[K - 1] < nsh;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      a[j] = any_in ? g1[e0 + j] : make_float2(0.f, 0.f);
+      b[j] = any_in ? g2[e0 + j] : make_float2(0.f, 0.f);
+    }
+    // runs inside the lane: f = first run, q = current run
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    int sf = sk[0], sq = sk[0];
+    bool multi = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double v0 = (double)a[j].x * b[j].x + (double)a[j].y * b[j].y;
+      double v1 = (double)a[j].x * a[j].x + (double)a[j].y * a[j].y;
+      double v2 = (double)b[j].x * b[j].x + (double)b[j].y * b[j].y;
+      if (sk[j] == nsh) v0 = v1 = v2 = 0.0;
+      if (j == 0) {
+        f0 = v0;
+        f1 = v1;
+        f2 = v2;
+      } else if (sk[j] == sq) {
+        if (multi) {
+          q0 += v0;
+          q1 += v1;
+          q2 += v2;
+        } else {
+          f0 += v0;
+          f1 += v1;
+          f2 += v2;
+        }
+      } else {
+        if (multi) put(sq, q0, q1, q2);  // a run inside the lane is complete
+        multi = true;
+        sq = sk[j];
+        q0 = v0;
+        q1 = v1;
+        q2 = v2;
       }
     }
-    const int sp = __shfl_up(s, 1, 64);
-    if ((lane == 0 || sp != s) && s < nsh) {
-      h[s] += v0;
-      h[nsh + s] += v1;
-      h[2 * nsh + s] += v2;
+    const int sl = multi ? sq : sf;  // kappa of the lane's last run
+    const int sl_prev = __shfl_up(sl, 1, 64);
+    const bool join = lane > 0 && sl_prev == sf;
+    int A = !multi && join ? 1 : 0;
+    double B0 = multi ? q0 : f0, B1 = multi ? q1 : f1, B2 = multi ? q2 : f2;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int Ap = __shfl_up(A, d, 64);
+      const double P0 = __shfl_up(B0, d, 64);
+      const double P1 = __shfl_up(B1, d, 64);
+      const double P2 = __shfl_up(B2, d, 64);
+      if (lane >= d) {
+        if (A) {
+          B0 += P0;
+          B1 += P1;
+          B2 += P2;
+        }
+        A &= Ap;
+      }
     }
-  };
-  // two chunks per step, both chunks' loads issued before either is reduced
-  // (the chunks are still reduced in the order c, c + stride, c + 2 stride, ...)
-  const float2 zero = make_float2(0.f, 0.f);
-  for (size_t c = (size_t)blockIdx.x * waves + wave; c < chunks; c += 2 * stride) {
-    const size_t c2 = c + stride;
-    const int s1 = shell_of(c);
-    const int s2 = c2 < chunks ? shell_of(c2) : nsh;
-    const size_t i1 = (c << 6) + lane, i2 = (c2 << 6) + lane;
-    const float2 a1 = s1 < nsh ? g1[i1] : zero, b1 = s1 < nsh ? g2[i1] : zero;
-    const float2 a2 = s2 < nsh ? g1[i2] : zero, b2 = s2 < nsh ? g2[i2] : zero;
-    accumulate(s1, a1, b1);
-    if (c2 < chunks) accumulate(s2, a2, b2);
+    // B is now the sum of this lane's last run and the run it continues
+    const double in0 = __shfl_up(B0, 1, 64), in1 = __shfl_up(B1, 1, 64), in2 = __shfl_up(B2, 1, 64);
+    if (multi) put(sf, join ? f0 + in0 : f0, join ? f1 + in1 : f1, join ? f2 + in2 : f2);
+    const int sf_next = __shfl_down(sf, 1, 64);
+    if (!(lane < 63 && sf_next == sl)) put(sl, B0, B1, B2);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 3 * nsh; i += blockDim.x) {
@@ -252,8 +308,12 @@ hipError_t launch_fsc_shells(const float2* g1, const float2* g2, int n, int dims
                              hipStream_t st) {
   const int nsh = n / 2 + 1;
   const int threads = n > 1024 ? kFscThreads / 2 : kFscThreads;
-  hipLaunchKernelGGL(fsc_shell_kernel, dim3(fsc_blocks()), dim3(threads), sizeof(double) * (threads / 64) * 3 * nsh,
-                     st, g1, g2, n, dims, partial);
+  const size_t lds = sizeof(double) * (threads / 64) * 3 * nsh;
+  // four elements per lane where 256 divides n/2, else one (64 divides n/2 from n = 128)
+  if (n >= 512)
+    hipLaunchKernelGGL(fsc_shell_kernel<4>, dim3(fsc_blocks()), dim3(threads), lds, st, g1, g2, n, dims, partial);
+  else
+    hipLaunchKernelGGL(fsc_shell_kernel<1>, dim3(fsc_blocks()), dim3(threads), lds, st, g1, g2, n, dims, partial);
   hipLaunchKernelGGL(fsc_final_kernel, dim3((3 * nsh + 255) / 256), dim3(256), 0, st, partial, fsc_blocks(),
                      3 * nsh, out);
   return hipGetLastError();

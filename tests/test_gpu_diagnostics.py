@@ -27,7 +27,7 @@ def test_rmse_image_matches_oracle(workload, frac):
     assert rel(img[0].cpu().numpy(), ref) <= 1e-5 * np.linalg.norm(f) / np.linalg.norm(y - f)
 
 
-@pytest.mark.parametrize("n,dims", [(128, 3), (256, 2), (2048, 2)])
+@pytest.mark.parametrize("n,dims", [(128, 3), (256, 2), (512, 2), (2048, 2)])
 def test_shell_correlation_matches_oracle(n, dims):
     """FP32 transforms against FP64: the shell correlations agree to 1e-5; the
     shell sums run in a fixed order, so a second call gives the same bits (2048:
