@@ -137,8 +137,10 @@ def _read_counter_csv(path: str, counter: str):
     return {k: sum(v) / len(v) for k, v in per_kernel.items()}, calib
 
 
-def ingest_counters(fetch_csv: str, write_csv: str, projections: int) -> int:
-    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the copy-kernel calibration."""
+def ingest_counters(fetch_csv: str, write_csv: str, projections: int, side: int = 1024) -> int:
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the copy-kernel calibration.  The
+    1024^2 run goes to profiles/traffic_counters.json (the bench's roofline.traffic), other
+    sides to profiles/traffic_counters_<side>.json (documentation only)."""
     fetch, copy_f = _read_counter_csv(fetch_csv, "FETCH_SIZE")
     write, copy_w = _read_counter_csv(write_csv, "WRITE_SIZE")
     if copy_f <= 0 or copy_w <= 0:
@@ -148,11 +150,12 @@ def ingest_counters(fetch_csv: str, write_csv: str, projections: int) -> int:
     kib = COPY_BYTES / 1024.0
     f_scale = kib / copy_f
     w_scale = kib / copy_w
-    pixels = projections * 1024 * 1024
-    out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES,
+    pixels = projections * side * side
+    out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES, "side": side,
            "fetch_scale": f_scale, "write_scale": w_scale, "pixels_per_launch": pixels, "sweeps": {}}
     for s, frag in enumerate(SWEEP_KERNELS):
-        for w in (4, 8, 16):
+        frag = frag.replace("<1024,", f"<{side},")
+        for w in (4, 8, 16, 32):
             names = [k for k in fetch if frag.format(w=w) in k]
             if not names:
                 continue
@@ -163,10 +166,50 @@ def ingest_counters(fetch_csv: str, write_csv: str, projections: int) -> int:
             out["sweeps"][key] = {"kernel": name, "fetch_bytes": fb, "write_bytes": wb,
                                   "hbm_bytes_per_px": (fb + wb) / pixels,
                                   "algorithmic_bytes_per_px": SWEEP_BYTES_PER_PX[s]}
-    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    name = "traffic_counters.json" if side == 1024 else f"traffic_counters_{side}.json"
+    path = os.path.join(ROOT, "profiles", name)
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
+    return 0
+
+
+# column-tile widths compiled per side (the default first)
+COL_WIDTHS = {128: (32, 16), 256: (16, 32), 512: (16, 32), 1024: (16, 8), 2048: (8, 16)}
+
+
+def sweep_only_side(side: int, n: int, which: str, reps: int, dev) -> int:
+    """Counter runs at a side other than 1024: a batch of n instances of side^2 (the shared
+    diffuser a seeded random phase screen, flat intensities: the sweeps' traffic does not
+    depend on the values), a 2-iteration solve, the calibration copy, then every sweep
+    `reps` times at each compiled column-tile width and the built-in row plans."""
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    from paper_2503_20146_amd import PWF, _lib, problem_from_geometry
+    geo = S.Geometry(ny=side, nx=side, sigma_x_px=1.5, sigma_y_px=1.5)
+    rng = np.random.default_rng(S.BASE_SEED + side)
+    t = torch.from_numpy(np.exp(1j * rng.uniform(0.0, 3.0, (side, side))).astype(np.complex64)).to(dev)
+    batch = PWF([problem_from_geometry(geo, t) for _ in range(n)])
+    ys = [torch.full((side, side), 0.9, device=dev) for _ in range(n)]
+    batch.solve(ys, 2)
+    torch.cuda.synchronize()
+    sweeps = range(12) if which == "all" else [int(which)]
+    if which == "all":
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    lib = _lib.load()
+    for w in COL_WIDTHS[side]:
+        _lib.check(lib.pwf_set_column_tile(side, -1, w), "pwf_set_column_tile")
+        for sw in sweeps:
+            batch.bench_sweep(sw, reps)
+        torch.cuda.synchronize()
+    lib.pwf_set_column_tile(side, -1, 0)
+    print(f"[bench] {n} x {side}^2: sweeps {list(sweeps)} x {reps} done", file=sys.stderr, flush=True)
     return 0
 
 
@@ -523,6 +566,9 @@ def main() -> int:
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output (counter_collection.csv or "
                          "the rocpd .db) of a --sweep-only all run "
                          "into profiles/traffic_counters.json and exit")
+    ap.add_argument("--side", type=int, default=1024,
+                    help="grid side of --sweep-only / --ingest-counters runs (1024: the headline batch; "
+                         "others: --projections synthetic instances of that side)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--retune", action="store_true",
                     help="time every tile width and row plan again and rewrite the tuning cache's entries")
@@ -540,7 +586,7 @@ def main() -> int:
     if args.tuning_cache:
         TUNING_CACHE = args.tuning_cache
     if args.ingest_counters:
-        return ingest_counters(*args.ingest_counters, projections=args.projections)
+        return ingest_counters(*args.ingest_counters, projections=args.projections, side=args.side)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -556,6 +602,11 @@ def main() -> int:
     if args.workload == "uneven":
         print(json.dumps(uneven_batch(dev, args.iters)), flush=True)
         return 0
+    if args.sweep_only is not None and args.side != 1024:
+        if args.side not in COL_WIDTHS:
+            print(f"bench.py: --side {args.side} is not a supported grid side", file=sys.stderr)
+            return 2
+        return sweep_only_side(args.side, args.projections, args.sweep_only, args.sweep_reps, dev)
     print(f"[bench] building workload: {args.projections} x 1024^2", file=sys.stderr, flush=True)
     batch, ys, geo, probs, d_inputs = build_workload(args.projections, dev)
     pixels = args.projections * geo.nx * geo.ny

@@ -45,3 +45,25 @@ def test_counter_calibration_and_staleness(tmp_path, monkeypatch):
     assert abs(bench.measured_traffic(11, px, 8) - 56.0 * px) < 1e-3
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h2")      # the sweep sources changed
     assert bench.measured_traffic(11, px, 8) is None
+
+
+def test_counter_ingest_at_another_side(tmp_path, monkeypatch):
+    """A --side 2048 counter run goes to its own file, keyed by the 2048 kernels, and
+    leaves the 1024^2 record (the bench's roofline.traffic) alone."""
+    os.makedirs(tmp_path / "profiles")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h1")
+    px = 4 * 2048 * 2048
+    copy_kib = bench.COPY_BYTES / 1024.0
+    chirp = "void pwf::col_sweep<2048, 8, 0>(pwf::Sweep)"
+    other = "void pwf::col_sweep<1024, 8, 0>(pwf::Sweep)"
+    _csv(tmp_path / "f.csv", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", copy_kib / 2), (chirp, 8.0 * px / 1024 / 2),
+                                            (other, 1.0)])
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", copy_kib), (chirp, 8.5 * px / 1024),
+                                            (other, 1.0)])
+    assert bench.ingest_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 4, side=2048) == 0
+    assert not os.path.exists(tmp_path / "profiles" / "traffic_counters.json")
+    rec = json.load(open(tmp_path / "profiles" / "traffic_counters_2048.json"))
+    assert rec["side"] == 2048 and set(rec["sweeps"]) == {"1:8"}
+    assert abs(rec["sweeps"]["1:8"]["hbm_bytes_per_px"] - 16.5) < 1e-9
+    assert bench.measured_traffic(1, px, 8) is None
