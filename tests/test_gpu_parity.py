@@ -489,6 +489,38 @@ def test_mixed_sizes_in_one_batch():
         assert np.sqrt(np.mean(np.abs(out[i].cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL
 
 
+def test_zero_and_one_iterations():
+    """Algorithm S1 starts from psi = 0: a solve of 0 iterations returns that start exactly
+    (on a batch of two sizes, so the per-class path and the final inverse transform run),
+    and one iteration matches the oracle's first iterate."""
+    import torch
+    dev = device()
+    say("0 and 1 iterations on 512 / 128")
+    specs = [(512, 512, 1.1), (128, 128, 0.6)]
+    probs, ys, refs = [], [], []
+    for k, (ny, nx, sig) in enumerate(specs):
+        rng = np.random.default_rng(300 + k)
+        geo = S.Geometry(ny=ny, nx=nx, sigma_x_px=sig, sigma_y_px=sig)
+        t = S.diffuser(rng, ny, nx)
+        psi_true = S.phase_object(rng, ny, nx, 4.0, 2.0)
+        prob = O.make_problem(t, geo)
+        f, _, _ = O.physical_model(psi_true, prob)
+        y = S.poisson_intensity(f, (9, k))
+        probs.append(gpu_problem(geo, t, dev))
+        ys.append(to_dev(y, dev))
+        refs.append((prob, y))
+    batch = _pwf(probs)
+    out, _ = batch.solve(ys, 0, loss_hist=False)
+    for o in out:
+        assert int(torch.count_nonzero(o)) == 0
+    out, hist = batch.solve(ys, 1)
+    for i in range(2):
+        psi_ref, hist_ref, _ = O.pwf(refs[i][1], refs[i][0], 1)
+        assert np.sqrt(np.mean(np.abs(out[i].cpu().numpy() - psi_ref) ** 2)) <= PHASE_TOL
+        tol = loss_history_tolerance(refs[i][1], hist_ref[:1])[0]
+        assert abs(float(hist[i, 0]) - hist_ref[0]) <= tol * hist_ref[0]
+
+
 @pytest.mark.parametrize("ny,nx", [(512, 256), (1024, 128)])
 def test_solve_nonsquare_split_matches_oracle(ny, nx):
     """Split column transform (ny >= 512) with rows shorter than 64 lanes per
