@@ -358,22 +358,37 @@ __device__ __forceinline__ void unscramble(float2 (&v)[E]) {
   });
 }
 
+// Order a pass's LDS stores before the next pass's loads.  WAVE: the
+// transform's lanes (and the LDS region they exchange through) belong to one
+// wave, whose LDS operations complete in issue order, so a compiler fence at
+// wavefront scope suffices; otherwise a workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Forward transform: registers in "first-radix layout" (v[c*R0 + q] = x[t + T c
 // + q N/R0]) -> registers in "last-radix layout" (v[c*RL + r] = X[t + T c + r
 // N/RL]).  The LDS region must be free on entry; it is free again on exit
 // (a trailing barrier is issued only between passes).
-template <class Plan, int T, int E, class TW>
+template <class Plan, int T, bool WAVE = false, int E, class TW>
 __device__ __forceinline__ void fft_forward(float2 (&v)[E], int t, const TW& tw, LdsView lds) {
   static_for<0, Plan::NPASS>([&](auto pp) {
     constexpr int P = decltype(pp)::value;
     if constexpr (P > 0) {
       pass_load_lds<Plan, P, T>(v, t, lds);
-      __syncthreads();
+      exchange_sync<WAVE>();
     }
     pass_compute<Plan, P, T, -1>(v, t, tw);
     if constexpr (P + 1 < Plan::NPASS) {
       pass_store_lds<Plan, P, T>(v, t, lds);
-      __syncthreads();
+      exchange_sync<WAVE>();
     }
   });
   unscramble<Plan::radix[Plan::NPASS - 1]>(v);
@@ -429,19 +444,19 @@ struct TwSel {
 
 // Inverse transform: registers in last-radix layout of Plan -> registers in
 // first-radix layout of Plan.  `twr` gives the twiddles of the reversed plan.
-template <class Plan, int T, int E, class TW>
+template <class Plan, int T, bool WAVE = false, int E, class TW>
 __device__ __forceinline__ void fft_inverse(float2 (&v)[E], int t, const TW& twr, LdsView lds) {
   using RP = typename Reverse<Plan>::type;
   static_for<0, RP::NPASS>([&](auto pp) {
     constexpr int P = decltype(pp)::value;
     if constexpr (P > 0) {
       pass_load_lds<RP, P, T>(v, t, lds);
-      __syncthreads();
+      exchange_sync<WAVE>();
     }
     pass_compute<RP, P, T, +1>(v, t, twr);
     if constexpr (P + 1 < RP::NPASS) {
       pass_store_lds<RP, P, T>(v, t, lds);
-      __syncthreads();
+      exchange_sync<WAVE>();
     }
   });
   unscramble<RP::radix[RP::NPASS - 1]>(v);

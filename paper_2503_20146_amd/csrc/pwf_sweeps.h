@@ -283,8 +283,15 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
   // LDS exchange orders these writes before the first use.
   TwStage<TS::kLds, row_threads<NX, PLAN>()> tws;
   if constexpr (TS::kMode != 0) tws.load(TS::staged_from(twg, S.twn_row));
+  // The transforms of a row (or of a pair of rows) whose lanes lie in one wave
+  // order their LDS exchanges per wave; the staged twiddles, which every wave
+  // reads, then need a workgroup barrier of their own.
+  constexpr bool WAVE = PAIR ? 2 * T <= 64 : T <= 64;
   auto load_twiddles = [&]() {
-    if constexpr (TS::kMode != 0) tws.store(twl);
+    if constexpr (TS::kMode != 0) {
+      tws.store(twl);
+      if constexpr (WAVE) __syncthreads();
+    }
   };
 
   // Side input of the real-space step (t, v or x at this row), loaded after
@@ -348,7 +355,7 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
       // (issued after the side loads, whose latency then overlaps the wait)
       if constexpr (PAIR) split_elements<false, PD, E>(v, wp, pb, [](auto i) { return decltype(i)::value; });
     }
-    fft_inverse<Plan, T>(v, t, twr, lv);
+    fft_inverse<Plan, T, WAVE>(v, t, twr, lv);
   } else if constexpr (OP == ROW_REAL_FFT) {
     static_for<0, E / R1>([&](auto cc) {
       static_for<0, R1>([&](auto qq) {
@@ -482,7 +489,7 @@ __device__ __forceinline__ void row_body(const Sweep& S, int b, float2* lds, flo
   });
 
   if constexpr (OUT_FREQ) {
-    fft_forward<Plan, T>(v, t, tw, lv);
+    fft_forward<Plan, T, WAVE>(v, t, tw, lv);
     if constexpr (OP == ROW_INTENSITY || OP == ROW_REAL_FFT) {
       // spectrum of a real row in half form (see col_op_half); lane 0 holds
       // kx = 0 in v[0] and kx = nx/2 in v[RL/2].  Element (c, r) has kx < nx/2
