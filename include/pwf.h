@@ -315,8 +315,10 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
 /* Autotuner with a persistent cache: a text file at cache_path (host path,
  * created when missing) keyed by the device's architecture with the library
  * version (e.g. "gfx950/v10301": entries timed on other kernels are not
- * reused), the batch's class mix (its grid shapes and instance counts) and
- * the grid side, holding
+ * reused), the batch's class mix (its grid shapes and instance counts,
+ * marked "/merged" when pwf_set_merged_launch(1) makes the batch launch
+ * merged: the tuner then picks among what the merged kernels hold) and the
+ * grid side, holding
  * that side's column-tile widths (S1..S11) and row plans (S0..S10).  When
  * every side of the batch has an entry for this architecture and mix, the
  * stored choices are applied and nothing is timed (*tuned = 0, tuned may be

@@ -1507,13 +1507,16 @@ std::string device_arch() {
   return (colon == std::string::npos ? a : a.substr(0, colon)) + "/v" + std::to_string(kVersion);
 }
 
+// Tuning-cache key of a batch: its class mix, marked "/merged" when the batch
+// launches merged (the tuner then chooses only among the plans and widths the
+// merged kernels hold, so those choices are kept apart from per-class ones).
 std::string class_mix(const Batch& B) {
   std::string m;
   for (const Class& c : B.classes) {
     if (!m.empty()) m += '+';
     m += std::to_string(c.nx) + 'x' + std::to_string(c.ny) + '*' + std::to_string(c.count);
   }
-  return m;
+  return batch_merged(B) ? m + "/merged" : m;
 }
 
 std::vector<int> batch_sides(const Batch& B) {
@@ -1568,7 +1571,11 @@ pwf_status pwf_autotune_cached(const pwf_problem* problems, int32_t n, int32_t r
   if (!cache_path || reps < 1) return PWF_ERR_ARG;
   const Batch B = group(problems, n);
   const std::vector<int> sides = batch_sides(B);
-  const std::string mix = class_mix(B);
+  std::string mix;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);  // (the merge mode is read under the lock)
+    mix = class_mix(B);
+  }
   std::vector<std::string> lines;
   {
     std::ifstream in(cache_path);

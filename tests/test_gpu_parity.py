@@ -324,6 +324,48 @@ def test_autotune_cache_round_trip(tmp_path):
         reset()
 
 
+def test_autotune_cache_keeps_merged_choices_apart(tmp_path):
+    """A batch tuned for merged launches gets entries of its own (key marked /merged) with
+    the widths and plans the merged kernels hold, beside its per-class entries."""
+    from paper_2503_20146_amd import _lib, set_column_tile, set_merged_launch, set_row_plan
+    dev = device()
+    lib = _lib.load()
+    say("autotune cache: per-class and merged entries of a 512 + 1024 batch")
+    probs = []
+    for k, side in enumerate((512, 1024)):
+        rng = np.random.default_rng(500 + k)
+        geo = S.Geometry(ny=side, nx=side, sigma_x_px=1.0, sigma_y_px=1.0)
+        probs.append(gpu_problem(geo, S.diffuser(rng, side, side), dev))
+    batch = _pwf(probs)
+    path = tmp_path / "tuning.txt"
+
+    def reset():
+        for n in (512, 1024):
+            set_column_tile(n, 0)
+            for sw in range(0, 12, 2):
+                set_row_plan(n, sw, -1)
+    try:
+        set_merged_launch(False)
+        assert batch.autotune(2, path) is True
+        set_merged_launch(True)
+        assert batch.autotune(2, path) is True
+        lines = path.read_text().splitlines()
+        assert len(lines) == 4
+        merged = [ln for ln in lines if "512x512*1+1024x1024*1/merged" in ln]
+        assert len(merged) == 2
+        for ln in merged:
+            f = ln.split()
+            side, cols, plans = int(f[2]), [int(x) for x in f[4:10]], [int(x) for x in f[11:17]]
+            assert cols == [{512: 32, 1024: 16}[side]] * 6   # the merged column bodies' widths
+            assert all(p == 0 for p in plans) if side == 512 else all(p in (1, 2) for p in plans)
+        assert batch.autotune(2, path) is False            # both entries are read back
+        set_merged_launch(False)
+        assert batch.autotune(2, path) is False
+    finally:
+        set_merged_launch(False)
+        reset()
+
+
 ALT_TILE = {128: 16, 256: 32, 512: 32, 1024: 8, 2048: 16}   # the second compiled width per side
 
 
