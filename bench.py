@@ -174,8 +174,13 @@ def ingest_counters(fetch_csv: str, write_csv: str, projections: int, side: int 
     return 0
 
 
-# column-tile widths compiled per side (the default first)
-COL_WIDTHS = {128: (32, 16), 256: (16, 32), 512: (16, 32), 1024: (16, 8), 2048: (8, 16)}
+def compiled_widths(lib, side: int) -> list:
+    """Column-tile widths the library holds for `side` (pwf_set_column_tile accepts exactly
+    those; host-side calls only), the default first."""
+    default = lib.pwf_column_tile(side, 1)
+    found = [w for w in (4, 8, 16, 32) if lib.pwf_set_column_tile(side, -1, w) == 0]
+    lib.pwf_set_column_tile(side, -1, 0)
+    return sorted(found, key=lambda w: w != default)
 
 
 def sweep_only_side(side: int, n: int, which: str, reps: int, dev) -> int:
@@ -203,7 +208,7 @@ def sweep_only_side(side: int, n: int, which: str, reps: int, dev) -> int:
         torch.cuda.synchronize()
         del src, dst
     lib = _lib.load()
-    for w in COL_WIDTHS[side]:
+    for w in compiled_widths(lib, side):
         _lib.check(lib.pwf_set_column_tile(side, -1, w), "pwf_set_column_tile")
         for sw in sweeps:
             batch.bench_sweep(sw, reps)
@@ -605,7 +610,7 @@ def main() -> int:
         print(json.dumps(uneven_batch(dev, args.iters)), flush=True)
         return 0
     if args.sweep_only is not None and args.side != 1024:
-        if args.side not in COL_WIDTHS:
+        if args.side not in (128, 256, 512, 2048):
             print(f"bench.py: --side {args.side} is not a supported grid side", file=sys.stderr)
             return 2
         return sweep_only_side(args.side, args.projections, args.sweep_only, args.sweep_reps, dev)
@@ -637,7 +642,7 @@ def main() -> int:
             torch.cuda.synchronize()
             del src, dst
         # every compiled column-tile width in turn unless one is fixed
-        for w in ([args.col_tile] if args.col_tile else [16, 8]):
+        for w in ([args.col_tile] if args.col_tile else compiled_widths(_l.load(), 1024)):
             _l.load().pwf_set_column_tile(1024, -1, w)
             for sw in sweeps:
                 batch.bench_sweep(sw, args.sweep_reps)

@@ -67,3 +67,14 @@ def test_counter_ingest_at_another_side(tmp_path, monkeypatch):
     assert rec["side"] == 2048 and set(rec["sweeps"]) == {"1:8"}
     assert abs(rec["sweeps"]["1:8"]["hbm_bytes_per_px"] - 16.5) < 1e-9
     assert bench.measured_traffic(1, px, 8) is None
+
+
+def test_compiled_widths_from_the_library():
+    """The counter runs launch every compiled column-tile width, asked of the library (host
+    calls only), the default first; the settings are left at the defaults."""
+    from paper_2503_20146_amd import _lib
+    lib = _lib.load()
+    assert bench.compiled_widths(lib, 1024) == [16, 8]
+    assert bench.compiled_widths(lib, 2048) == [8, 16]
+    assert bench.compiled_widths(lib, 512) == [16, 32]
+    assert lib.pwf_column_tile(1024, 11) == 16 and lib.pwf_column_tile(2048, 11) == 8
