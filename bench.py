@@ -517,7 +517,7 @@ def cpu_baseline(iters: int):
 
     import oracle as O
     import synthetic as S
-    # threads: OMP_NUM_THREADS if set (16 on the GPU machine), else every core, at most 16
+    # threads: OMP_NUM_THREADS if set, else every core, at most 16
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     threads = max(1, min(threads, 16))
     O.FFT_WORKERS = threads
