@@ -1247,15 +1247,15 @@ pwf_status solve_impl(const pwf_problem* problems, int32_t n, const float* const
     const pwf_status cs = enqueue(ctx->side);
     const hipError_t ee = hipStreamEndCapture(ctx->side, &graph);
     if (cs != PWF_OK) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return cs;
     }
     PWF_HIP(ee);
     const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     PWF_HIP(ie);
     if (ctx->graphs.size() >= 8) {
-      hipGraphExecDestroy(ctx->graphs.begin()->second);
+      (void)hipGraphExecDestroy(ctx->graphs.begin()->second);
       ctx->graphs.erase(ctx->graphs.begin());
     }
     ctx->graphs[key] = exec;
@@ -1482,8 +1482,8 @@ pwf_status pwf_autotune(const pwf_problem* problems, int32_t n, int32_t reps, vo
     if (result != PWF_OK) break;
   }
   ++g_tune_gen;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return result;
 }
 
@@ -2180,45 +2180,45 @@ void pwf_finalize(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (Context& c : g_ctx) {
     if (!c.ready) continue;
-    for (auto& kv : c.graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
     c.graphs.clear();
     for (float2*& t : c.tw) {
-      if (t) hipFree(t);
+      if (t) (void)hipFree(t);
       t = nullptr;
     }
     for (float2*& t : c.twc) {
-      if (t) hipFree(t);
+      if (t) (void)hipFree(t);
       t = nullptr;
     }
     for (float2*& t : c.twn) {
-      if (t) hipFree(t);
+      if (t) (void)hipFree(t);
       t = nullptr;
     }
     for (float2*& t : c.twa) {
-      if (t) hipFree(t);
+      if (t) (void)hipFree(t);
       t = nullptr;
     }
     for (float2*& t : c.twa2) {
-      if (t) hipFree(t);
+      if (t) (void)hipFree(t);
       t = nullptr;
     }
-    if (c.beta) hipFree(c.beta);
+    if (c.beta) (void)hipFree(c.beta);
     c.beta = nullptr;
     for (int i = 0; i < Context::kSlots; ++i) {
-      if (c.stage_ev[i]) hipEventSynchronize(c.stage_ev[i]);
-      if (c.stage[i]) hipHostFree(c.stage[i]);
+      if (c.stage_ev[i]) (void)hipEventSynchronize(c.stage_ev[i]);
+      if (c.stage[i]) (void)hipHostFree(c.stage[i]);
       c.stage[i] = nullptr;
       c.stage_bytes[i] = 0;
-      if (c.stage_ev[i]) hipEventDestroy(c.stage_ev[i]);
+      if (c.stage_ev[i]) (void)hipEventDestroy(c.stage_ev[i]);
       c.stage_ev[i] = nullptr;
     }
     for (hipStream_t& f : c.fork)
-      if (f) hipStreamDestroy(f);
+      if (f) (void)hipStreamDestroy(f);
     for (hipEvent_t& e : c.fork_ev)
-      if (e) hipEventDestroy(e);
-    if (c.ev_in) hipEventDestroy(c.ev_in);
-    if (c.ev_out) hipEventDestroy(c.ev_out);
-    if (c.side) hipStreamDestroy(c.side);
+      if (e) (void)hipEventDestroy(e);
+    if (c.ev_in) (void)hipEventDestroy(c.ev_in);
+    if (c.ev_out) (void)hipEventDestroy(c.ev_out);
+    if (c.side) (void)hipStreamDestroy(c.side);
     c = Context();
   }
 }

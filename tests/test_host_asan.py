@@ -1,12 +1,14 @@
-"""Host-side AddressSanitizer run of the C ABI (no GPU).
+"""Host-side AddressSanitizer and UndefinedBehaviorSanitizer run of the C ABI (no GPU).
 
 The API and tomography translation units, which hold the library's host code
 (argument validation, workspace layout, batch grouping, tuning settings, the
-host fits), are rebuilt with AddressSanitizer on their host pass only and
+host fits), are rebuilt with both sanitizers on their host pass only and
 linked with the device objects of the regular build; the ABI tests then run
 against that library in a child process with the compiler's ASan runtime
-preloaded.  A heap or stack overflow, use after free or double free in any
-host path those tests reach fails this test with the sanitizer's report.
+(which carries the UBSan handlers) preloaded.  A heap or stack overflow, use
+after free, double free, signed overflow, misaligned or null access, or
+out-of-range shift in any host path those tests reach fails this test with
+the sanitizer's report.
 """
 
 from __future__ import annotations
@@ -44,7 +46,7 @@ def test_abi_suite_under_host_asan(tmp_path):
     for unit in HOST_UNITS:
         out = str(tmp_path / (unit[:-4] + ".o"))
         cmd = [hipcc, *B.FLAGS, "-O1", "-g",
-               "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
+               "-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-omit-frame-pointer",
                "-c", os.path.join(B.CSRC, unit), "-o", out]
         res = subprocess.run(cmd, capture_output=True, text=True)
         assert res.returncode == 0, res.stderr[-3000:]
@@ -62,10 +64,12 @@ def test_abi_suite_under_host_asan(tmp_path):
         "import pytest\n"
         "sys.exit(pytest.main(['-q', '-x', '-m', 'not gpu', '-p', 'no:cacheprovider', %r]))\n"
     ) % (ROOT, lib, os.path.join(ROOT, "tests", "test_abi.py"))
-    env = dict(os.environ, LD_PRELOAD=rt, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1")
+    env = dict(os.environ, LD_PRELOAD=rt, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     res = subprocess.run([sys.executable, "-c", driver], capture_output=True, text=True, env=env, cwd=ROOT,
                          timeout=600)
     report = res.stdout[-4000:] + res.stderr[-4000:]
     assert "ERROR: AddressSanitizer" not in report, report
+    assert "runtime error:" not in report, report
     assert res.returncode == 0, report
     assert " passed" in res.stdout, report
