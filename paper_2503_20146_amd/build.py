@@ -68,5 +68,30 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     return LIB
 
 
+C_CONSUMER = os.path.join(ROOT, "tests", "c_consumer", "pwf_c_solve")
+
+
+def build_c_consumer(verbose: bool = True) -> str | None:
+    """Compile the tests' C99 consumer of the library (tests/c_consumer/pwf_c_solve.c: a
+    plain C program that runs pwf_solve with the HIP runtime for memory and a stream) with
+    gcc against include/pwf.h and libpwf.so; returns its path, or None without gcc."""
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        if verbose:
+            print("[build] gcc not found: the C consumer of the tests is not built", flush=True)
+        return None
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = [gcc, "-std=c99", "-O2", "-Wall", "-Wextra", "-pedantic", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           "-isystem", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"), C_CONSUMER + ".c",
+           "-o", C_CONSUMER, "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-L", PKG, "-lpwf",
+           f"-Wl,-rpath,{PKG}", f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"C consumer build failed:\n{res.stdout}\n{res.stderr}")
+    if verbose:
+        print(f"[build] wrote {C_CONSUMER}", flush=True)
+    return C_CONSUMER
+
+
 if __name__ == "__main__":
     build(int(sys.argv[1]) if len(sys.argv) > 1 else None)
