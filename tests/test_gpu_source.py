@@ -4,7 +4,8 @@ function"; Eqs. 3-5 and the STF of Eq. 14).
 * Coherence lengths in metres (PWF_SRC_COHERENCE): the paper's beamline values, x_coh =
   3.47 um and y_coh = 4.31 um, on the 128^2 workload.
 * A caller's separable IOTF (PWF_SRC_IOTF) that is not Gaussian: a Lorentzian factor along
-  x and an exponential one along y, on square and non-square grids; the oracle takes the
+  x and an exponential one along y, on square and non-square grids, with and without the
+  split column transform (ny >= 512); the oracle takes the
   same float32 samples as its window, with STF = IOTF^(2 gamma).
 * The IOTF form given the samples of the Gaussian equals the sigma form.
 """
@@ -70,8 +71,10 @@ def _separable_iotf(ny, nx):
     return ix, iy
 
 
-@pytest.mark.parametrize("ny,nx", [(128, 128), (256, 512)])
+@pytest.mark.parametrize("ny,nx", [(128, 128), (256, 512), (512, 256), (1024, 512)])
 def test_separable_iotf_source_matches_oracle(ny, nx):
+    """(From ny = 512 on the column transforms are split: the staged y factors of the
+    caller's IOTF are read at ky = 2 j + p and at the mirror positions of each half.)"""
     dev = device()
     rng = np.random.default_rng(ny + 3 * nx)
     geo = S.Geometry(ny=ny, nx=nx)
