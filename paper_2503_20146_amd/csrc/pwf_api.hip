@@ -2017,13 +2017,13 @@ pwf_status pwf_background_quadratic(void* vol, int32_t n_slices, int32_t n, doub
 // ------------------------------------------------------------ shell correlation
 
 namespace {
-bool fsc_layout(int n, int dims, size_t* g2_off, size_t* part_off, size_t* out_off, size_t* total) {
+// workspace: the packed field and its DFT (one complex n^dims array), the
+// workgroups' shell partials, the shell sums
+bool fsc_layout(int n, int dims, size_t* part_off, size_t* out_off, size_t* total) {
   if ((dims != 2 && dims != 3) || size_index(n) < 0) return false;
   const size_t m = dims == 3 ? (size_t)n * n * n : (size_t)n * n;
   const size_t nsh = (size_t)n / 2 + 1;
   size_t off = align_up(sizeof(float2) * m);
-  *g2_off = off;
-  off += align_up(sizeof(float2) * m);
   *part_off = off;
   off += align_up(sizeof(double) * 3 * nsh * pwf::fsc_blocks());
   *out_off = off;
@@ -2034,14 +2034,14 @@ bool fsc_layout(int n, int dims, size_t* g2_off, size_t* part_off, size_t* out_o
 }  // namespace
 
 size_t pwf_shell_correlation_workspace_size(int32_t n, int32_t dims) {
-  size_t a, b, c, total;
-  return fsc_layout(n, dims, &a, &b, &c, &total) ? total : 0;
+  size_t b, c, total;
+  return fsc_layout(n, dims, &b, &c, &total) ? total : 0;
 }
 
 pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int32_t dims, int32_t part,
                                  double* fsc_out, void* workspace, size_t workspace_bytes, void* stream) {
-  size_t g2_off, part_off, out_off, total;
-  if (!fsc_layout(n, dims, &g2_off, &part_off, &out_off, &total)) return PWF_ERR_SIZE;
+  size_t part_off, out_off, total;
+  if (!fsc_layout(n, dims, &part_off, &out_off, &total)) return PWF_ERR_SIZE;
   if (!g1 || !g2 || !fsc_out || (part != 0 && part != 1)) return PWF_ERR_ARG;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < total) return PWF_ERR_WORKSPACE;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -2050,21 +2050,18 @@ pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int3
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   const size_t m = dims == 3 ? (size_t)n * n * n : (size_t)n * n;
-  float2* A = (float2*)ws;
-  float2* B = (float2*)(ws + g2_off);
+  float2* X = (float2*)ws;
   const float2* twr = ctx->tw[size_index(n)];
   const float2* twc = ctx->twc[size_index(n)];
-  // the n^dims DFT as 1-D transforms along x, y (per z plane) and z
-  for (int v = 0; v < 2; ++v) {
-    float2* X = v == 0 ? A : B;
-    PWF_HIP(pwf::launch_fsc_part((const float2*)(v == 0 ? g1 : g2), part, X, m, st));
-    PWF_HIP(pwf::launch_plain_rows(n, -1, X, X, (int)(m / n), twr, st));
-    const int planes = dims == 3 ? n : 1;
-    PWF_HIP(pwf::launch_plain_cols(n, -1, X, n, twc, st, planes, (size_t)n * n));
-    if (dims == 3) PWF_HIP(pwf::launch_plain_cols(n, -1, X, n * n, twc, st));
-  }
+  // both parts in one complex field, then its n^dims DFT as 1-D transforms
+  // along x, y (per z plane) and z; the shell sums separate the two spectra
+  PWF_HIP(pwf::launch_fsc_pack((const float2*)g1, (const float2*)g2, part, X, m, st));
+  PWF_HIP(pwf::launch_plain_rows(n, -1, X, X, (int)(m / n), twr, st));
+  const int planes = dims == 3 ? n : 1;
+  PWF_HIP(pwf::launch_plain_cols(n, -1, X, n, twc, st, planes, (size_t)n * n));
+  if (dims == 3) PWF_HIP(pwf::launch_plain_cols(n, -1, X, n * n, twc, st));
   double* out = (double*)(ws + out_off);
-  PWF_HIP(pwf::launch_fsc_shells(A, B, n, dims, (double*)(ws + part_off), out, st));
+  PWF_HIP(pwf::launch_fsc_shells(X, n, dims, (double*)(ws + part_off), out, st));
   const int nsh = n / 2 + 1;
   std::vector<double> h(3 * (size_t)nsh);
   PWF_HIP(hipMemcpyAsync(h.data(), out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));

@@ -142,11 +142,18 @@ hipError_t launch_fbp_backproject(const float2* q, int n_proj, int nx, int ny, i
 
 namespace pwf {
 
-// Fourier shell correlation (Methods, Eq. 16): the chosen part (0 real, 1
-// imaginary) of a complex volume, as a complex field for the transforms.
-__global__ void fsc_part_kernel(const float2* __restrict__ src, int part, float2* __restrict__ dst, size_t m) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = make_float2(part ? src[i].y : src[i].x, 0.f);
+// Fourier shell correlation (Methods, Eq. 16) of the chosen parts (0 real,
+// 1 imaginary) of two complex volumes.  Both real fields go into one complex
+// field c = a + i b, whose single DFT C holds both spectra:
+//   A(k) = (C(k) + conj C(-k)) / 2,   B(k) = (C(k) - conj C(-k)) / (2 i),
+// one transform instead of two (the rounding of each spectrum is then relative
+// to the larger of the two at that frequency).
+__global__ void fsc_pack_kernel(const float2* __restrict__ g1, const float2* __restrict__ g2, int part,
+                                float2* __restrict__ dst, size_t m) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 a = g1[i], b = g2[i];
+    dst[i] = part ? make_float2(a.y, b.y) : make_float2(a.x, b.x);
+  }
 }
 
 // Shell sums of Re(G1* G2), |G1|^2, |G2|^2 over kappa = round(|k|) (signed
@@ -176,8 +183,7 @@ __global__ void fsc_part_kernel(const float2* __restrict__ src, int part, float2
 constexpr int kFscThreads = 256;
 
 template <int K>
-__global__ void __launch_bounds__(kFscThreads) fsc_shell_kernel(const float2* __restrict__ g1,
-                                                                const float2* __restrict__ g2, int n, int dims,
+__global__ void __launch_bounds__(kFscThreads) fsc_shell_kernel(const float2* __restrict__ spec, int n, int dims,
                                                                 double* __restrict__ partial) {
   extern __shared__ double sh[];
   const int nsh = n / 2 + 1;
@@ -213,13 +219,15 @@ __global__ void __launch_bounds__(kFscThreads) fsc_shell_kernel(const float2* __
       const int k = (int)rintf(sqrtf(fx * fx + r2));
       sk[j] = k < nsh ? k : nsh;  // nsh: outside the last shell
     }
-    // kappa is monotone over the lane's elements: one inside means an end is
-    float2 a[K], b[K];
+    // kappa is monotone over the lane's elements: one inside means an end is.
+    // C(k) and C(-k) (same shell): -k is (n - kx, n - ky, n - kz) mod n.
+    float2 ck[K], cm[K];
     const bool any_in = sk[0] < nsh || sk[K - 1] < nsh;
+    const size_t mrow = (((size_t)((n - kz) & (n - 1)) * n + (size_t)((n - ky) & (n - 1)))) * n;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      a[j] = any_in ? g1[e0 + j] : make_float2(0.f, 0.f);
-      b[j] = any_in ? g2[e0 + j] : make_float2(0.f, 0.f);
+      ck[j] = any_in ? spec[e0 + j] : make_float2(0.f, 0.f);
+      cm[j] = any_in ? spec[mrow + ((n - kx0 - j) & (n - 1))] : make_float2(0.f, 0.f);
     }
     // runs inside the lane: f = first run, q = current run
     double f0 = 0.0, f1 = 0.0, f2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
@@ -227,9 +235,12 @@ __global__ void __launch_bounds__(kFscThreads) fsc_shell_kernel(const float2* __
     bool multi = false;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      double v0 = (double)a[j].x * b[j].x + (double)a[j].y * b[j].y;
-      double v1 = (double)a[j].x * a[j].x + (double)a[j].y * a[j].y;
-      double v2 = (double)b[j].x * b[j].x + (double)b[j].y * b[j].y;
+      // A = ((Cr + Cmr) + i (Ci - Cmi)) / 2,  B = ((Ci + Cmi) + i (Cmr - Cr)) / 2
+      const double ax = 0.5 * ((double)ck[j].x + cm[j].x), ay = 0.5 * ((double)ck[j].y - cm[j].y);
+      const double bx = 0.5 * ((double)ck[j].y + cm[j].y), by = 0.5 * ((double)cm[j].x - ck[j].x);
+      double v0 = ax * bx + ay * by;
+      double v1 = ax * ax + ay * ay;
+      double v2 = bx * bx + by * by;
       if (sk[j] == nsh) v0 = v1 = v2 = 0.0;
       if (j == 0) {
         f0 = v0;
@@ -299,21 +310,20 @@ __global__ void fsc_final_kernel(const double* __restrict__ partial, int blocks,
 // three 49 KB workgroups per CU: one round over the 256 CUs
 int fsc_blocks() { return 768; }
 
-hipError_t launch_fsc_part(const float2* src, int part, float2* dst, size_t m, hipStream_t st) {
-  hipLaunchKernelGGL(fsc_part_kernel, dim3(4096), dim3(256), 0, st, src, part, dst, m);
+hipError_t launch_fsc_pack(const float2* g1, const float2* g2, int part, float2* dst, size_t m, hipStream_t st) {
+  hipLaunchKernelGGL(fsc_pack_kernel, dim3(4096), dim3(256), 0, st, g1, g2, part, dst, m);
   return hipGetLastError();
 }
 
-hipError_t launch_fsc_shells(const float2* g1, const float2* g2, int n, int dims, double* partial, double* out,
-                             hipStream_t st) {
+hipError_t launch_fsc_shells(const float2* spec, int n, int dims, double* partial, double* out, hipStream_t st) {
   const int nsh = n / 2 + 1;
   const int threads = n > 1024 ? kFscThreads / 2 : kFscThreads;
   const size_t lds = sizeof(double) * (threads / 64) * 3 * nsh;
   // four elements per lane where 256 divides n/2, else one (64 divides n/2 from n = 128)
   if (n >= 512)
-    hipLaunchKernelGGL(fsc_shell_kernel<4>, dim3(fsc_blocks()), dim3(threads), lds, st, g1, g2, n, dims, partial);
+    hipLaunchKernelGGL(fsc_shell_kernel<4>, dim3(fsc_blocks()), dim3(threads), lds, st, spec, n, dims, partial);
   else
-    hipLaunchKernelGGL(fsc_shell_kernel<1>, dim3(fsc_blocks()), dim3(threads), lds, st, g1, g2, n, dims, partial);
+    hipLaunchKernelGGL(fsc_shell_kernel<1>, dim3(fsc_blocks()), dim3(threads), lds, st, spec, n, dims, partial);
   hipLaunchKernelGGL(fsc_final_kernel, dim3((3 * nsh + 255) / 256), dim3(256), 0, st, partial, fsc_blocks(),
                      3 * nsh, out);
   return hipGetLastError();
