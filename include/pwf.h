@@ -441,10 +441,9 @@ size_t pwf_shell_correlation_workspace_size(int32_t n, int32_t dims);
  *   fsc[kappa] = Re sum G1* G2 / sqrt(sum |G1|^2 sum |G2|^2) over the shell
  *   kappa = round(|k|) of signed index frequencies, kappa = 0 .. n/2.
  * The resolution criterion of the paper is fsc = 1/4 (Eqs. 17-18).  The two
- * real fields are transformed together as one complex field (FP32), so the
- * rounding of each spectrum is relative to the larger of the two at that
- * frequency; shell sums in FP64 in a fixed order (bit-reproducible from call
- * to call).  fsc_out: HOST float64 [n/2 + 1]; the call synchronises on
+ * real fields, each scaled to unit RMS (which leaves fsc unchanged), are
+ * transformed together as one complex field (FP32); shell sums in FP64 in a
+ * fixed order (bit-reproducible from call to call).  fsc_out: HOST float64 [n/2 + 1]; the call synchronises on
  * `stream`. */
 pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int32_t dims, int32_t part,
                                  double* fsc_out, void* workspace, size_t workspace_bytes, void* stream);

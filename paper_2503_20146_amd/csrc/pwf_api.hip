@@ -2055,7 +2055,9 @@ pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int3
   const float2* twc = ctx->twc[size_index(n)];
   // both parts in one complex field, then its n^dims DFT as 1-D transforms
   // along x, y (per z plane) and z; the shell sums separate the two spectra
-  PWF_HIP(pwf::launch_fsc_pack((const float2*)g1, (const float2*)g2, part, X, m, st));
+  // (the unit-RMS scales live in the shell-sum area until the sums overwrite it)
+  PWF_HIP(pwf::launch_fsc_pack((const float2*)g1, (const float2*)g2, part, X, m, (double*)(ws + part_off),
+                               (float*)(ws + out_off), st));
   PWF_HIP(pwf::launch_plain_rows(n, -1, X, X, (int)(m / n), twr, st));
   const int planes = dims == 3 ? n : 1;
   PWF_HIP(pwf::launch_plain_cols(n, -1, X, n, twc, st, planes, (size_t)n * n));

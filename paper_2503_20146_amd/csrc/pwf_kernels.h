@@ -120,7 +120,9 @@ hipError_t launch_fbp_backproject(const float2* q, int n_proj, int nx, int ny, i
 // Fourier shell correlation (pwf_tomo.hip): out[s], out[nsh + s], out[2 nsh + s]
 // = shell sums of Re(G1* G2), |G1|^2, |G2|^2, nsh = n/2 + 1.
 int fsc_blocks();
-hipError_t launch_fsc_pack(const float2* g1, const float2* g2, int part, float2* dst, size_t m, hipStream_t st);
+// (partial: 2 fsc_blocks() doubles of scratch; scale: 2 floats of device memory)
+hipError_t launch_fsc_pack(const float2* g1, const float2* g2, int part, float2* dst, size_t m, double* partial,
+                           float* scale, hipStream_t st);
 hipError_t launch_fsc_shells(const float2* spec, int n, int dims, double* partial, double* out, hipStream_t st);
 // Quadratic background removal (pwf_tomo.hip): n a multiple of 16; slices are
 // split into bands of bg_rows_per_band(n) rows (n a multiple of that).

@@ -146,13 +146,55 @@ namespace pwf {
 // 1 imaginary) of two complex volumes.  Both real fields go into one complex
 // field c = a + i b, whose single DFT C holds both spectra:
 //   A(k) = (C(k) + conj C(-k)) / 2,   B(k) = (C(k) - conj C(-k)) / (2 i),
-// one transform instead of two (the rounding of each spectrum is then relative
-// to the larger of the two at that frequency).
+// one transform instead of two.  The rounding of each spectrum is then
+// relative to the larger of the two at that frequency, so a and b are first
+// scaled to unit RMS: the correlation does not change under positive scaling
+// of either input, and inputs of any relative size keep FP32 accuracy.
+constexpr int kFscThreads = 256;
+
+// FP64 sums of a^2 and b^2 per workgroup, in a fixed order.
+__global__ void __launch_bounds__(kFscThreads) fsc_norm_kernel(const float2* __restrict__ g1,
+                                                               const float2* __restrict__ g2, int part, size_t m,
+                                                               double* __restrict__ partial) {
+  double sa = 0.0, sb = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 u = g1[i], v = g2[i];
+    const double a = part ? u.y : u.x, b = part ? v.y : v.x;
+    sa = fma(a, a, sa);
+    sb = fma(b, b, sb);
+  }
+  __shared__ double red[kFscThreads / 64][2];
+  for (int off = 32; off > 0; off >>= 1) {
+    sa += __shfl_xor(sa, off, 64);
+    sb += __shfl_xor(sb, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = sa;
+    red[threadIdx.x >> 6][1] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int w = 0; w < kFscThreads / 64; ++w) t += red[w][threadIdx.x];
+    partial[2 * (size_t)blockIdx.x + threadIdx.x] = t;
+  }
+}
+
+// scale[p] = 1 / RMS of field p (1 for a field of zeros), the partials summed in order
+__global__ void fsc_scale_kernel(const double* __restrict__ partial, int blocks, size_t m, float* __restrict__ scale) {
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int b = 0; b < blocks; ++b) t += partial[2 * (size_t)b + threadIdx.x];
+    scale[threadIdx.x] = t > 0.0 ? (float)(1.0 / sqrt(t / (double)m)) : 1.f;
+  }
+}
+
 __global__ void fsc_pack_kernel(const float2* __restrict__ g1, const float2* __restrict__ g2, int part,
-                                float2* __restrict__ dst, size_t m) {
+                                const float* __restrict__ scale, float2* __restrict__ dst, size_t m) {
+  const float sa = scale[0], sb = scale[1];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
     const float2 a = g1[i], b = g2[i];
-    dst[i] = part ? make_float2(a.y, b.y) : make_float2(a.x, b.x);
+    dst[i] = part ? make_float2(a.y * sa, b.y * sb) : make_float2(a.x * sa, b.x * sb);
   }
 }
 
@@ -180,7 +222,6 @@ __global__ void fsc_pack_kernel(const float2* __restrict__ g1, const float2* __r
 // The workgroup then adds its waves' histograms in wave order and writes one
 // row of partials.  Four waves per workgroup up to n = 1024 and two at 2048
 // keep the histograms at 49 KB of LDS.
-constexpr int kFscThreads = 256;
 
 template <int K>
 __global__ void __launch_bounds__(kFscThreads) fsc_shell_kernel(const float2* __restrict__ spec, int n, int dims,
@@ -310,8 +351,11 @@ __global__ void fsc_final_kernel(const double* __restrict__ partial, int blocks,
 // three 49 KB workgroups per CU: one round over the 256 CUs
 int fsc_blocks() { return 768; }
 
-hipError_t launch_fsc_pack(const float2* g1, const float2* g2, int part, float2* dst, size_t m, hipStream_t st) {
-  hipLaunchKernelGGL(fsc_pack_kernel, dim3(4096), dim3(256), 0, st, g1, g2, part, dst, m);
+hipError_t launch_fsc_pack(const float2* g1, const float2* g2, int part, float2* dst, size_t m, double* partial,
+                           float* scale, hipStream_t st) {
+  hipLaunchKernelGGL(fsc_norm_kernel, dim3(fsc_blocks()), dim3(kFscThreads), 0, st, g1, g2, part, m, partial);
+  hipLaunchKernelGGL(fsc_scale_kernel, dim3(1), dim3(64), 0, st, partial, fsc_blocks(), m, scale);
+  hipLaunchKernelGGL(fsc_pack_kernel, dim3(4096), dim3(256), 0, st, g1, g2, part, scale, dst, m);
   return hipGetLastError();
 }
 

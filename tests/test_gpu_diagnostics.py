@@ -49,3 +49,22 @@ def test_shell_correlation_matches_oracle(n, dims):
     assert np.array_equal(got, again)
     same = np.array(shell_correlation(ta, ta, part=1))
     assert np.max(np.abs(same[1:] - 1.0)) <= 1e-6
+
+
+@pytest.mark.parametrize("scale", [1e-6, 1e3])
+def test_shell_correlation_is_scale_invariant(scale):
+    """The correlation does not change when one input is scaled (Eq. 16 is invariant under
+    positive scaling of either input): the two fields share one complex transform, so the
+    library brings both to unit RMS first; without that, a 1e-6 scale cost 1e-2 here."""
+    from paper_2503_20146_amd import shell_correlation
+    dev = device()
+    rng = np.random.default_rng(77)
+    shape = (128,) * 3
+    s = rng.standard_normal(shape)
+    a = (s + 0.7 * rng.standard_normal(shape)) + 1j * rng.standard_normal(shape)
+    b = (s + 0.7 * rng.standard_normal(shape)) + 1j * rng.standard_normal(shape)
+    say(f"shell correlation, second input scaled by {scale:g}")
+    got = np.array(shell_correlation(to_dev(a.astype(np.complex64), dev),
+                                     to_dev((scale * b).astype(np.complex64), dev), part=0))
+    ref = O.shell_correlation(a.real.astype(np.float32), b.real.astype(np.float32))
+    assert np.max(np.abs(got - ref)) <= 1e-5
