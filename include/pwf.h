@@ -442,8 +442,10 @@ size_t pwf_shell_correlation_workspace_size(int32_t n, int32_t dims);
  *   kappa = round(|k|) of signed index frequencies, kappa = 0 .. n/2.
  * The resolution criterion of the paper is fsc = 1/4 (Eqs. 17-18).  The two
  * real fields, each scaled to unit RMS (which leaves fsc unchanged), are
- * transformed together as one complex field (FP32); shell sums in FP64 in a
- * fixed order (bit-reproducible from call to call).  fsc_out: HOST float64 [n/2 + 1]; the call synchronises on
+ * transformed together as one complex field (FP32): a shell where one input's
+ * amplitude is a fraction r of the other's carries an absolute error of about
+ * 1e-7 / r.  Shell sums in FP64 in a fixed order (bit-reproducible from call
+ * to call).  fsc_out: HOST float64 [n/2 + 1]; the call synchronises on
  * `stream`. */
 pwf_status pwf_shell_correlation(const void* g1, const void* g2, int32_t n, int32_t dims, int32_t part,
                                  double* fsc_out, void* workspace, size_t workspace_bytes, void* stream);
